@@ -1,0 +1,48 @@
+"""Pins of the seeded input generator (tsgen)."""
+import numpy as np
+
+import tsgen
+
+
+def test_splitmix64_reference_output():
+    """SplitMix64 started from state 0 gives 0xe220a8397b1dcdaf as its first
+    output (the published generator's well-known first value)."""
+    assert int(tsgen.raw(0, 0, [0])[0]) == 0xE220A8397B1DCDAF
+
+
+def test_uniform_range_and_exactness():
+    x = tsgen.uniform_pm1(2, tsgen.STREAM_A, np.arange(200000, dtype=np.uint64))
+    assert x.min() >= -1.0 and x.max() < 1.0
+    # every value lies on the 2^-52 grid
+    assert np.all(np.ldexp(x, 52) == np.round(np.ldexp(x, 52)))
+    assert abs(x.mean()) < 0.01
+    u = tsgen.uniform01(2, 1, np.arange(1000, dtype=np.uint64))
+    assert u.min() >= 0 and u.max() < 1
+
+
+def test_counter_based_reproducible():
+    full = tsgen.uniform_array(3, 1, 1000)
+    part = tsgen.uniform_array(3, 1, 10, start=500)
+    assert np.array_equal(full[500:510], part)
+    assert not np.array_equal(tsgen.uniform_array(3, 2, 10), tsgen.uniform_array(3, 1, 10))
+    assert not np.array_equal(tsgen.uniform_array(4, 1, 10), tsgen.uniform_array(3, 1, 10))
+
+
+def test_narrowing_goes_through_binary32():
+    x = tsgen.uniform_pm1(4, 0, np.arange(5000, dtype=np.uint64))
+    f32 = tsgen.narrow(x, "f32")
+    assert f32.dtype == np.float32 and np.array_equal(f32, x.astype(np.float32))
+    f16 = tsgen.narrow(x, "f16")
+    assert np.array_equal(f16, f32.astype(np.float16).view(np.uint16))
+    bf = tsgen.narrow(x, "bf16")
+    assert bf.dtype == np.uint16
+
+
+def test_batched_lengths_and_scalars():
+    lens = tsgen.batched_lengths(5, 4096)
+    assert lens.min() >= 1000 and lens.max() < 10 ** 7
+    total = int(lens.sum())
+    # E[len] = (1e7 - 1e3) / (4 ln 10) ~ 1.0856e6 per instance
+    assert 4.1e9 < total < 4.8e9
+    q = tsgen.batched_scalars(5, 4096)
+    assert q.min() >= 0.5 and q.max() < 4.0
