@@ -1,0 +1,376 @@
+/*
+ * tstream.h -- C ABI of libtstream: the STREAM kernels (copy, scale, add,
+ * triad) on AMD Instinct MI355X (gfx950), expressed the way Heller et al.,
+ * "Closing the Performance Gap with Modern C++", frame data-parallel work:
+ *
+ *   target     a place: one GPU plus the HIP stream work is ordered on
+ *              (Section 3.1; the GPU target of Section 4.2 is exactly the
+ *              pair "device id + stream");
+ *   allocator  arrays placed on a target's device, with bulk construction
+ *              (fill) run on the device itself (Section 3.2, Listing 1, and
+ *              the GPU allocator of Section 4.2);
+ *   executor   the target again: every algorithm call is one bulk launch on
+ *              the target's stream (Section 3.3, Listing 2; bulk execution
+ *              is what makes GPUs fast, Sections 3.3 and 4.2);
+ *   algorithms copy and transform over placed arrays (Section 3.4), here the
+ *              four maps of the generic STREAM benchmark (Section 5,
+ *              Listing 4).
+ *
+ * Conventions for every function:
+ *   - Returns ts_status: TS_OK (0) or a negative error.  On error a message
+ *     is available from ts_last_error() (thread-local); out-parameters are
+ *     written only on success.  No C++ exception crosses the ABI.
+ *   - Handles are opaque; objects made by *_create / *_alloc are owned by the
+ *     caller and released by the matching *_destroy / *_free, which never
+ *     fail on a valid handle (the allocator's bulk_destroy is noexcept,
+ *     Listing 1) and accept NULL as a no-op.
+ *   - "Device pointer" means memory of the target's device (from hipMalloc,
+ *     or a torch CUDA/HIP tensor); "host pointer" means ordinary CPU memory.
+ *   - Algorithm, fill and copy calls are asynchronous and ordered on the
+ *     target's stream; ts_target_synchronize() is the blocking form
+ *     (Listing 2's execute).  Calls that return values to the host
+ *     (ts_checksum, ts_mismatch_count, ts_batch_mismatch_count, ts_time_op,
+ *     ts_autotune*) block until their result is ready.
+ *   - Arrays are contiguous, one-dimensional, of one storage type.  Storage
+ *     types other than binary64 are evaluated in binary32 (the map in
+ *     binary32, fmaf for triad) and rounded back to nearest-even; copy moves
+ *     stored bits unchanged.
+ *   - Overlapping calls on different host threads must use different
+ *     targets (streams); handles are not internally locked.
+ */
+#ifndef TSTREAM_H
+#define TSTREAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define TS_API __attribute__((visibility("default")))
+#else
+#define TS_API
+#endif
+
+#define TS_VERSION_MAJOR 1
+#define TS_VERSION_MINOR 0
+
+typedef enum {
+    TS_OK = 0,
+    TS_E_INVALID = -1,     /* NULL or unknown handle, bad argument value      */
+    TS_E_SHAPE = -2,       /* an operand shorter than the element count       */
+    TS_E_DTYPE = -3,       /* operands of different storage types             */
+    TS_E_PLACEMENT = -4,   /* an array not placed on the executor's device    */
+    TS_E_ALIAS = -5,       /* output partly overlaps an input                 */
+    TS_E_DEVICE = -6,      /* HIP runtime error (message has its text)        */
+    TS_E_OOM = -7,         /* device or host allocation failed                */
+    TS_E_UNSUPPORTED = -8  /* valid request this build cannot serve           */
+} ts_status;
+
+typedef enum { TS_F64 = 0, TS_F32 = 1, TS_BF16 = 2, TS_F16 = 3 } ts_dtype;
+
+/* The four maps of Listing 4, in the order the benchmark runs them. */
+typedef enum { TS_COPY = 0, TS_SCALE = 1, TS_ADD = 2, TS_TRIAD = 3 } ts_op;
+
+typedef struct ts_target_s *ts_target;
+typedef struct ts_array_s *ts_array;
+typedef struct ts_batch_s *ts_batch;
+typedef struct ts_graph_s *ts_graph;
+typedef struct ts_event_s *ts_event;
+
+/* ------------------------------------------------------------------------ */
+/* Errors and version                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Message of the last failed call on this thread ("" if none).  The pointer
+ * stays valid until the next ts_* call on the same thread. */
+TS_API const char *ts_last_error(void);
+TS_API int ts_version(int *major, int *minor);
+
+/* ------------------------------------------------------------------------ */
+/* Targets (Section 3.1; GPU target = device + stream, Section 4.2)         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int device;                 /* HIP device ordinal                        */
+    int compute_units;          /* CUs reported by the device                */
+    int wavefront_size;         /* 64 on CDNA                                */
+    int max_threads_per_block;
+    int clock_khz;
+    int memory_clock_khz;
+    int memory_bus_width_bits;
+    uint64_t hbm_bytes;         /* device memory                             */
+    uint64_t l2_bytes;          /* L2 per the runtime (per XCD on MI3xx)     */
+    double peak_bytes_per_s;    /* denominator used for % of peak: 8.0e12   */
+    char arch[64];              /* e.g. "gfx950:sramecc+:xnack-"             */
+    char name[128];
+} ts_device_info;
+
+/* Create a target on `device`.  `hip_stream` is a hipStream_t of that device
+ * (e.g. torch.cuda.Stream().cuda_stream); the target borrows it.  NULL asks
+ * the library to create (and later destroy) a non-blocking stream.
+ * Errors: TS_E_INVALID (out NULL, device out of range), TS_E_DEVICE (no
+ * usable GPU / HIP failure), TS_E_OOM. */
+TS_API int ts_target_create(int device, void *hip_stream, ts_target *out);
+TS_API int ts_target_destroy(ts_target target);
+/* Block until all work enqueued on the target's stream has finished. */
+TS_API int ts_target_synchronize(ts_target target);
+TS_API int ts_target_info(ts_target target, ts_device_info *out);
+/* The hipStream_t the target orders its work on. */
+TS_API int ts_target_stream(ts_target target, void **hip_stream_out);
+/* Enqueue host callback fn(user) after all work enqueued so far on the
+ * target (the continuation behind Listing 2's async_execute futures; the
+ * GPU executor signals completion from a stream callback, Section 4.2).
+ * fn runs on a runtime thread and must not call into the HIP runtime. */
+TS_API int ts_target_then(ts_target target, void (*fn)(void *), void *user);
+
+/* ------------------------------------------------------------------------ */
+/* Arrays: placement and bulk construction (Section 3.2, Listing 1)          */
+/* ------------------------------------------------------------------------ */
+
+/* Allocate n elements of `dtype` on the target's device (owning).  The
+ * allocation base is at least 256-byte aligned; the array starts
+ * `offset_elems` elements past it (offset 1 makes a deliberately misaligned
+ * array).  Contents are undefined until filled.
+ * Errors: TS_E_INVALID, TS_E_OOM (hipMalloc out of memory), TS_E_DEVICE. */
+TS_API int ts_array_alloc(ts_target target, ts_dtype dtype, size_t n,
+                          size_t offset_elems, ts_array *out);
+/* Borrow n elements at `dev_ptr` (device pointer of the target's device,
+ * aligned to the element size).  ts_array_free releases only the handle.
+ * The memory must outlive every enqueued use.
+ * Errors: TS_E_INVALID (NULL with n > 0, misaligned), TS_E_PLACEMENT
+ * (pointer of another device or of host memory). */
+TS_API int ts_array_wrap(ts_target target, ts_dtype dtype, void *dev_ptr,
+                         size_t n, ts_array *out);
+/* Release the handle (and the memory, if the array owns it).  Work still
+ * enqueued on the array must have finished (synchronize first). */
+TS_API int ts_array_free(ts_array array);
+TS_API int ts_array_info(ts_array array, void **dev_ptr, size_t *n,
+                         ts_dtype *dtype);
+
+/* bulk_construct on the device (Listing 1; the GPU allocator constructs on
+ * the device, Section 4.2).  ts_fill stores `value` rounded to nearest-even
+ * into the storage type (via binary32 for the 16-bit types).
+ * ts_fill_uniform stores element j (j = 0..n-1) as
+ *   u = (h >> 11) * 2^-52 - 1,  h = SplitMix64 output number
+ *   (first_index + j + 1) from the state seed ^ (stream_id << 48),
+ * an exact binary64 value in [-1, 1), narrowed to binary32 by RNE and then,
+ * for bfloat16/binary16, to the storage type by RNE.  Asynchronous. */
+TS_API int ts_fill(ts_array array, double value);
+TS_API int ts_fill_uniform(ts_array array, uint64_t seed, uint64_t stream_id,
+                           uint64_t first_index);
+
+/* Host <-> device copies (the parallel copy specialised to the runtime's
+ * memcpy, Section 4.2).  n elements; enqueued on the array's target stream;
+ * the host buffer must stay valid and untouched until the stream has
+ * reached the copy (synchronize the target).  Errors: TS_E_SHAPE if n
+ * exceeds the array, TS_E_INVALID on NULL. */
+TS_API int ts_copy_from_host(ts_array dst, const void *host_src, size_t n);
+TS_API int ts_copy_to_host(void *host_dst, ts_array src, size_t n);
+
+/* ------------------------------------------------------------------------ */
+/* Algorithms on an execution target (Section 3.4; maps of Listing 4)        */
+/* ------------------------------------------------------------------------ */
+/*
+ * Element count = n of the first input (iterator-range semantics); every
+ * other operand must hold at least that many elements (else TS_E_SHAPE).
+ * All operands share one storage type (else TS_E_DTYPE) and live on the
+ * executor's device (else TS_E_PLACEMENT).  dst may equal an input exactly
+ * (in place); any other overlap between dst and an input is TS_E_ALIAS.
+ * A zero count returns TS_OK without a launch.  For the non-binary64 types
+ * q is rounded once to binary32.  One kernel launch per call, enqueued on
+ * `exec`'s stream; launch parameters come from the tuning table.
+ */
+/* Listing 4 "Copy": dst[j] = src[j]. */
+TS_API int ts_copy(ts_target exec, ts_array src, ts_array dst);
+/* Listing 4 "Scale": dst[j] = q * src[j]. */
+TS_API int ts_scale(ts_target exec, ts_array src, ts_array dst, double q);
+/* Listing 4 "Add": dst[j] = x[j] + y[j]. */
+TS_API int ts_add(ts_target exec, ts_array x, ts_array y, ts_array dst);
+/* Listing 4 "Triad": dst[j] = x[j] + q * y[j] as one fused multiply-add,
+ * fma(q, y[j], x[j]) (single rounding).  The benchmark's a = b + q*c is
+ * ts_triad(exec, b, c, a, q). */
+TS_API int ts_triad(ts_target exec, ts_array x, ts_array y, ts_array dst,
+                    double q);
+/* One benchmark iteration of Listing 4 over a, b, c:
+ * c = a; b = q*c; c = a + b; a = b + q*c (four launches, in order).
+ * a, b, c must not overlap; count = n of a. */
+TS_API int ts_stream_iteration(ts_target exec, ts_array a, ts_array b,
+                               ts_array c, double q);
+
+/* ------------------------------------------------------------------------ */
+/* Validation (the STREAM benchmark's own result check, done on the GPU)    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double sum;          /* sum of x[j] widened to binary64                      */
+    double abs_dev_sum;  /* sum of |x[j] - expected|                             */
+    double max_abs_dev;  /* max |x[j] - expected|, NaN terms ignored (fmax);
+                            0 for an empty array                                */
+    uint64_t mismatches; /* elements whose binary64 value differs in bits from
+                            `expected` (NaN matches NaN)                       */
+} ts_checksum_out;
+
+/* Binary64 reductions over the whole array, in a fixed two-pass tree whose
+ * shape depends only on n (so results are reproducible run to run).
+ * Blocking.  The sums differ from a sequential sum only by rounding order. */
+TS_API int ts_checksum(ts_target exec, ts_array x, double expected,
+                       ts_checksum_out *out);
+/* Number of j < n(x) with stored bits of x[j] != ref[j] (NaN matches NaN).
+ * ref must hold n(x) elements of the same type.  Blocking. */
+TS_API int ts_mismatch_count(ts_target exec, ts_array x, ts_array ref,
+                             uint64_t *out);
+
+/* ------------------------------------------------------------------------ */
+/* Launch configuration and tuning                                           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t block;       /* threads per workgroup: 64..1024, multiple of 64 */
+    int32_t unroll;      /* vectors per lane per step: 1, 2, 4, 8           */
+    int32_t vec_bytes;   /* bytes per lane access: 16 or 8 (the element size
+                            selects the element-wise path)                  */
+    int32_t nt_load;     /* 1: nontemporal loads                            */
+    int32_t nt_store;    /* 1: nontemporal stores                           */
+    int32_t grid_per_cu; /* workgroups per CU with a grid-stride loop; 0: one
+                            pass, i.e. enough workgroups to cover the array
+                            once (plain kernels only)                       */
+    int64_t tile_elems;  /* batched: elements per tile, a multiple of 8;
+                            0 = default.  Ignored by plain kernels          */
+} ts_kernel_cfg;
+
+/* Operand alignment classes (keys of the tuning table). */
+enum { TS_ALIGN_16 = 0,     /* every operand 16-byte aligned                */
+       TS_ALIGN_SHARED = 1, /* same misalignment: a short head is peeled    */
+       TS_ALIGN_MIXED = 2   /* different misalignments: element-wise path   */
+};
+
+/* Launch configuration the library would use for this key.  `n` selects
+ * the size bucket floor(log2(n)). */
+TS_API int ts_get_kernel_cfg(ts_op op, ts_dtype dtype, size_t n,
+                             int align_class, int batched, ts_kernel_cfg *out);
+/* Force `cfg` for every call of (op, dtype) (plain if batched == 0, batched
+ * otherwise), overriding the table; NULL removes the override.  Results are
+ * bit-identical under every valid configuration.  TS_E_INVALID for an
+ * invalid configuration. */
+TS_API int ts_set_kernel_cfg(ts_op op, ts_dtype dtype, int batched,
+                             const ts_kernel_cfg *cfg);
+/* The candidate set the autotuner searches (plain or batched).  Writes up
+ * to `cap` entries and the full count to *count. */
+TS_API int ts_autotune_candidates(int batched, ts_kernel_cfg *out, size_t cap,
+                                  size_t *count);
+/* Time every candidate for (op, dtype) at n elements with the given offset
+ * from a 256-byte aligned base (library-allocated scratch arrays, freed
+ * before return), median of `reps` event-timed launches each after a
+ * warm-up, store the fastest in the table and return it with its rate in
+ * STREAM bytes per second (copy/scale count 2 arrays, add/triad 3).
+ * Blocking.  TS_E_OOM if the scratch arrays do not fit. */
+TS_API int ts_autotune(ts_target target, ts_op op, ts_dtype dtype, size_t n,
+                       size_t offset_elems, int reps, ts_kernel_cfg *best,
+                       double *best_bytes_per_s);
+/* Same for the batched kernel of (op) over an existing batch (its arrays'
+ * contents are overwritten). */
+TS_API int ts_autotune_batch(ts_target target, ts_batch batch, ts_op op,
+                             int reps, ts_kernel_cfg *best,
+                             double *best_bytes_per_s);
+/* Tuning table persistence (a small JSON file).  Load merges entries and
+ * fails with TS_E_INVALID, leaving the table unchanged, on a malformed file
+ * or another format version.  TS_TUNE_CACHE in the environment names a file
+ * loaded at the first ts_target_create. */
+TS_API int ts_tune_cache_load(const char *path);
+TS_API int ts_tune_cache_save(const char *path);
+TS_API int ts_tune_cache_clear(void);
+
+/* Time `reps` back-to-back launches of one map between two events on the
+ * executor's stream; *ms_total receives the elapsed milliseconds.  Operands
+ * as for the algorithm calls (y ignored by copy/scale).  Blocking. */
+TS_API int ts_time_op(ts_target exec, ts_op op, ts_array x, ts_array y,
+                      ts_array dst, double q, int reps, float *ms_total);
+
+/* ------------------------------------------------------------------------ */
+/* Batched ragged instances: one persistent launch per map                   */
+/* ------------------------------------------------------------------------ */
+
+/* One instance: device pointers of its three arrays (len elements each) and
+ * its scalar.  The maps keep Listing 4's roles inside every instance:
+ * copy c = a, scale b = q*c, add c = a + b, triad a = b + q*c. */
+typedef struct {
+    void *a;
+    void *b;
+    void *c;
+    uint64_t len;
+    double q;
+} ts_batch_desc;
+
+/* Copy `count` descriptors (host memory), split every instance into tiles
+ * (tile_elems from the tuning table unless forced), and upload the
+ * descriptor and tile tables to the target's device.  The instances' arrays
+ * must not overlap one another.  Zero-length instances are allowed.
+ * Errors: TS_E_INVALID (NULL pointer with len > 0, misaligned element),
+ * TS_E_PLACEMENT, TS_E_OOM, TS_E_DEVICE.  Blocking (uploads complete). */
+TS_API int ts_batch_create(ts_target target, ts_dtype dtype,
+                           const ts_batch_desc *host_descs, size_t count,
+                           ts_batch *out);
+TS_API int ts_batch_destroy(ts_batch batch);
+TS_API int ts_batch_info(ts_batch batch, size_t *count, uint64_t *total_elems,
+                         uint64_t *tiles, int64_t *tile_elems);
+/* Re-plan the tiles with tile_elems (multiple of 8, > 0).  Blocking. */
+TS_API int ts_batch_set_tile(ts_batch batch, int64_t tile_elems);
+/* Apply map `op` to every instance in one persistent launch (bulk
+ * execution over all instances, Sections 3.3 and 4.2). */
+TS_API int ts_batch_op(ts_target exec, ts_batch batch, ts_op op);
+/* The same map as one plain launch per instance (the comparison form). */
+TS_API int ts_batch_op_plain(ts_target exec, ts_batch batch, ts_op op);
+/* Bulk construction of array `which` (0 = a, 1 = b, 2 = c) of every
+ * instance: a constant, or uniform[-1,1) with stream 16 + 3*i + which for
+ * instance i (same generator as ts_fill_uniform, first_index 0). */
+TS_API int ts_batch_fill(ts_target exec, ts_batch batch, int which,
+                         double value);
+TS_API int ts_batch_fill_uniform(ts_target exec, ts_batch batch, int which,
+                                 uint64_t seed);
+/* Per-instance count of elements of array `which` whose binary64 value
+ * differs in bits from expected[i] (host array of `count` values, NaN
+ * matches NaN); counts[i] receives instance i's count.  Blocking. */
+TS_API int ts_batch_mismatch_count(ts_target exec, ts_batch batch, int which,
+                                   const double *expected, uint64_t *counts);
+
+/* ------------------------------------------------------------------------ */
+/* HIP graphs                                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Capture the four batched maps of one benchmark iteration (copy, scale,
+ * add, triad) on the target's stream into an instantiated graph.  The
+ * target's stream must not be the legacy default stream
+ * (TS_E_UNSUPPORTED).  The batch must outlive the graph. */
+TS_API int ts_graph_capture_stream_iteration(ts_target target, ts_batch batch,
+                                             ts_graph *out);
+/* Capture a single batched map (one graph node). */
+TS_API int ts_graph_capture_batch_op(ts_target target, ts_batch batch,
+                                     ts_op op, ts_graph *out);
+/* Capture one plain benchmark iteration over arrays a, b, c (four nodes). */
+TS_API int ts_graph_capture_arrays_iteration(ts_target target, ts_array a,
+                                             ts_array b, ts_array c, double q,
+                                             ts_graph *out);
+/* Enqueue the graph `repeats` times on the target's stream. */
+TS_API int ts_graph_launch(ts_target target, ts_graph graph, int repeats);
+TS_API int ts_graph_destroy(ts_graph graph);
+
+/* ------------------------------------------------------------------------ */
+/* Events: completion and timing of enqueued work (Listing 2's futures)      */
+/* ------------------------------------------------------------------------ */
+
+TS_API int ts_event_create(ts_event *out);
+TS_API int ts_event_destroy(ts_event event);
+/* Mark the current end of the target's stream. */
+TS_API int ts_event_record(ts_event event, ts_target target);
+TS_API int ts_event_synchronize(ts_event event);
+/* TS_OK (0) if the recorded work has finished, 1 if it is still pending. */
+TS_API int ts_event_query(ts_event event);
+TS_API int ts_event_elapsed_ms(ts_event start, ts_event end, float *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSTREAM_H */

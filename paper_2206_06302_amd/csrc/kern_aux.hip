@@ -1,0 +1,274 @@
+// kern_aux.hip -- device-side bulk construction (fill) and the validation
+// reductions used to check STREAM results on the GPU.
+//
+// Bulk construction runs on the device, as the paper's GPU allocator does
+// (Section 3.2, Listing 1's bulk_construct; Section 4.2).  The uniform fill
+// is SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) evaluated at a counter,
+// so any element can be regenerated alone.
+#include "ts_device.hpp"
+#include "ts_internal.hpp"
+
+namespace ts {
+
+namespace {
+
+constexpr uint64_t kGamma = 0x9e3779b97f4a7c15ull;
+
+__device__ __forceinline__ uint64_t splitmix64_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// Store a binary64 value into storage format DT: binary32 by nearest-even,
+// then the 16-bit formats by nearest-even from that binary32 value.
+template <int DT>
+__device__ __forceinline__ typename Fmt<DT>::T from_f64(double v) {
+  if constexpr (DT == DT_F64) return v;
+  else if constexpr (DT == DT_F32) return static_cast<float>(v);
+  else return narrow<DT>(static_cast<float>(v));
+}
+
+template <int DT>
+__device__ __forceinline__ double to_f64(typename Fmt<DT>::T v) {
+  return static_cast<double>(widen<DT>(v));
+}
+
+__device__ __forceinline__ double uniform_pm1(uint64_t state0, uint64_t counter) {
+  const uint64_t h = splitmix64_mix(state0 + counter * kGamma);
+  return static_cast<double>(h >> 11) * 0x1p-52 - 1.0;
+}
+
+__device__ __forceinline__ bool differs(double v, double e) {
+  if (__builtin_isnan(v) && __builtin_isnan(e)) return false;
+  return __builtin_bit_cast(uint64_t, v) != __builtin_bit_cast(uint64_t, e);
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void fill_const_kernel(void* p, uint64_t n, double value) {
+  using T = typename Fmt<DT>::T;
+  T* d = static_cast<T*>(p);
+  const T v = from_f64<DT>(value);
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n; j += stride)
+    d[j] = v;
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void fill_uniform_kernel(void* p, uint64_t n, uint64_t state0,
+                                                           uint64_t first) {
+  using T = typename Fmt<DT>::T;
+  T* d = static_cast<T*>(p);
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n; j += stride)
+    d[j] = from_f64<DT>(uniform_pm1(state0, first + j + 1));
+}
+
+__device__ __forceinline__ void combine(CsPart& a, const CsPart& b) {
+  a.sum += b.sum;
+  a.absdev += b.absdev;
+  a.maxdev = fmax(a.maxdev, b.maxdev);
+  a.mism += b.mism;
+}
+
+// Fixed-order tree over the 256 lanes of a workgroup.
+__device__ CsPart block_reduce(CsPart v) {
+  __shared__ double s_sum[kReduceBlock], s_abs[kReduceBlock], s_max[kReduceBlock];
+  __shared__ unsigned long long s_cnt[kReduceBlock];
+  const uint32_t t = threadIdx.x;
+  s_sum[t] = v.sum;
+  s_abs[t] = v.absdev;
+  s_max[t] = v.maxdev;
+  s_cnt[t] = v.mism;
+  __syncthreads();
+  for (uint32_t s = kReduceBlock / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      s_sum[t] += s_sum[t + s];
+      s_abs[t] += s_abs[t + s];
+      s_max[t] = fmax(s_max[t], s_max[t + s]);
+      s_cnt[t] += s_cnt[t + s];
+    }
+    __syncthreads();
+  }
+  return CsPart{s_sum[0], s_abs[0], s_max[0], s_cnt[0]};
+}
+
+// Pass 1: workgroup g reduces the contiguous range [g*n/P, (g+1)*n/P).
+template <int DT>
+__global__ __launch_bounds__(256) void checksum_pass1(const void* xv, uint64_t n, double expected,
+                                                      CsPart* parts, uint32_t nparts) {
+  using T = typename Fmt<DT>::T;
+  const T* x = static_cast<const T*>(xv);
+  const uint64_t lo = static_cast<uint64_t>(blockIdx.x) * n / nparts;
+  const uint64_t hi = static_cast<uint64_t>(blockIdx.x + 1) * n / nparts;
+  CsPart acc{0.0, 0.0, __builtin_nan(""), 0ull};
+  for (uint64_t j = lo + threadIdx.x; j < hi; j += kReduceBlock) {
+    const double v = to_f64<DT>(x[j]);
+    const double dv = fabs(v - expected);
+    acc.sum += v;
+    acc.absdev += dv;
+    acc.maxdev = fmax(acc.maxdev, dv);
+    acc.mism += differs(v, expected) ? 1ull : 0ull;
+  }
+  const CsPart r = block_reduce(acc);
+  if (threadIdx.x == 0) parts[blockIdx.x] = r;
+}
+
+// Pass 2: one workgroup folds the parts in a fixed order.
+__global__ __launch_bounds__(256) void reduce_pass2(const CsPart* parts, uint32_t nparts, CsPart* out) {
+  CsPart acc{0.0, 0.0, __builtin_nan(""), 0ull};
+  for (uint32_t j = threadIdx.x; j < nparts; j += kReduceBlock) combine(acc, parts[j]);
+  const CsPart r = block_reduce(acc);
+  if (threadIdx.x == 0) *out = r;
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void mismatch_pass1(const void* xv, const void* rv, uint64_t n,
+                                                      CsPart* parts, uint32_t nparts) {
+  using T = typename Fmt<DT>::T;
+  const T* x = static_cast<const T*>(xv);
+  const T* r = static_cast<const T*>(rv);
+  const uint64_t lo = static_cast<uint64_t>(blockIdx.x) * n / nparts;
+  const uint64_t hi = static_cast<uint64_t>(blockIdx.x + 1) * n / nparts;
+  CsPart acc{0.0, 0.0, 0.0, 0ull};
+  for (uint64_t j = lo + threadIdx.x; j < hi; j += kReduceBlock) {
+    const T a = x[j], b = r[j];
+    bool diff;
+    if constexpr (sizeof(T) == 8) diff = __builtin_bit_cast(uint64_t, a) != __builtin_bit_cast(uint64_t, b);
+    else if constexpr (sizeof(T) == 4) diff = __builtin_bit_cast(uint32_t, a) != __builtin_bit_cast(uint32_t, b);
+    else diff = a != b;
+    if (diff && __builtin_isnan(to_f64<DT>(a)) && __builtin_isnan(to_f64<DT>(b))) diff = false;
+    acc.mism += diff ? 1ull : 0ull;
+  }
+  const CsPart res = block_reduce(acc);
+  if (threadIdx.x == 0) parts[blockIdx.x] = res;
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void batch_fill_kernel(const BatchDesc* descs, const BatchTile* tiles,
+                                                         uint64_t ntiles, int which, int uniform,
+                                                         double value, uint64_t seed) {
+  using T = typename Fmt<DT>::T;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const BatchTile tl = tiles[t];
+    const BatchDesc ds = descs[tl.inst];
+    T* d = static_cast<T*>(const_cast<void*>(which == 0 ? ds.a : which == 1 ? ds.b : ds.c));
+    const uint64_t state0 = seed ^ ((16ull + 3ull * tl.inst + static_cast<uint64_t>(which)) << 48);
+    const T cv = from_f64<DT>(value);
+    for (uint64_t j = tl.start + threadIdx.x; j < tl.end; j += blockDim.x)
+      d[j] = uniform ? from_f64<DT>(uniform_pm1(state0, j + 1)) : cv;
+  }
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void batch_mismatch_kernel(const BatchDesc* descs,
+                                                             const BatchTile* tiles, uint64_t ntiles,
+                                                             int which, const double* expected,
+                                                             unsigned long long* counts) {
+  using T = typename Fmt<DT>::T;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const BatchTile tl = tiles[t];
+    const BatchDesc ds = descs[tl.inst];
+    const T* x = static_cast<const T*>(which == 0 ? ds.a : which == 1 ? ds.b : ds.c);
+    const double e = expected[tl.inst];
+    CsPart acc{0.0, 0.0, 0.0, 0ull};
+    for (uint64_t j = tl.start + threadIdx.x; j < tl.end; j += kReduceBlock)
+      acc.mism += differs(to_f64<DT>(x[j]), e) ? 1ull : 0ull;
+    const CsPart r = block_reduce(acc);
+    if (threadIdx.x == 0 && r.mism) atomicAdd(&counts[tl.inst], r.mism);
+    __syncthreads();  // the next tile reuses the shared reduction arrays
+  }
+}
+
+__global__ __launch_bounds__(256) void zero_u64_kernel(unsigned long long* p, uint64_t n) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n; j += stride)
+    p[j] = 0ull;
+}
+
+uint32_t fill_grid(uint64_t n) {
+  const uint64_t g = (n + 255) / 256;
+  return static_cast<uint32_t>(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+
+}  // namespace
+
+uint32_t reduce_parts(uint64_t n) {
+  const uint64_t p = (n + 4095) / 4096;
+  return static_cast<uint32_t>(p < 1 ? 1 : (p > kReduceMaxParts ? kReduceMaxParts : p));
+}
+
+#define TS_BY_FORMAT(dt, KERNEL, ...)                                                          \
+  switch (dt) {                                                                                \
+    case DT_F64: hipLaunchKernelGGL(KERNEL<DT_F64>, __VA_ARGS__); break;                       \
+    case DT_F32: hipLaunchKernelGGL(KERNEL<DT_F32>, __VA_ARGS__); break;                       \
+    case DT_BF16: hipLaunchKernelGGL(KERNEL<DT_BF16>, __VA_ARGS__); break;                     \
+    case DT_F16: hipLaunchKernelGGL(KERNEL<DT_F16>, __VA_ARGS__); break;                       \
+    default: return hipErrorInvalidValue;                                                      \
+  }                                                                                            \
+  return hipGetLastError();
+
+hipError_t launch_fill_const(int dt, void* p, uint64_t n, double value, hipStream_t s) {
+  TS_BY_FORMAT(dt, fill_const_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, n, value)
+}
+
+hipError_t launch_fill_uniform(int dt, void* p, uint64_t n, uint64_t seed, uint64_t stream_id,
+                               uint64_t first_index, hipStream_t s) {
+  const uint64_t state0 = seed ^ (stream_id << 48);
+  TS_BY_FORMAT(dt, fill_uniform_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, n, state0, first_index)
+}
+
+hipError_t launch_checksum(int dt, const void* x, uint64_t n, double expected, void* scratch,
+                           hipStream_t s) {
+  CsPart* parts = static_cast<CsPart*>(scratch);
+  const uint32_t np = reduce_parts(n);
+  switch (dt) {
+    case DT_F64: hipLaunchKernelGGL(checksum_pass1<DT_F64>, dim3(np), dim3(kReduceBlock), 0, s, x, n, expected, parts, np); break;
+    case DT_F32: hipLaunchKernelGGL(checksum_pass1<DT_F32>, dim3(np), dim3(kReduceBlock), 0, s, x, n, expected, parts, np); break;
+    case DT_BF16: hipLaunchKernelGGL(checksum_pass1<DT_BF16>, dim3(np), dim3(kReduceBlock), 0, s, x, n, expected, parts, np); break;
+    case DT_F16: hipLaunchKernelGGL(checksum_pass1<DT_F16>, dim3(np), dim3(kReduceBlock), 0, s, x, n, expected, parts, np); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_pass2, dim3(1), dim3(kReduceBlock), 0, s, parts, np, parts + kReduceMaxParts);
+  return hipGetLastError();
+}
+
+hipError_t launch_mismatch(int dt, const void* x, const void* ref, uint64_t n, void* scratch,
+                           hipStream_t s) {
+  CsPart* parts = static_cast<CsPart*>(scratch);
+  const uint32_t np = reduce_parts(n);
+  switch (dt) {
+    case DT_F64: hipLaunchKernelGGL(mismatch_pass1<DT_F64>, dim3(np), dim3(kReduceBlock), 0, s, x, ref, n, parts, np); break;
+    case DT_F32: hipLaunchKernelGGL(mismatch_pass1<DT_F32>, dim3(np), dim3(kReduceBlock), 0, s, x, ref, n, parts, np); break;
+    case DT_BF16: hipLaunchKernelGGL(mismatch_pass1<DT_BF16>, dim3(np), dim3(kReduceBlock), 0, s, x, ref, n, parts, np); break;
+    case DT_F16: hipLaunchKernelGGL(mismatch_pass1<DT_F16>, dim3(np), dim3(kReduceBlock), 0, s, x, ref, n, parts, np); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_pass2, dim3(1), dim3(kReduceBlock), 0, s, parts, np, parts + kReduceMaxParts);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_fill(int dt, const BatchDesc* descs, const BatchTile* tiles, uint64_t ntiles,
+                             int which, int uniform, double value, uint64_t seed, uint32_t grid,
+                             hipStream_t s) {
+  TS_BY_FORMAT(dt, batch_fill_kernel, dim3(grid), dim3(256), 0, s, descs, tiles, ntiles, which,
+               uniform, value, seed)
+}
+
+hipError_t launch_batch_mismatch(int dt, const BatchDesc* descs, const BatchTile* tiles,
+                                 uint64_t ntiles, int which, const double* expected,
+                                 unsigned long long* counts, uint32_t grid, hipStream_t s) {
+  TS_BY_FORMAT(dt, batch_mismatch_kernel, dim3(grid), dim3(kReduceBlock), 0, s, descs, tiles, ntiles,
+               which, expected, counts)
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, uint64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace ts

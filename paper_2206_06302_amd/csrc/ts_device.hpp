@@ -1,0 +1,352 @@
+// ts_device.hpp -- gfx950 device code for the STREAM maps (Section 5,
+// Listing 4 of Heller et al.): copy, scale, add, triad over placed arrays.
+//
+// Design (CDNA4, HBM-bound, no matrix cores: nothing here is a contraction):
+//  * every lane moves VB bytes per access (16 B -> global_load/store_dwordx4),
+//    so one wave instruction covers 1 KiB of contiguous memory;
+//  * U independent vectors per lane are loaded before any is stored, giving
+//    U (or 2U) loads in flight per lane without LDS or barriers;
+//  * optional nontemporal hints on loads and stores (streaming data is never
+//    reused);
+//  * either one pass (grid covers the array once) or a grid-stride loop over
+//    a fixed grid; both keep element ownership disjoint, so results do not
+//    depend on the launch shape;
+//  * reduced-precision storage widens exactly to binary32, evaluates the map
+//    in binary32 and rounds back to nearest-even.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ts_internal.hpp"
+
+namespace ts {
+
+enum : int { OP_COPY = 0, OP_SCALE = 1, OP_ADD = 2, OP_TRIAD = 3 };
+enum : int { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3 };
+
+// Storage type T and arithmetic type C of each storage format.
+template <int DT> struct Fmt;
+template <> struct Fmt<DT_F64> { using T = double; using C = double; };
+template <> struct Fmt<DT_F32> { using T = float; using C = float; };
+template <> struct Fmt<DT_BF16> { using T = uint16_t; using C = float; };
+template <> struct Fmt<DT_F16> { using T = uint16_t; using C = float; };
+
+// Keep a binary32 result in a register as it is, so the compiler cannot fold
+// the multiply or add into a mixed-precision instruction that rounds once,
+// straight to 16 bits: the map is defined as binary32 arithmetic followed by
+// a separate rounding to the storage format.
+__device__ __forceinline__ float materialize(float v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
+template <int DT>
+__device__ __forceinline__ typename Fmt<DT>::C widen(typename Fmt<DT>::T v) {
+  if constexpr (DT == DT_BF16) {
+    return __builtin_bit_cast(float, static_cast<uint32_t>(v) << 16);
+  } else if constexpr (DT == DT_F16) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, v));
+  } else {
+    return v;
+  }
+}
+
+// Round-to-nearest-even narrowing (the hardware conversions use the MODE
+// register's rounding, which is nearest-even).
+template <int DT>
+__device__ __forceinline__ typename Fmt<DT>::T narrow(typename Fmt<DT>::C v) {
+  if constexpr (DT == DT_BF16) {
+    return __builtin_bit_cast(uint16_t, static_cast<__bf16>(materialize(v)));
+  } else if constexpr (DT == DT_F16) {
+    return __builtin_bit_cast(uint16_t, static_cast<_Float16>(materialize(v)));
+  } else {
+    return v;
+  }
+}
+
+template <int OP, typename C>
+__device__ __forceinline__ C apply(C x, C y, C q) {
+  if constexpr (OP == OP_SCALE) {
+    return q * x;
+  } else if constexpr (OP == OP_ADD) {
+    return x + y;
+  } else if constexpr (OP == OP_TRIAD) {
+    if constexpr (sizeof(C) == 8) return __builtin_fma(q, y, x);
+    else return __builtin_fmaf(q, y, x);
+  } else {
+    return x;
+  }
+}
+
+template <int OP> constexpr bool uses_y() { return OP == OP_ADD || OP == OP_TRIAD; }
+
+// Raw lane vector of VB bytes.
+template <int VB> struct Raw;
+template <> struct Raw<16> { typedef uint32_t type __attribute__((ext_vector_type(4))); };
+template <> struct Raw<8> { typedef uint32_t type __attribute__((ext_vector_type(2))); };
+template <> struct Raw<4> { typedef uint32_t type; };
+template <> struct Raw<2> { typedef uint16_t type; };
+
+template <int VB, bool NT>
+__device__ __forceinline__ typename Raw<VB>::type load(const void* p) {
+  using R = typename Raw<VB>::type;
+  if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const R*>(p));
+  else return *reinterpret_cast<const R*>(p);
+}
+
+template <int VB, bool NT>
+__device__ __forceinline__ void store(void* p, typename Raw<VB>::type v) {
+  using R = typename Raw<VB>::type;
+  if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<R*>(p));
+  else *reinterpret_cast<R*>(p) = v;
+}
+
+template <typename T, int VB> union Pack {
+  typename Raw<VB>::type raw;
+  T e[VB / sizeof(T)];
+};
+
+// The map over one raw vector.  Copy moves the bits unchanged.
+template <int DT, int OP, int VB>
+__device__ __forceinline__ typename Raw<VB>::type map_vec(typename Raw<VB>::type rx,
+                                                          typename Raw<VB>::type ry,
+                                                          typename Fmt<DT>::C q) {
+  if constexpr (OP == OP_COPY) {
+    return rx;
+  } else {
+    using T = typename Fmt<DT>::T;
+    constexpr int V = VB / sizeof(T);
+    Pack<T, VB> px, py, pd;
+    px.raw = rx;
+    py.raw = ry;
+#pragma unroll
+    for (int k = 0; k < V; ++k)
+      pd.e[k] = narrow<DT>(apply<OP>(widen<DT>(px.e[k]), widen<DT>(py.e[k]), q));
+    return pd.raw;
+  }
+}
+
+// The map on element j (head, tail and element-wise paths).
+template <int DT, int OP>
+__device__ __forceinline__ void map_elem(const typename Fmt<DT>::T* x, const typename Fmt<DT>::T* y,
+                                         typename Fmt<DT>::T* d, typename Fmt<DT>::C q, uint64_t j) {
+  if constexpr (OP == OP_COPY) {
+    d[j] = x[j];
+  } else {
+    typename Fmt<DT>::C yv = 0;
+    if constexpr (uses_y<OP>()) yv = widen<DT>(y[j]);
+    d[j] = narrow<DT>(apply<OP>(widen<DT>(x[j]), yv, q));
+  }
+}
+
+template <int DT>
+__device__ __forceinline__ typename Fmt<DT>::C pick_q(double q, float qf) {
+  if constexpr (sizeof(typename Fmt<DT>::C) == 8) return q;
+  else return qf;
+}
+
+// Vector body over nvec VB-byte vectors starting at xb/yb/db (all VB-aligned):
+// lane `lane` of a group of `width` lanes handles vectors v0, v0+width, ...
+// U at a time, starting at `first`, with stride `step` between groups.
+template <int DT, int OP, int VB, int U, bool NTL, bool NTS>
+__device__ __forceinline__ void vec_body(const char* xb, const char* yb, char* db,
+                                         typename Fmt<DT>::C q, uint64_t nvec, uint64_t first,
+                                         uint64_t width, uint64_t step) {
+  using R = typename Raw<VB>::type;
+  for (uint64_t v0 = first; v0 < nvec; v0 += step) {
+    if (v0 + (U - 1) * width < nvec) {
+      R rx[U], ry[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        rx[k] = load<VB, NTL>(xb + (v0 + k * width) * VB);
+        if constexpr (uses_y<OP>()) ry[k] = load<VB, NTL>(yb + (v0 + k * width) * VB);
+        else ry[k] = rx[k];
+      }
+#pragma unroll
+      for (int k = 0; k < U; ++k)
+        store<VB, NTS>(db + (v0 + k * width) * VB, map_vec<DT, OP, VB>(rx[k], ry[k], q));
+    } else {
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const uint64_t v = v0 + k * width;
+        if (v < nvec) {
+          R rx = load<VB, NTL>(xb + v * VB);
+          R ry = rx;
+          if constexpr (uses_y<OP>()) ry = load<VB, NTL>(yb + v * VB);
+          store<VB, NTS>(db + v * VB, map_vec<DT, OP, VB>(rx, ry, q));
+        }
+      }
+    }
+  }
+}
+
+// Plain kernel: elements [0, head) and the `tail` elements after the vector
+// body are done one per lane by the first lanes of the grid; the body covers
+// nvec vectors of VB bytes starting at element `head`.
+template <int DT, int OP, int VB, int U, bool NTL, bool NTS>
+__global__ __launch_bounds__(1024) void stream_kernel(const void* xv, const void* yv, void* dv,
+                                                      double q, float qf, uint64_t head,
+                                                      uint64_t nvec, uint64_t tail) {
+  using T = typename Fmt<DT>::T;
+  constexpr int V = VB / sizeof(T);
+  const T* x = static_cast<const T*>(xv);
+  const T* y = static_cast<const T*>(yv);
+  T* d = static_cast<T*>(dv);
+  const typename Fmt<DT>::C qc = pick_q<DT>(q, qf);
+  const uint64_t width = blockDim.x;
+  const uint64_t gid = static_cast<uint64_t>(blockIdx.x) * width + threadIdx.x;
+  if (gid < head) map_elem<DT, OP>(x, y, d, qc, gid);
+  if (gid < tail) map_elem<DT, OP>(x, y, d, qc, head + nvec * V + gid);
+  const char* xb = reinterpret_cast<const char*>(x + head);
+  const char* yb = reinterpret_cast<const char*>(y + head);
+  char* db = reinterpret_cast<char*>(d + head);
+  vec_body<DT, OP, VB, U, NTL, NTS>(xb, yb, db, qc, nvec,
+                                    static_cast<uint64_t>(blockIdx.x) * width * U + threadIdx.x,
+                                    width, static_cast<uint64_t>(gridDim.x) * width * U);
+}
+
+// ---------------------------------------------------------------------------
+// Batched ragged instances.
+// ---------------------------------------------------------------------------
+
+template <int OP>
+__device__ __forceinline__ void roles(const BatchDesc& ds, const void*& x, const void*& y, void*& d) {
+  // Listing 4 roles inside every instance.
+  if constexpr (OP == OP_COPY) { x = ds.a; y = nullptr; d = const_cast<void*>(ds.c); }
+  else if constexpr (OP == OP_SCALE) { x = ds.c; y = nullptr; d = const_cast<void*>(ds.b); }
+  else if constexpr (OP == OP_ADD) { x = ds.a; y = ds.b; d = const_cast<void*>(ds.c); }
+  else { x = ds.b; y = ds.c; d = const_cast<void*>(ds.a); }
+}
+
+// Persistent kernel: workgroup w takes tiles w, w + G, w + 2G, ... (static
+// stride, G = grid size); inside a tile the lanes stream 16-byte vectors.
+template <int DT, int OP, int U, bool NTL, bool NTS>
+__global__ __launch_bounds__(1024) void batch_kernel(const BatchDesc* __restrict__ descs,
+                                                     const BatchTile* __restrict__ tiles,
+                                                     uint64_t ntiles) {
+  using T = typename Fmt<DT>::T;
+  constexpr int VB = 16;
+  constexpr uint64_t V = VB / sizeof(T);
+  const uint64_t width = blockDim.x;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const BatchTile tl = tiles[t];
+    const BatchDesc ds = descs[tl.inst];
+    const void *xv, *yv;
+    void* dv;
+    roles<OP>(ds, xv, yv, dv);
+    const T* x = static_cast<const T*>(xv);
+    const T* y = static_cast<const T*>(yv);
+    T* d = static_cast<T*>(dv);
+    const typename Fmt<DT>::C qc = pick_q<DT>(ds.q, ds.qf);
+    uint64_t vs = tl.end, ve = tl.end;  // vector range [vs, ve)
+    if (ds.vec_ok) {
+      const uint64_t h = ds.head;
+      vs = tl.start < h ? h : h + (tl.start - h + V - 1) / V * V;
+      if (vs > tl.end) vs = tl.end;
+      ve = tl.end < h ? vs : h + (tl.end - h) / V * V;
+      if (ve < vs) ve = vs;
+    }
+    for (uint64_t j = tl.start + threadIdx.x; j < vs; j += width) map_elem<DT, OP>(x, y, d, qc, j);
+    for (uint64_t j = ve + threadIdx.x; j < tl.end; j += width) map_elem<DT, OP>(x, y, d, qc, j);
+    const uint64_t nvec = (ve - vs) / V;
+    if (nvec) {
+      vec_body<DT, OP, VB, U, NTL, NTS>(reinterpret_cast<const char*>(x + vs),
+                                        reinterpret_cast<const char*>(y + vs),
+                                        reinterpret_cast<char*>(d + vs), qc, nvec, threadIdx.x,
+                                        width, width * U);
+    }
+  }
+}
+
+template <int DT, int OP, int VB, int U, bool NTL, bool NTS>
+hipError_t launch_plain_inst(const PlainLaunch& L) {
+  hipLaunchKernelGGL((stream_kernel<DT, OP, VB, U, NTL, NTS>), dim3(L.grid), dim3(L.block), 0,
+                     L.stream, L.x, L.y, L.d, L.q, L.qf, L.head, L.nvec, L.tail);
+  return hipGetLastError();
+}
+
+template <int DT, int OP, int VB, int U>
+hipError_t plain_nt(const PlainLaunch& L) {
+  if (L.ntl) {
+    return L.nts ? launch_plain_inst<DT, OP, VB, U, true, true>(L)
+                 : launch_plain_inst<DT, OP, VB, U, true, false>(L);
+  }
+  return L.nts ? launch_plain_inst<DT, OP, VB, U, false, true>(L)
+               : launch_plain_inst<DT, OP, VB, U, false, false>(L);
+}
+
+template <int DT, int OP, int VB>
+hipError_t plain_u(const PlainLaunch& L) {
+  switch (L.unroll) {
+    case 1: return plain_nt<DT, OP, VB, 1>(L);
+    case 2: return plain_nt<DT, OP, VB, 2>(L);
+    case 4: return plain_nt<DT, OP, VB, 4>(L);
+    case 8: return plain_nt<DT, OP, VB, 8>(L);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int DT, int OP>
+hipError_t plain_vb(const PlainLaunch& L) {
+  constexpr int ES = sizeof(typename Fmt<DT>::T);
+  switch (L.vb) {
+    case 16: return plain_u<DT, OP, 16>(L);
+    case 8: return plain_u<DT, OP, 8>(L);
+    default:
+      if (L.vb == ES) return plain_u<DT, OP, ES>(L);
+      return hipErrorInvalidValue;
+  }
+}
+
+template <int DT>
+hipError_t plain_dispatch(const PlainLaunch& L) {
+  switch (L.op) {
+    case OP_COPY: return plain_vb<DT, OP_COPY>(L);
+    case OP_SCALE: return plain_vb<DT, OP_SCALE>(L);
+    case OP_ADD: return plain_vb<DT, OP_ADD>(L);
+    case OP_TRIAD: return plain_vb<DT, OP_TRIAD>(L);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int DT, int OP, int U, bool NTL, bool NTS>
+hipError_t launch_batch_inst(const BatchLaunch& L) {
+  hipLaunchKernelGGL((batch_kernel<DT, OP, U, NTL, NTS>), dim3(L.grid), dim3(L.block), 0, L.stream,
+                     L.descs, L.tiles, L.ntiles);
+  return hipGetLastError();
+}
+
+template <int DT, int OP, int U>
+hipError_t batch_nt(const BatchLaunch& L) {
+  if (L.ntl) {
+    return L.nts ? launch_batch_inst<DT, OP, U, true, true>(L)
+                 : launch_batch_inst<DT, OP, U, true, false>(L);
+  }
+  return L.nts ? launch_batch_inst<DT, OP, U, false, true>(L)
+               : launch_batch_inst<DT, OP, U, false, false>(L);
+}
+
+template <int DT, int OP>
+hipError_t batch_u(const BatchLaunch& L) {
+  switch (L.unroll) {
+    case 1: return batch_nt<DT, OP, 1>(L);
+    case 2: return batch_nt<DT, OP, 2>(L);
+    case 4: return batch_nt<DT, OP, 4>(L);
+    case 8: return batch_nt<DT, OP, 8>(L);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int DT>
+hipError_t batch_dispatch(const BatchLaunch& L) {
+  switch (L.op) {
+    case OP_COPY: return batch_u<DT, OP_COPY>(L);
+    case OP_SCALE: return batch_u<DT, OP_SCALE>(L);
+    case OP_ADD: return batch_u<DT, OP_ADD>(L);
+    case OP_TRIAD: return batch_u<DT, OP_TRIAD>(L);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ts

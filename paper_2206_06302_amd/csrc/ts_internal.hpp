@@ -1,0 +1,80 @@
+// ts_internal.hpp -- declarations shared by the host runtime and the kernel
+// translation units of libtstream (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "ts_layout.hpp"
+
+namespace ts {
+
+// Arguments of one plain launch: element-wise head, nvec vectors of vb
+// bytes, element-wise tail (see plan_plain), and the launch shape.
+struct PlainLaunch {
+  const void* x;
+  const void* y;
+  void* d;
+  double q;
+  float qf;
+  uint64_t head, nvec, tail;
+  uint32_t grid, block;
+  int op, vb, unroll, ntl, nts;
+  hipStream_t stream;
+};
+
+// Arguments of one persistent batched launch over a tile table.
+struct BatchLaunch {
+  const BatchDesc* descs;
+  const BatchTile* tiles;
+  uint64_t ntiles;
+  uint32_t grid, block;
+  int op, unroll, ntl, nts;
+  hipStream_t stream;
+};
+
+// Per-format dispatch of the STREAM kernels (kern_<fmt>.hip).
+hipError_t plain_launch_f64(const PlainLaunch& L);
+hipError_t plain_launch_f32(const PlainLaunch& L);
+hipError_t plain_launch_bf16(const PlainLaunch& L);
+hipError_t plain_launch_f16(const PlainLaunch& L);
+hipError_t batch_launch_f64(const BatchLaunch& L);
+hipError_t batch_launch_f32(const BatchLaunch& L);
+hipError_t batch_launch_bf16(const BatchLaunch& L);
+hipError_t batch_launch_f16(const BatchLaunch& L);
+
+// Partial results of the validation reductions (kern_aux.hip).
+struct CsPart {
+  double sum;
+  double absdev;
+  double maxdev;
+  unsigned long long mism;
+};
+
+// Fixed reduction shape: depends only on n, never on tuning.
+constexpr uint32_t kReduceBlock = 256;
+constexpr uint32_t kReduceMaxParts = 1024;
+uint32_t reduce_parts(uint64_t n);
+// Device scratch a target needs for one reduction: parts plus the result.
+constexpr size_t kReduceScratchBytes = (kReduceMaxParts + 1) * sizeof(CsPart);
+
+hipError_t launch_fill_const(int dt, void* p, uint64_t n, double value, hipStream_t s);
+hipError_t launch_fill_uniform(int dt, void* p, uint64_t n, uint64_t seed, uint64_t stream_id,
+                               uint64_t first_index, hipStream_t s);
+// Leaves the reduced CsPart at scratch + kReduceMaxParts parts.
+hipError_t launch_checksum(int dt, const void* x, uint64_t n, double expected, void* scratch,
+                           hipStream_t s);
+// Leaves the count in the `mism` field of the part after kReduceMaxParts.
+hipError_t launch_mismatch(int dt, const void* x, const void* ref, uint64_t n, void* scratch,
+                           hipStream_t s);
+hipError_t launch_batch_fill(int dt, const BatchDesc* descs, const BatchTile* tiles,
+                             uint64_t ntiles, int which, int uniform, double value, uint64_t seed,
+                             uint32_t grid, hipStream_t s);
+// counts: device array of one unsigned long long per instance, zeroed by the
+// caller's fill kernel (launch_zero_u64).
+hipError_t launch_batch_mismatch(int dt, const BatchDesc* descs, const BatchTile* tiles,
+                                 uint64_t ntiles, int which, const double* expected,
+                                 unsigned long long* counts, uint32_t grid, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long* p, uint64_t n, hipStream_t s);
+
+}  // namespace ts

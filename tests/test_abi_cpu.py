@@ -1,0 +1,314 @@
+"""CPU-side tests of the C-ABI library: exports, argument checks that need no
+device, the tuning table, and the GPU-free launch/batch planning rules."""
+import ctypes
+import json
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tstream.h")
+LIBPATH = os.path.join(ROOT, "paper_2206_06302_amd", "libtstream.so")
+CSRC = os.path.join(ROOT, "paper_2206_06302_amd", "csrc")
+
+TS_OK, TS_E_INVALID, TS_E_SHAPE, TS_E_DTYPE, TS_E_PLACEMENT, TS_E_ALIAS, TS_E_DEVICE = 0, -1, -2, -3, -4, -5, -6
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"TS_API\s+[^;(]*?\b(ts_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def raw():
+    if not os.path.exists(LIBPATH):
+        pytest.fail("libtstream.so is not built (run __graft_entry__.build())")
+    import torch  # noqa: F401  (load torch's HIP runtime first, as the binding does)
+    return ctypes.CDLL(LIBPATH)
+
+
+@pytest.fixture(scope="module")
+def ts():
+    import paper_2206_06302_amd as ts
+    return ts
+
+
+def test_every_declared_symbol_is_exported(raw):
+    names = declared_functions()
+    assert len(names) >= 50
+    missing = [n for n in names if not hasattr(raw, n)]
+    assert not missing, missing
+
+
+def test_no_undeclared_exports():
+    out = subprocess.run(["nm", "-D", "--defined-only", LIBPATH], capture_output=True, text=True, check=True).stdout
+    exported = sorted(l.split()[-1] for l in out.splitlines() if l.split()[-1].startswith("ts_"))
+    assert exported == declared_functions()
+
+
+def test_binding_covers_every_function(ts):
+    from paper_2206_06302_amd import _lib
+    assert sorted(_lib.PROTOTYPES) == declared_functions()
+
+
+def test_version_and_errors(ts):
+    assert ts.version() == (1, 0)
+    L = ts.lib
+    assert L.ts_copy(None, None, None) == TS_E_INVALID
+    assert "invalid" in ts.last_error()
+    assert L.ts_triad(None, None, None, None, ctypes.c_double(3.0)) == TS_E_INVALID
+    assert L.ts_target_synchronize(None) == TS_E_INVALID
+    assert L.ts_array_info(None, None, None, None) == TS_E_INVALID
+    assert L.ts_version(None, None) == TS_E_INVALID
+    # destroy/free accept NULL as a no-op and never fail on it
+    for fn in ("ts_target_destroy", "ts_array_free", "ts_batch_destroy", "ts_graph_destroy", "ts_event_destroy"):
+        assert getattr(L, fn)(None) == TS_OK
+    assert L.ts_batch_op(None, None, 3) == TS_E_INVALID
+    assert L.ts_graph_launch(None, None, 1) == TS_E_INVALID
+    assert L.ts_event_query(None) == TS_E_INVALID
+
+
+def test_target_create_without_gpu_reports_device_error(ts):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    rc = ts.lib.ts_target_create(0, None, ctypes.byref(h))
+    assert rc == TS_E_DEVICE and "GPU" in ts.last_error()
+    assert ts.lib.ts_target_create(0, None, None) == TS_E_INVALID
+
+
+# --------------------------------------------------------------- tuning table
+def test_tune_table_roundtrip(ts, tmp_path):
+    ts.tune_cache_clear()
+    base = ts.get_kernel_cfg("triad", "f64", 1 << 27)
+    assert base["vec_bytes"] == 16 and base["grid_per_cu"] == 0
+    p = tmp_path / "t.json"
+    doc = {"format": "tstream-tune", "version": 1, "entries": [
+        {"op": "triad", "dtype": "f64", "bucket": 27, "align": 0, "batched": 0, "block": 512, "unroll": 2,
+         "vec_bytes": 16, "nt_load": 1, "nt_store": 1, "grid_per_cu": 4, "tile_elems": 0, "bytes_per_s": 6.9e12},
+        {"op": "copy", "dtype": "bf16", "bucket": 20, "align": 1, "batched": 0, "block": 1024, "unroll": 8,
+         "vec_bytes": 8, "nt_load": 0, "nt_store": 0, "grid_per_cu": 0, "tile_elems": 0},
+        {"op": "triad", "dtype": "f64", "bucket": 32, "align": 0, "batched": 1, "block": 256, "unroll": 4,
+         "vec_bytes": 16, "nt_load": 0, "nt_store": 1, "grid_per_cu": 8, "tile_elems": 65536}]}
+    p.write_text(json.dumps(doc))
+    ts.tune_cache_load(str(p))
+    c = ts.get_kernel_cfg("triad", "f64", 1 << 27)
+    assert (c["block"], c["unroll"], c["nt_load"], c["grid_per_cu"]) == (512, 2, 1, 4)
+    # nearest size bucket with the same op/dtype/alignment/batched fields
+    assert ts.get_kernel_cfg("triad", "f64", 1 << 16)["block"] == 512
+    assert ts.get_kernel_cfg("triad", "f64", 1 << 27, align_class=1)["block"] == 256  # default
+    assert ts.get_kernel_cfg("copy", "bf16", 1 << 20, align_class=1)["vec_bytes"] == 8
+    assert ts.get_kernel_cfg("triad", "f64", 4 << 30, batched=True)["tile_elems"] == 65536
+    # mixed misalignment falls back to the element-wise width by default
+    assert ts.get_kernel_cfg("add", "f32", 1000, align_class=2)["vec_bytes"] == 4
+    q = tmp_path / "u.json"
+    ts.tune_cache_save(str(q))
+    saved = json.loads(q.read_text())
+    assert saved["format"] == "tstream-tune" and len(saved["entries"]) == 3
+    ts.tune_cache_clear()
+    ts.tune_cache_load(str(q))
+    assert ts.get_kernel_cfg("triad", "f64", 1 << 27)["block"] == 512
+    ts.tune_cache_clear()
+
+
+@pytest.mark.parametrize("text", [
+    "", "{", "[]", '{"format": "other", "version": 1, "entries": []}',
+    '{"format": "tstream-tune", "version": 2, "entries": []}',
+    '{"format": "tstream-tune", "version": 1}',
+    '{"format": "tstream-tune", "version": 1, "entries": [{"op": "triad"}]}',
+    '{"format": "tstream-tune", "version": 1, "entries": [{"op": "fma", "dtype": "f64", "bucket": 1, "align": 0, '
+    '"batched": 0, "block": 256, "unroll": 4, "vec_bytes": 16, "nt_load": 0, "nt_store": 0, "grid_per_cu": 0, '
+    '"tile_elems": 0}]}',
+    '{"format": "tstream-tune", "version": 1, "entries": [{"op": "copy", "dtype": "f64", "bucket": 1, "align": 0, '
+    '"batched": 0, "block": 100, "unroll": 4, "vec_bytes": 16, "nt_load": 0, "nt_store": 0, "grid_per_cu": 0, '
+    '"tile_elems": 0}]}',
+    '{"format": "tstream-tune", "version": 1, "entries": []} trailing',
+])
+def test_tune_table_rejects_bad_files(ts, tmp_path, text):
+    ts.tune_cache_clear()
+    good = tmp_path / "good.json"
+    good.write_text(json.dumps({"format": "tstream-tune", "version": 1, "entries": [
+        {"op": "add", "dtype": "f32", "bucket": 10, "align": 0, "batched": 0, "block": 128, "unroll": 1,
+         "vec_bytes": 16, "nt_load": 0, "nt_store": 0, "grid_per_cu": 2, "tile_elems": 0}]}))
+    ts.tune_cache_load(str(good))
+    bad = tmp_path / "bad.json"
+    bad.write_text(text)
+    with pytest.raises(ts.TSError) as e:
+        ts.tune_cache_load(str(bad))
+    assert e.value.status == TS_E_INVALID
+    assert ts.get_kernel_cfg("add", "f32", 1024)["block"] == 128  # table unchanged
+    with pytest.raises(ts.TSError):
+        ts.tune_cache_load(str(tmp_path / "missing.json"))
+    ts.tune_cache_clear()
+
+
+def test_forced_configuration(ts):
+    ts.set_kernel_cfg("scale", "f16", {"block": 1024, "unroll": 8, "vec_bytes": 8, "nt_load": 1,
+                                       "nt_store": 0, "grid_per_cu": 2})
+    assert ts.get_kernel_cfg("scale", "f16", 5)["block"] == 1024
+    ts.set_kernel_cfg("scale", "f16", None)
+    assert ts.get_kernel_cfg("scale", "f16", 5)["block"] == 256
+    for bad in ({"block": 96}, {"unroll": 3}, {"vec_bytes": 32}, {"nt_load": 2}, {"grid_per_cu": -1}):
+        cfg = {"block": 256, "unroll": 4, "vec_bytes": 16, "nt_load": 0, "nt_store": 0, "grid_per_cu": 0}
+        cfg.update(bad)
+        with pytest.raises(ts.TSError):
+            ts.set_kernel_cfg("copy", "f64", cfg)
+    with pytest.raises(ts.TSError):  # batched kernels require 16-byte vectors and a persistent grid
+        ts.set_kernel_cfg("copy", "f64", {"vec_bytes": 8, "grid_per_cu": 4, "tile_elems": 8192}, batched=True)
+
+
+def test_candidate_sets_are_valid(ts):
+    plain = ts.candidates()
+    batched = ts.candidates(batched=True)
+    assert len(plain) > 100 and len(batched) > 50
+    keys = {tuple(sorted(c.items())) for c in plain}
+    assert len(keys) == len(plain)
+    for c in plain:
+        ts.set_kernel_cfg("copy", "f64", c)
+    for c in batched:
+        ts.set_kernel_cfg("copy", "f64", c, batched=True)
+        assert c["tile_elems"] % 8 == 0
+    ts.set_kernel_cfg("copy", "f64", None)
+    ts.set_kernel_cfg("copy", "f64", None, batched=True)
+
+
+# ------------------------------------------------- GPU-free planning rules
+@pytest.fixture(scope="module")
+def shim(tmp_path_factory):
+    out = tmp_path_factory.mktemp("shim") / "layout_shim.so"
+    subprocess.run(["g++", "-std=c++17", "-O1", "-shared", "-fPIC", "-Wall", "-I" + CSRC, "-o", str(out),
+                    os.path.join(ROOT, "tests", "cpp", "layout_shim.cpp")], check=True)
+    lib = ctypes.CDLL(str(out))
+    U = ctypes.POINTER(ctypes.c_uint64)
+    lib.shim_check_map.argtypes = [ctypes.c_int, ctypes.c_int, U, U, U, U]
+    lib.shim_align_class.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
+    lib.shim_plan_plain.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                    ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, U]
+    lib.shim_plan_batch.argtypes = [U, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int64, U, ctypes.c_size_t,
+                                    U, U, U]
+    return lib
+
+
+def _u64(vals):
+    return (ctypes.c_uint64 * len(vals))(*vals)
+
+
+def check_map(shim, uses_y, dev, x, y, d):
+    cnt = ctypes.c_uint64()
+    st = shim.shim_check_map(uses_y, dev, _u64(x), _u64(y), _u64(d), ctypes.byref(cnt))
+    return st, cnt.value
+
+
+def test_check_map_rules(shim):
+    B = 1 << 20
+    x = [B, 100, 0, 0]
+    y = [2 * B, 100, 0, 0]
+    d = [3 * B, 100, 0, 0]
+    assert check_map(shim, 1, 0, x, y, d) == (TS_OK, 100)
+    assert check_map(shim, 1, 0, x, y, [3 * B, 99, 0, 0])[0] == TS_E_SHAPE
+    assert check_map(shim, 1, 0, x, [2 * B, 99, 0, 0], d)[0] == TS_E_SHAPE
+    assert check_map(shim, 0, 0, x, [2 * B, 5, 1, 3], d) == (TS_OK, 100)  # y unused by copy/scale
+    assert check_map(shim, 1, 0, x, [2 * B, 100, 1, 0], d)[0] == TS_E_DTYPE
+    assert check_map(shim, 1, 0, x, y, [3 * B, 100, 2, 0])[0] == TS_E_DTYPE
+    assert check_map(shim, 1, 1, x, y, d)[0] == TS_E_PLACEMENT
+    assert check_map(shim, 1, 0, x, y, [3 * B, 100, 0, 1])[0] == TS_E_PLACEMENT
+    assert check_map(shim, 1, 0, x, y, [B, 100, 0, 0]) == (TS_OK, 100)            # in place on x
+    assert check_map(shim, 1, 0, x, y, [2 * B, 100, 0, 0]) == (TS_OK, 100)        # in place on y
+    assert check_map(shim, 1, 0, x, y, [B + 8, 100, 0, 0])[0] == TS_E_ALIAS       # partial overlap
+    assert check_map(shim, 1, 0, x, y, [B - 8 * 99, 100, 0, 0])[0] == TS_E_ALIAS
+    assert check_map(shim, 1, 0, x, y, [B - 8 * 100, 100, 0, 0]) == (TS_OK, 100)  # adjacent, disjoint
+    assert check_map(shim, 1, 0, [B, 0, 0, 0], y, [B + 8, 0, 0, 0]) == (TS_OK, 0)
+    # inputs may overlap each other (read-only)
+    assert check_map(shim, 1, 0, x, [B + 8, 100, 0, 0], d) == (TS_OK, 100)
+
+
+def test_align_class(shim):
+    assert shim.shim_align_class(256, 1, 512, 1024) == 0
+    assert shim.shim_align_class(264, 1, 520, 1032) == 1
+    assert shim.shim_align_class(264, 0, 0, 1032) == 1
+    assert shim.shim_align_class(264, 1, 512, 1032) == 2
+    assert shim.shim_align_class(256, 1, 512, 1028) == 2
+
+
+@pytest.mark.parametrize("es,vb", [(8, 16), (8, 8), (4, 16), (4, 8), (4, 4), (2, 16), (2, 8), (2, 2)])
+def test_plan_plain_partitions_the_range(shim, es, vb):
+    rng = np.random.default_rng(es * 100 + vb)
+    out = _u64([0, 0, 0])
+    for _ in range(300):
+        count = int(rng.integers(0, 200))
+        mis = int(rng.integers(0, 16 // es)) * es
+        base = 1 << 16
+        ok = shim.shim_plan_plain(base + mis, 1, 2 * base + mis, 3 * base + mis, count, es, vb, out)
+        assert ok == 1
+        head, nvec, tail = out[0], out[1], out[2]
+        assert head + nvec * (vb // es) + tail == count
+        if nvec:
+            assert (3 * base + mis + head * es) % vb == 0   # body starts on a vector boundary
+        assert tail < vb // es and head < vb // es + (0 if head <= count else 1)
+    # different misalignments cannot share a vector body
+    if vb > es:
+        assert shim.shim_plan_plain(1 << 16, 1, (1 << 17) + es, 1 << 18, 100, es, vb, out) == 0
+
+
+def plan_batch(shim, descs, es, tile):
+    flat = [v for d in descs for v in d]
+    cap = 100000
+    tiles = (ctypes.c_uint64 * (3 * cap))()
+    meta = (ctypes.c_uint64 * (2 * max(1, len(descs))))()
+    nt, tot = ctypes.c_uint64(), ctypes.c_uint64()
+    st = shim.shim_plan_batch(_u64(flat or [0]), len(descs), es, tile, tiles, cap, meta, ctypes.byref(nt),
+                              ctypes.byref(tot))
+    if st != 0:
+        return st, None, None, None
+    t = np.frombuffer(tiles, np.uint64, 3 * nt.value).reshape(-1, 3)
+    m = np.frombuffer(meta, np.uint64, 2 * len(descs)).reshape(-1, 2)
+    return st, t, m, tot.value
+
+
+@pytest.mark.parametrize("es", [8, 4, 2])
+@pytest.mark.parametrize("tile", [8, 64, 1024])
+def test_plan_batch_covers_every_element_once(shim, es, tile):
+    rng = np.random.default_rng(es + tile)
+    descs = []
+    base = 1 << 30
+    for i in range(60):
+        n = int(rng.choice([0, 1, 2, 3, 7, 8, 9, int(rng.integers(10, 5000))]))
+        mis = [int(rng.integers(0, 16 // es)) * es for _ in range(3)]
+        if i % 3:
+            mis = [mis[0]] * 3
+        descs.append([base + mis[0], base + (1 << 24) + mis[1], base + (2 << 24) + mis[2], n])
+        base += 3 << 24
+    st, t, m, total = plan_batch(shim, descs, es, tile)
+    assert st == 0
+    assert total == sum(d[3] for d in descs)
+    for i, d in enumerate(descs):
+        mine = t[t[:, 0] == i]
+        n = d[3]
+        if n == 0:
+            assert mine.size == 0
+            continue
+        # consecutive, covering [0, n) exactly once
+        assert mine[0, 1] == 0 and mine[-1, 2] == n
+        assert np.all(mine[1:, 1] == mine[:-1, 2]) and np.all(mine[:, 2] > mine[:, 1])
+        head, vec_ok = int(m[i, 0]), int(m[i, 1])
+        shared = len({(x % 16) for x in d[:3]}) == 1
+        assert vec_ok == int(shared)
+        if vec_ok:
+            assert (d[2] + head * es) % 16 == 0 and head < 16 // es
+            # inner boundaries sit at head + k * tile
+            for s in mine[1:, 1]:
+                assert (int(s) - min(head, n)) % tile == 0
+        assert np.all(mine[:, 2] - mine[:, 1] <= tile + head)
+    # tiles of one instance are consecutive in the table, instances in order
+    assert np.all(np.diff(t[:, 0].astype(np.int64)) >= 0)
+
+
+def test_plan_batch_rejects_bad_input(shim):
+    assert plan_batch(shim, [[0, 0, 0, 5]], 8, 64)[0] == TS_E_INVALID           # NULL arrays
+    assert plan_batch(shim, [[1 << 20, 1 << 21, (1 << 22) + 4, 5]], 8, 64)[0] == TS_E_INVALID  # misaligned
+    assert plan_batch(shim, [[1 << 20, 1 << 21, 1 << 22, 5]], 8, 60)[0] == TS_E_INVALID        # tile % 8
+    assert plan_batch(shim, [[0, 0, 0, 0]], 8, 64)[0] == 0                      # empty instance is fine

@@ -1,0 +1,265 @@
+"""GPU parity: every map of the STREAM listing (Section 5, Listing 4) through
+the C ABI, compared element by element with the CPU oracle on the same
+seeded inputs -- bit-exact (0 ulp) in every storage format."""
+import numpy as np
+import pytest
+
+import oracle
+import tsgen
+from gpu_util import assert_same_bits, device_array, empty_array, say
+
+pytestmark = pytest.mark.gpu
+
+OPS = ("copy", "scale", "add", "triad")
+SIZES = [0, 1, 2, 3, 7, 8, 9, 15, 16, 17, 63, 64, 65, 1023, 4096 + 5, (1 << 20), (1 << 20) + 7]
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_2206_06302_amd as ts
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    stream = torch.cuda.Stream()
+    tgt = ts.Target(0, stream)
+    yield ts, torch, tgt
+    tgt.synchronize()
+    tgt.close()
+    torch.cuda.empty_cache()
+
+
+def _inputs(n, dtype, seed=7):
+    x = tsgen.uniform_array(seed, 0, n, dtype)
+    y = tsgen.uniform_array(seed, 1, n, dtype)
+    d0 = tsgen.uniform_array(seed, 2, n, dtype)
+    return x, y, d0
+
+
+def _oracle_op(dtype, op, x, y, d0, q):
+    ref = d0.copy()
+    oracle.op(oracle.DTYPES[dtype], oracle.OPS[op], x, y if op in ("add", "triad") else None, ref, q)
+    return ref
+
+
+def _run(ts, torch, tgt, op, dtype, x, y, d0, q, offs=(0, 0, 0)):
+    X = device_array(ts, torch, tgt, x, dtype, offs[0])
+    Y = device_array(ts, torch, tgt, y, dtype, offs[1])
+    Dd = device_array(ts, torch, tgt, d0, dtype, offs[2])
+    ts.run_op(tgt, op, X, Y, Dd, q)
+    return Dd.to_host()
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("offset", [0, 1, 3])
+def test_f64_ops_zero_ulp(env, op, n, offset):
+    ts, torch, tgt = env
+    say(f"[f64 {op}] n={n} offset={offset}")
+    x, y, d0 = _inputs(n, "f64", seed=11 + n % 5)
+    got = _run(ts, torch, tgt, op, "f64", x, y, d0, 3.0, (offset, offset, offset))
+    assert_same_bits(got, _oracle_op("f64", op, x, y, d0, 3.0), "f64", f"{op} n={n} off={offset}")
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("offs", [(0, 1, 0), (1, 0, 2), (0, 0, 1), (2, 3, 1)])
+def test_f64_mixed_misalignment(env, op, offs):
+    ts, torch, tgt = env
+    n = (1 << 16) + 13
+    say(f"[f64 {op} mixed] offs={offs}")
+    x, y, d0 = _inputs(n, "f64", seed=5)
+    got = _run(ts, torch, tgt, op, "f64", x, y, d0, 3.0, offs)
+    assert_same_bits(got, _oracle_op("f64", op, x, y, d0, 3.0), "f64", f"{op} offs={offs}")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("n,offset", [(1, 0), (7, 1), (17, 3), (1023, 0), ((1 << 20) + 7, 1), ((1 << 18), 0)])
+def test_reduced_ops_zero_ulp(env, dtype, op, n, offset):
+    ts, torch, tgt = env
+    say(f"[{dtype} {op}] n={n} offset={offset}")
+    x, y, d0 = _inputs(n, dtype, seed=21)
+    for q in (3.0, 0.1):
+        got = _run(ts, torch, tgt, op, dtype, x, y, d0, q, (offset, offset, offset))
+        assert_same_bits(got, _oracle_op(dtype, op, x, y, d0, q), dtype, f"{dtype} {op} n={n} q={q}")
+
+
+def _special_values(dtype):
+    v = [0.0, -0.0, 1.0, -1.0, 3.0, 0.5, 1e-5, -1e-5, 6e-8, -6e-8, 1e-40, -1e-40, 65504.0, -65504.0,
+         70000.0, 3.0e38, -3.0e38, 1.0e-30, np.inf, -np.inf, np.nan, 2.0 ** -24, 2.0 ** -25, 1.5 * 2.0 ** -24]
+    if dtype == "f64":
+        v += [5e-324, -5e-324, 1.7976931348623157e308, 2.2250738585072014e-308, 1e300, -1e300]
+    a = np.array(v, np.float64)
+    x = np.repeat(a, a.size)
+    y = np.tile(a, a.size)
+    return tsgen.narrow(x, dtype), tsgen.narrow(y, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+@pytest.mark.parametrize("op", OPS)
+def test_special_values(env, dtype, op):
+    """Signed zeros, subnormals, overflow to infinity, infinities and NaN,
+    every pair, through the vector body and the element-wise paths."""
+    ts, torch, tgt = env
+    say(f"[special {dtype} {op}]")
+    x, y = _special_values(dtype)
+    d0 = np.zeros_like(x)
+    for q in (3.0, -0.0, 1e-30, 1e30):
+        for offs in ((0, 0, 0), (1, 1, 1), (0, 1, 2)):
+            got = _run(ts, torch, tgt, op, dtype, x, y, d0, q, offs)
+            assert_same_bits(got, _oracle_op(dtype, op, x, y, d0, q), dtype, f"special {dtype} {op} q={q} offs={offs}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+def test_in_place(env, dtype):
+    """dst identical to an input is allowed (in place)."""
+    ts, torch, tgt = env
+    n = 100003
+    x, y, _ = _inputs(n, dtype, seed=3)
+    X = device_array(ts, torch, tgt, x, dtype, 1)
+    Y = device_array(ts, torch, tgt, y, dtype, 1)
+    say(f"[in place {dtype}]")
+    ts.triad(tgt, X, Y, X, 3.0)  # x = x + 3*y
+    ref = x.copy()
+    oracle.op(oracle.DTYPES[dtype], oracle.TRIAD, x.copy(), y, ref, 3.0)
+    assert_same_bits(X.to_host(), ref, dtype, "in-place triad")
+    ts.scale(tgt, Y, Y, 0.5)
+    ref2 = y.copy()
+    oracle.op(oracle.DTYPES[dtype], oracle.SCALE, y.copy(), None, ref2, 0.5)
+    assert_same_bits(Y.to_host(), ref2, dtype, "in-place scale")
+
+
+def test_closed_form_c1(env):
+    """N = 2^20 doubles from (1, 2, 0), q = 3, ten iterations of Listing 4:
+    every element must equal 15^10, 3*15^9, 4*15^9 exactly."""
+    ts, torch, tgt = env
+    n = 1 << 20
+    A, B, C = (empty_array(ts, torch, tgt, n, "f64") for _ in range(3))
+    A.fill(1.0), B.fill(2.0), C.fill(0.0)
+    say("[closed form N=2^20 K=10]")
+    for _ in range(10):
+        ts.stream_iteration(tgt, A, B, C, 3.0)
+    for arr, exp in ((A, 576650390625.0), (B, 115330078125.0), (C, 153773437500.0)):
+        cs = ts.checksum(tgt, arr, exp)
+        assert cs["mismatches"] == 0 and cs["max_abs_dev"] == 0.0
+        assert cs["sum"] == exp * n  # exact: exp * 2^20 is representable, partial sums exact
+    a = np.full(n, 1.0)
+    b = np.full(n, 2.0)
+    c = np.zeros(n)
+    oracle.stream_run(oracle.F64, a, b, c, 3.0, 10)
+    assert_same_bits(A.to_host(), a, "f64", "a")
+    assert_same_bits(B.to_host(), b, "f64", "b")
+    assert_same_bits(C.to_host(), c, "f64", "c")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+def test_iterated_chain_matches_oracle(env, dtype):
+    """Random init, 21 iterations in listing order, full-array comparison."""
+    ts, torch, tgt = env
+    n = (1 << 18) + 3
+    a, b, c = _inputs(n, dtype, seed=2)
+    A = device_array(ts, torch, tgt, a, dtype)
+    B = device_array(ts, torch, tgt, b, dtype)
+    C = device_array(ts, torch, tgt, c, dtype)
+    say(f"[chain {dtype} K=21]")
+    for _ in range(21):
+        ts.stream_iteration(tgt, A, B, C, 3.0)
+    oracle.stream_run(oracle.DTYPES[dtype], a, b, c, 3.0, 21)
+    assert_same_bits(A.to_host(), a, dtype, "a")
+    assert_same_bits(B.to_host(), b, dtype, "b")
+    assert_same_bits(C.to_host(), c, dtype, "c")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+@pytest.mark.parametrize("first", [0, 12345])
+def test_fill_uniform_matches_generator(env, dtype, first):
+    """Device bulk construction draws the same values as the host generator."""
+    ts, torch, tgt = env
+    n = (1 << 16) + 5
+    A = empty_array(ts, torch, tgt, n, dtype, offset=1)
+    say(f"[fill_uniform {dtype} first={first}]")
+    A.fill_uniform(9, 2, first)
+    ref = tsgen.uniform_array(9, 2, n, dtype, start=first)
+    assert_same_bits(A.to_host(), ref, dtype, "fill_uniform")
+    A.fill(0.1)
+    assert_same_bits(A.to_host(), tsgen.narrow(np.full(n, 0.1), dtype), dtype, "fill")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+def test_checksum_against_oracle(env, dtype):
+    ts, torch, tgt = env
+    n = (1 << 20) + 11
+    x = tsgen.uniform_array(4, 0, n, dtype)
+    expected = float(oracle.widen_f64(oracle.DTYPES[dtype], x[100:101])[0])
+    X = device_array(ts, torch, tgt, x, dtype)
+    say(f"[checksum {dtype}]")
+    cs = ts.checksum(tgt, X, expected)
+    ref = oracle.checksum(oracle.DTYPES[dtype], x, expected)
+    w = oracle.widen_f64(oracle.DTYPES[dtype], x)
+    bound = n * 2.0 ** -53 * float(np.abs(w).sum())
+    assert abs(cs["sum"] - ref.sum) <= 2 * bound
+    dev = np.abs(w - expected)
+    assert abs(cs["abs_dev_sum"] - ref.abs_dev_sum) <= 2 * n * 2.0 ** -53 * float(dev.sum())
+    assert cs["max_abs_dev"] == ref.max_abs_dev
+    assert cs["mismatches"] == ref.mismatches
+    # reproducible: the reduction tree depends only on n
+    assert ts.checksum(tgt, X, expected) == cs
+
+
+def test_mismatch_count(env):
+    ts, torch, tgt = env
+    n = 300001
+    x = tsgen.uniform_array(8, 0, n)
+    r = x.copy()
+    idx = np.array([0, 5, 77777, n - 1])
+    r[idx] = np.nextafter(r[idx], 2.0)
+    X = device_array(ts, torch, tgt, x, "f64")
+    R = device_array(ts, torch, tgt, r, "f64", 1)
+    assert ts.mismatch_count(tgt, X, R) == 4
+    assert ts.mismatch_count(tgt, X, X) == 0
+
+
+def test_time_op_and_events(env):
+    ts, torch, tgt = env
+    n = 1 << 20
+    A, B, C = (empty_array(ts, torch, tgt, n, "f64") for _ in range(3))
+    A.fill(1.0), B.fill(2.0), C.fill(0.0)
+    ms = ts.time_op(tgt, "triad", B, C, A, 3.0, reps=5)
+    assert ms > 0
+    e0, e1 = ts.Event(), ts.Event()
+    e0.record(tgt)
+    ts.copy(tgt, A, C)
+    e1.record(tgt)
+    e1.synchronize()
+    assert e1.query() and e0.elapsed_ms(e1) >= 0
+    done = []
+    ts.scale(tgt, C, B, 3.0)
+    tgt.then(lambda: done.append(1))
+    tgt.synchronize()
+    import time
+    for _ in range(100):
+        if done:
+            break
+        time.sleep(0.01)
+    assert done == [1]
+
+
+def test_plain_graph_matches_eager(env):
+    """A captured iteration replayed K times equals K eager iterations."""
+    ts, torch, tgt = env
+    n = (1 << 20) + 3
+    a, b, c = _inputs(n, "f64", seed=13)
+    A1, B1, C1 = (device_array(ts, torch, tgt, v, "f64") for v in (a, b, c))
+    A2, B2, C2 = (device_array(ts, torch, tgt, v, "f64", 1) for v in (a, b, c))
+    say("[plain graph]")
+    g = ts.Graph.capture_arrays_iteration(tgt, A1, B1, C1, 3.0)
+    for rep in range(3):
+        g.launch(tgt, 2)
+        for _ in range(2):
+            ts.stream_iteration(tgt, A2, B2, C2, 3.0)
+        tgt.synchronize()
+        for X, Y, nm in ((A1, A2, "a"), (B1, B2, "b"), (C1, C2, "c")):
+            assert ts.mismatch_count(tgt, X, Y) == 0, (rep, nm)
+    g.close()
+    oracle.stream_run(oracle.F64, a, b, c, 3.0, 6)
+    assert_same_bits(A1.to_host(), a, "f64", "a after graph")
