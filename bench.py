@@ -1,0 +1,317 @@
+#!/usr/bin/env python3
+"""STREAM benchmark on one MI355X through libtstream (one JSON line on stdout).
+
+Workload (the headline): three binary64 arrays of N = 2^27 elements (1 GiB
+each) placed on the GPU by the library's allocator, initialised on the device
+to a = 1, b = 2, c = 0, scalar q = 3.  One step = one iteration of the
+generic STREAM benchmark (Section 5, Listing 4 of the paper): copy c = a,
+scale b = q*c, add c = a + b, triad a = b + q*c, four launches in that order.
+W untimed warm-up steps, then exactly K timed steps bracketed by device
+synchronisation.  Every launch is bracketed by events on the target's stream,
+giving per-kernel best/average times; bytes follow the STREAM convention
+(copy and scale move 2 arrays, add and triad 3; GB = 1e9 B).
+
+After timing, the arrays are validated on the GPU against the oracle's
+scalar recurrence (every element of a, b, c must match bit for bit).
+
+Extra legs (skipped with --quick): the batched ragged form (4096 instances,
+log-uniform lengths in [1e3, 1e7), one persistent launch per map, the
+iteration captured as a HIP graph and replayed) against per-instance plain
+launches; and reduced-precision storage (binary32, bfloat16, binary16) at
+N = 2^28 per array.  The CPU-baseline leg times the oracle on host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "STREAM Triad/Copy GB/s and % of HBM peak, FP64 N=2^27; batched vs plain"
+PEAK_GBPS = 8000.0
+OPS = ("copy", "scale", "add", "triad")
+PROFILE_PMC = os.path.join(ROOT, "profiles", "triad_f64_n2p27_pmc.md")
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for rel in ("paper_2206_06302_amd/csrc/ts_device.hpp", "paper_2206_06302_amd/csrc/kern_f64.hip",
+                "paper_2206_06302_amd/tune/gfx950.json"):
+        p = os.path.join(ROOT, rel)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per triad launch from the committed rocprofv3 counter runs,
+    or None when absent or taken on other kernel sources."""
+    if not os.path.exists(PROFILE_PMC):
+        return None
+    text = open(PROFILE_PMC).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    d = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", text)
+    if not m or not d or d.group(1) != kernel_source_digest():
+        return None
+    return float(m.group(1))
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main_leg(ts, torch, tgt, n, steps, warmup):
+    """Headline: FP64 STREAM at n elements; returns the result dict."""
+    A, B, C = (ts.Array.alloc(tgt, "f64", n) for _ in range(3))
+    A.fill(1.0), B.fill(2.0), C.fill(0.0)
+    tgt.synchronize()
+    roles = {"copy": (A, None, C), "scale": (C, None, B), "add": (A, B, C), "triad": (B, C, A)}
+    ev = [[ts.Event() for _ in range(5)] for _ in range(steps)]
+    for _ in range(warmup):
+        ts.stream_iteration(tgt, A, B, C, 3.0)
+    tgt.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        e = ev[s]
+        e[0].record(tgt)
+        for k, op in enumerate(OPS):
+            x, y, d = roles[op]
+            ts.run_op(tgt, op, x, y, d, 3.0)
+            e[k + 1].record(tgt)
+    tgt.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = {op: [ev[s][k].elapsed_ms(ev[s][k + 1]) for s in range(steps)] for k, op in enumerate(OPS)}
+    step_ms = [ev[s][0].elapsed_ms(ev[s][4]) for s in range(steps)]
+    # validation against the oracle's scalar recurrence (all elements equal)
+    import oracle
+    exp = oracle.stream_scalar_f64(1.0, 2.0, 0.0, 3.0, warmup + steps)
+    valid = all(ts.checksum(tgt, arr, e)["mismatches"] == 0 for arr, e in zip((A, B, C), exp))
+    kernels = {}
+    for op in OPS:
+        b = ts.stream_bytes(op, n)
+        best, avg = min(per[op]), sum(per[op]) / len(per[op])
+        kernels[op] = {"bytes": b, "best_ms": round(best, 5), "avg_ms": round(avg, 5),
+                       "best_GBps": round(b / best / 1e6, 1), "avg_GBps": round(b / avg / 1e6, 1),
+                       "pct_peak_best": round(100 * b / best / 1e6 / PEAK_GBPS, 2),
+                       "pct_peak_avg": round(100 * b / avg / 1e6 / PEAK_GBPS, 2),
+                       "cfg": ts.get_kernel_cfg(op, "f64", n)}
+    for arr in (A, B, C):
+        arr.free()
+    return {"wall_s": wall, "step_ms": step_ms, "kernels": kernels, "valid": valid}
+
+
+def batched_leg(ts, torch, tgt, count=4096, seed=5, replays=50, triad_reps=20):
+    """Batched ragged triad and the graph-captured iteration vs plain launches."""
+    import tsgen
+    lens = tsgen.batched_lengths(seed, count)
+    qs = tsgen.batched_scalars(seed, count)
+    es = 8
+    offs, pos = [], 0
+    for n in lens:
+        start = (pos + 31) // 32 * 32  # every instance starts on a 256-byte boundary
+        offs.append(start)
+        pos = start + int(n)
+    pools = [torch.empty(pos + 32, dtype=torch.float64, device="cuda") for _ in range(3)]
+    torch.cuda.synchronize()
+    descs = [(pools[0].data_ptr() + o * es, pools[1].data_ptr() + o * es, pools[2].data_ptr() + o * es, int(n), float(q))
+             for o, n, q in zip(offs, lens, qs)]
+    batch = ts.Batch(tgt, "f64", descs)
+    total = int(sum(int(n) for n in lens))
+    batch.fill(tgt, 0, 1.0), batch.fill(tgt, 1, 2.0), batch.fill(tgt, 2, 0.0)
+    tgt.synchronize()
+    g = ts.Graph.capture_stream_iteration(tgt, batch)
+    e0, e1 = ts.Event(), ts.Event()
+    g.launch(tgt, 1)  # warm-up
+    e0.record(tgt)
+    g.launch(tgt, replays - 1)
+    e1.record(tgt)
+    e1.synchronize()
+    graph_ms = e0.elapsed_ms(e1) / (replays - 1)
+    # per-instance closed recurrence after `replays` iterations
+    import oracle
+    exp = [oracle.stream_scalar_f64(1.0, 2.0, 0.0, float(q), replays) for q in qs]
+    valid = all(int(batch.mismatch_count(tgt, k, [e[k] for e in exp]).sum()) == 0 for k in range(3))
+    # triad alone: one persistent launch over all instances
+    t_ms = []
+    for _ in range(triad_reps):
+        e0.record(tgt)
+        batch.op(tgt, "triad")
+        e1.record(tgt)
+        e1.synchronize()
+        t_ms.append(e0.elapsed_ms(e1))
+    # comparison: one plain launch per instance
+    p_ms = []
+    for _ in range(5):
+        e0.record(tgt)
+        batch.op_plain(tgt, "triad")
+        e1.record(tgt)
+        e1.synchronize()
+        p_ms.append(e0.elapsed_ms(e1))
+    tb = 3 * total * es
+    info = batch.info()
+    out = {
+        "instances": count, "total_elems": total, "device_bytes": 3 * total * es, "tiles": info["tiles"],
+        "tile_elems": info["tile_elems"], "valid_after_graph_replays": valid, "graph_replays": replays,
+        "graph_iteration_ms": round(graph_ms, 4),
+        "graph_iteration_GBps": round(10 * total * es / graph_ms / 1e6, 1),  # 2+2+3+3 arrays per element
+        "triad_best_GBps": round(tb / min(t_ms) / 1e6, 1), "triad_avg_GBps": round(tb / (sum(t_ms) / len(t_ms)) / 1e6, 1),
+        "plain_per_instance_triad_best_GBps": round(tb / min(p_ms) / 1e6, 1),
+        "cfg": ts.get_kernel_cfg("triad", "f64", total, batched=True),
+    }
+    g.close()
+    batch.close()
+    del pools
+    torch.cuda.empty_cache()
+    return out
+
+
+def reduced_leg(ts, torch, tgt, n=1 << 28, reps=10):
+    out = {}
+    for dtype in ("f64", "f32", "bf16", "f16"):
+        A, B, C = (ts.Array.alloc(tgt, dtype, n) for _ in range(3))
+        A.fill_uniform(4, 0), B.fill_uniform(4, 1), C.fill_uniform(4, 2)
+        roles = {"copy": (A, None, C), "scale": (C, None, B), "add": (A, B, C), "triad": (B, C, A)}
+        res = {}
+        for op in OPS:
+            x, y, d = roles[op]
+            ts.time_op(tgt, op, x, y, d, 3.0, reps=2)
+            ms = ts.time_op(tgt, op, x, y, d, 3.0, reps=reps) / reps
+            b = ts.stream_bytes(op, n, dtype)
+            res[op] = {"GBps": round(b / ms / 1e6, 1), "Gelem_per_s": round(n / ms / 1e6, 2)}
+        out[dtype] = res
+        for arr in (A, B, C):
+            arr.free()
+    for dtype in ("f32", "bf16", "f16"):
+        for op in OPS:
+            out[dtype][op]["elem_rate_vs_f64"] = round(out[dtype][op]["Gelem_per_s"] / out["f64"][op]["Gelem_per_s"], 2)
+    out["n"] = n
+    return out
+
+
+def cpu_baseline_leg(n, target_seconds=12.0):
+    """The oracle's timed mode on the host (pinned threads, first touch)."""
+    import oracle
+    try:
+        cpus = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cpus = os.cpu_count() or 1
+    threads = max(1, min(16, cpus))
+    t0 = time.perf_counter()
+    secs, _ = oracle.stream_timed_f64(n, 1, threads)
+    one = float(secs.sum())
+    iters = int(max(2, min(40, target_seconds / max(one, 1e-3))))
+    secs, fin = oracle.stream_timed_f64(n, iters, threads)
+    spent = time.perf_counter() - t0
+    exp = oracle.stream_scalar_f64(1.0, 2.0, 0.0, 3.0, iters)
+    ok = tuple(fin[:3]) == exp
+    per_iter = secs.sum(axis=1)  # seconds per iteration (4 maps)
+    agg = 80 * n / per_iter.mean() / 1e9
+    best = {op: round(ts_bytes / secs[:, k].min() / 1e9, 2)
+            for k, (op, ts_bytes) in enumerate(zip(OPS, (16 * n, 16 * n, 24 * n, 24 * n)))}
+    return {"value": round(agg, 2), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"N=2^{n.bit_length()-1} f64 x3 arrays, {iters} iterations of copy/scale/add/triad, "
+                      f"{threads} pinned threads, first-touch blocks; {spent:.1f} s wall",
+            "best_GBps_per_kernel": best, "valid": bool(ok)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1 << 27)
+    ap.add_argument("--quick", action="store_true", help="headline leg only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--autotune", action="store_true", help="re-tune the four maps before timing")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(STREAM shards with no exchange; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+    if a.steps < 1 or a.warmup < 0:
+        sys.exit("--steps must be >= 1 and --warmup >= 0")
+
+    import torch
+
+    import paper_2206_06302_amd as ts
+
+    stream = torch.cuda.Stream()
+    tgt = ts.Target(0, stream)
+    info = tgt.info()
+    log(f"device: {info['arch']} CUs={info['compute_units']} HBM={info['hbm_bytes']/2**30:.0f} GiB")
+    if a.autotune:
+        for op in OPS:
+            cfg, bps = ts.autotune(tgt, op, "f64", a.n)
+            log(f"autotune {op}: {bps/1e9:.1f} GB/s {cfg}")
+
+    log(f"main leg: f64 N={a.n}, warmup={a.warmup}, steps={a.steps}")
+    m = main_leg(ts, torch, tgt, a.n, a.steps, a.warmup)
+    if not m["valid"]:
+        print("validation failed: results differ from the oracle's recurrence", file=sys.stderr)
+        sys.exit(1)
+    k = m["kernels"]
+    step_bytes = sum(k[op]["bytes"] for op in OPS)
+    ms_per_step = sum(m["step_ms"]) / len(m["step_ms"])
+    value = step_bytes / ms_per_step / 1e6
+    traffic = committed_traffic()
+    tri = k["triad"]
+    achieved = tri["bytes"] / tri["avg_ms"] / 1e6
+    result = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "stream_f64_n2^27", "n": a.n, "arrays": 3, "q": 3.0,
+                   "init": "a=1,b=2,c=0 (device fill)", "order": "copy,scale,add,triad",
+                   "bytes_per_step": step_bytes},
+        "triad_best_GBps": tri["best_GBps"],
+        "triad_pct_peak_best": tri["pct_peak_best"],
+        "copy_best_GBps": k["copy"]["best_GBps"],
+        "copy_pct_peak_best": k["copy"]["pct_peak_best"],
+        "per_kernel": k,
+        "host_wall_ms_per_step": round(1e3 * m["wall_s"] / a.steps, 5),
+        "validated": "all elements of a, b, c equal the oracle's recurrence bit for bit",
+        "roofline": {"bound": "hbm", "kernel": "triad f64", "achieved": round(achieved, 1), "peak": PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_GBPS, 4),
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": tri["bytes"]},
+        "kernel_source_digest": kernel_source_digest(),
+        "device": {"arch": info["arch"], "compute_units": info["compute_units"], "hbm_bytes": info["hbm_bytes"]},
+    }
+    if not a.quick:
+        for name, fn in (("batched", lambda: batched_leg(ts, torch, tgt)),
+                         ("reduced_precision", lambda: reduced_leg(ts, torch, tgt))):
+            log(f"{name} leg")
+            try:
+                result[name] = fn()
+            except Exception as e:  # an extra leg must not hide the headline
+                result[name] = {"error": f"{type(e).__name__}: {e}"}
+        if "triad_best_GBps" in result.get("batched", {}):
+            result["batched"]["triad_vs_plain_n2p27_triad"] = round(
+                result["batched"]["triad_best_GBps"] / tri["best_GBps"], 3)
+    if not a.no_cpu:
+        log("cpu baseline leg (oracle)")
+        result["cpu_baseline"] = cpu_baseline_leg(a.n)
+    tgt.close()
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -331,10 +331,13 @@ uint32_t aux_grid(const ts_target_s* t, uint64_t ntiles) {
   return static_cast<uint32_t>(g < 1 ? 1 : g);
 }
 
-// Median of event-timed single launches, in seconds.
+// Seconds per launch of one candidate: `inner` back-to-back launches between
+// two events (so small, launch-bound sizes are timed as throughput), repeated
+// `reps` times after a warm-up; the median of the repetitions is returned.
 template <class Launch>
-int time_median(ts_target_s* t, int reps, Launch&& launch, double* seconds) {
+int time_candidate(ts_target_s* t, int reps, int inner, Launch&& launch, double* seconds) {
   if (reps < 1) reps = 1;
+  if (inner < 1) inner = 1;
   std::vector<hipEvent_t> ev(2 * static_cast<size_t>(reps), nullptr);
   int st = TS_OK;
   for (auto& e : ev) {
@@ -351,7 +354,7 @@ int time_median(ts_target_s* t, int reps, Launch&& launch, double* seconds) {
       st = hip_fail(he, "hipEventRecord");
       break;
     }
-    st = launch();
+    for (int i = 0; i < inner && st == TS_OK; ++i) st = launch();
     if (st != TS_OK) break;
     he = hipEventRecord(ev[2 * r + 1], t->stream);
     if (he != hipSuccess) st = hip_fail(he, "hipEventRecord");
@@ -371,8 +374,15 @@ int time_median(ts_target_s* t, int reps, Launch&& launch, double* seconds) {
     if (e) (void)hipEventDestroy(e);
   if (st != TS_OK) return st;
   std::sort(ms.begin(), ms.end());
-  *seconds = 1e-3 * ms[ms.size() / 2];
+  *seconds = 1e-3 * ms[ms.size() / 2] / inner;
   return TS_OK;
+}
+
+// Launches per timed repetition: about a millisecond of work at ~6 TB/s.
+int inner_launches(uint64_t bytes) {
+  const double est = static_cast<double>(bytes) / 6.0e12 + 5e-6;
+  const double r = 1e-3 / est;
+  return r < 1 ? 1 : (r > 200 ? 200 : static_cast<int>(r));
 }
 
 }  // namespace
@@ -795,8 +805,8 @@ int ts_autotune(ts_target t, ts_op op, ts_dtype dtype, size_t n, size_t offset_e
   for (const ts_kernel_cfg& c : candidates(0)) {
     if (st != TS_OK) break;
     double s = 0;
-    st = time_median(t, reps,
-                     [&]() { return launch_map(t, op, dtype, p[0], p[1], p[2], n, 3.0, c); }, &s);
+    st = time_candidate(t, reps, inner_launches(bytes),
+                        [&]() { return launch_map(t, op, dtype, p[0], p[1], p[2], n, 3.0, c); }, &s);
     if (st == TS_OK && s > 0 && (best_s == 0 || s < best_s)) {
       best_s = s;
       best_cfg = c;
@@ -826,7 +836,7 @@ int ts_autotune_batch(ts_target t, ts_batch b, ts_op op, int reps, ts_kernel_cfg
   for (const ts_kernel_cfg& c : candidates(1)) {
     if (c.tile_elems != b->tile_elems && (st = batch_replan(b, c.tile_elems)) != TS_OK) break;
     double s = 0;
-    st = time_median(t, reps, [&]() { return launch_batch(t, b, op, c); }, &s);
+    st = time_candidate(t, reps, 1, [&]() { return launch_batch(t, b, op, c); }, &s);
     if (st != TS_OK) break;
     if (s > 0 && (best_s == 0 || s < best_s)) {
       best_s = s;

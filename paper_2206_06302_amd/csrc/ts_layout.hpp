@@ -110,20 +110,28 @@ inline int align_class(uintptr_t x, const uintptr_t* y, uintptr_t d) {
   return m == 0 ? 0 : 1;
 }
 
-// Split [0, count) of a plain launch into an element-wise head (until every
-// operand sits on a vb-byte boundary), a body of whole vb-byte vectors and
-// an element-wise tail.  Returns false when the operands' misalignments
-// differ modulo vb, in which case only vb == element size can be used.
+// Split [0, count) of a plain launch into an element-wise head, a body of
+// whole vb-byte vectors and an element-wise tail.  When every operand has the
+// same misalignment modulo a 128-byte cache line, the head runs up to a line
+// boundary, so each wave's 1 KiB accesses cover whole lines; otherwise only
+// up to a vb boundary.  Returns false when the misalignments differ modulo
+// vb, in which case only vb == element size can be used.
 struct PlainPlan {
   uint64_t head, nvec, tail;
 };
+
+constexpr uintptr_t kLineBytes = 128;
 
 inline bool plan_plain(uintptr_t x, const uintptr_t* y, uintptr_t d, uint64_t count, size_t es,
                        size_t vb, PlainPlan& out) {
   const uintptr_t m = d % vb;
   if (x % vb != m || (y && *y % vb != m)) return false;
+  const uintptr_t ml = d % kLineBytes;
+  const bool line = x % kLineBytes == ml && (!y || *y % kLineBytes == ml);
+  const uintptr_t unit = line ? kLineBytes : vb;
+  const uintptr_t mu = d % unit;
   const uint64_t v = vb / es;
-  uint64_t head = m == 0 ? 0 : (vb - m) / es;
+  uint64_t head = mu == 0 ? 0 : (unit - mu) / es;
   if (head > count) head = count;
   const uint64_t rest = count - head;
   out.head = head;

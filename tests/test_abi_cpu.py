@@ -247,8 +247,13 @@ def test_plan_plain_partitions_the_range(shim, es, vb):
         head, nvec, tail = out[0], out[1], out[2]
         assert head + nvec * (vb // es) + tail == count
         if nvec:
-            assert (3 * base + mis + head * es) % vb == 0   # body starts on a vector boundary
-        assert tail < vb // es and head < vb // es + (0 if head <= count else 1)
+            # all three share the misalignment: the body starts on a 128-byte line
+            assert (3 * base + mis + head * es) % 128 == 0
+        assert tail < vb // es and head < 128 // es
+    # shared misalignment modulo vb but not modulo 128: peel only to vb
+    if vb > es:
+        assert shim.shim_plan_plain(1 << 16, 1, (1 << 17) + 16, 1 << 18, 1000, es, vb, out) == 1
+        assert out[0] == 0 and out[1] == 1000 // (vb // es)
     # different misalignments cannot share a vector body
     if vb > es:
         assert shim.shim_plan_plain(1 << 16, 1, (1 << 17) + es, 1 << 18, 100, es, vb, out) == 0
