@@ -17,8 +17,10 @@ scalar recurrence (every element of a, b, c must match bit for bit).
 Extra legs (skipped with --quick): the batched ragged form (4096 instances,
 log-uniform lengths in [1e3, 1e7), one persistent launch per map, the
 iteration captured as a HIP graph and replayed) against per-instance plain
-launches; and reduced-precision storage (binary32, bfloat16, binary16) at
-N = 2^28 per array.  The CPU-baseline leg times the oracle on host cores.
+launches; reduced-precision storage (binary32, bfloat16, binary16) at
+N = 2^28 per array; and a size/alignment sweep from 2^16 to 2^29 elements
+(L2, Infinity Cache and HBM regimes).  The CPU-baseline leg times the oracle
+on host cores.
 """
 from __future__ import annotations
 
@@ -197,6 +199,38 @@ def reduced_leg(ts, torch, tgt, n=1 << 28, reps=10):
     return out
 
 
+def sweep_leg(ts, tgt, lo=16, hi=29):
+    """Size and alignment sweep: GB/s of back-to-back launches (about 2 ms of
+    work per measurement, so launch-bound sizes report throughput) for f64
+    and f32 arrays of 2^p elements, aligned and as 2^p + 7 elements one
+    element past an aligned base.  Regime by working set (3 arrays): L2
+    (<= 32 MiB over 8 XCDs), MALL (<= 256 MiB Infinity Cache), else HBM."""
+    out = {}
+    for dtype in ("f64", "f32"):
+        es = ts.ELEM_SIZE[dtype]
+        for label, extra, off in (("aligned", 0, 0), ("offset1_plus7", 7, 1)):
+            rows = {}
+            for p in range(lo, hi + 1):
+                n = (1 << p) + extra
+                A, B, C = (ts.Array.alloc(tgt, dtype, n, off) for _ in range(3))
+                for k, arr in enumerate((A, B, C)):
+                    arr.fill_uniform(3, k)
+                ws = 3 * n * es
+                row = {"working_set_MiB": round(ws / 2 ** 20, 2),
+                       "regime": "L2" if ws <= 32 << 20 else ("MALL" if ws <= 256 << 20 else "HBM")}
+                for op, (x, y, d) in (("copy", (A, None, C)), ("triad", (B, C, A))):
+                    b = ts.stream_bytes(op, n, dtype)
+                    reps = int(max(3, min(400, 2e-3 / (b / 6e12 + 4e-6))))
+                    ts.time_op(tgt, op, x, y, d, 3.0, reps=2)
+                    ms = ts.time_op(tgt, op, x, y, d, 3.0, reps=reps) / reps
+                    row[op + "_GBps"] = round(b / ms / 1e6, 1)
+                rows[f"2^{p}"] = row
+                for arr in (A, B, C):
+                    arr.free()
+            out[f"{dtype}_{label}"] = rows
+    return out
+
+
 def cpu_baseline_leg(n, target_seconds=12.0):
     """The oracle's timed mode on the host (pinned threads, first touch)."""
     import oracle
@@ -297,7 +331,8 @@ def main():
     }
     if not a.quick:
         for name, fn in (("batched", lambda: batched_leg(ts, torch, tgt)),
-                         ("reduced_precision", lambda: reduced_leg(ts, torch, tgt))):
+                         ("reduced_precision", lambda: reduced_leg(ts, torch, tgt)),
+                         ("sweep", lambda: sweep_leg(ts, tgt))):
             log(f"{name} leg")
             try:
                 result[name] = fn()

@@ -79,6 +79,7 @@ typedef struct ts_array_s *ts_array;
 typedef struct ts_batch_s *ts_batch;
 typedef struct ts_graph_s *ts_graph;
 typedef struct ts_event_s *ts_event;
+typedef struct ts_future_s *ts_future;
 
 /* ------------------------------------------------------------------------ */
 /* Errors and version                                                        */
@@ -108,12 +109,15 @@ typedef struct {
     char name[128];
 } ts_device_info;
 
-/* Create a target on `device`.  `hip_stream` is a hipStream_t of that device
- * (e.g. torch.cuda.Stream().cuda_stream); the target borrows it.  NULL asks
- * the library to create (and later destroy) a non-blocking stream.
- * Errors: TS_E_INVALID (out NULL, device out of range), TS_E_DEVICE (no
- * usable GPU / HIP failure), TS_E_OOM. */
+/* Create a target on `device` ordered on `hip_stream`, a hipStream_t of that
+ * device (e.g. torch.cuda.Stream().cuda_stream) which the target borrows.
+ * NULL is the device's default stream, as in HIP (graph capture is not
+ * available on it).  Errors: TS_E_INVALID (out NULL, device out of range),
+ * TS_E_DEVICE (no usable GPU / HIP failure), TS_E_OOM. */
 TS_API int ts_target_create(int device, void *hip_stream, ts_target *out);
+/* Same, on a non-blocking stream the library creates and destroys with the
+ * target. */
+TS_API int ts_target_create_owned(int device, ts_target *out);
 TS_API int ts_target_destroy(ts_target target);
 /* Block until all work enqueued on the target's stream has finished. */
 TS_API int ts_target_synchronize(ts_target target);
@@ -369,6 +373,24 @@ TS_API int ts_event_synchronize(ts_event event);
 /* TS_OK (0) if the recorded work has finished, 1 if it is still pending. */
 TS_API int ts_event_query(ts_event event);
 TS_API int ts_event_elapsed_ms(ts_event start, ts_event end, float *ms);
+
+/* ------------------------------------------------------------------------ */
+/* Futures: host-side completion of asynchronous work (Listing 2)            */
+/* ------------------------------------------------------------------------ */
+/* The paper's asynchronous executor functions (async_execute,
+ * bulk_async_execute, Listing 2) return futures; its GPU executor makes them
+ * ready from a callback attached to the stream (Section 4.2).  Here every
+ * algorithm call is already asynchronous on the target's stream, and
+ * ts_target_async returns the future of all work enqueued so far: a host
+ * callback on the stream marks it ready.  Waiting does not synchronise the
+ * device; it blocks the calling thread until the callback has run. */
+TS_API int ts_target_async(ts_target target, ts_future *out);
+/* Block until the future is ready. */
+TS_API int ts_future_wait(ts_future future);
+/* 1 if ready, 0 if still pending (never blocks). */
+TS_API int ts_future_ready(ts_future future);
+/* Release the future; waits for its callback first if it is still pending. */
+TS_API int ts_future_destroy(ts_future future);
 
 #ifdef __cplusplus
 }

@@ -89,23 +89,26 @@ def version() -> tuple[int, int]:
 class Target:
     """A device plus the stream its work is ordered on.
 
-    ``stream`` may be a torch stream, a raw hipStream_t (int), ``None`` for
-    torch's current stream of the device, or ``"own"`` for a stream the
-    library creates (non-blocking)."""
+    ``stream`` may be a torch stream, a raw hipStream_t (int; 0 is the
+    device's default stream), ``None`` for torch's current stream of the
+    device, or ``"own"`` for a non-blocking stream the library creates."""
 
     def __init__(self, device: int = 0, stream=None):
         self._torch_stream = None
-        if stream is None:
-            stream = torch.cuda.current_stream(device)
-        if isinstance(stream, str) and stream == "own":
-            raw = None
-        elif isinstance(stream, torch.cuda.Stream):
-            self._torch_stream = stream
-            raw = stream.cuda_stream
-        else:
-            raw = int(stream)
         h = ctypes.c_void_p()
-        _check(lib.ts_target_create(int(device), ctypes.c_void_p(raw) if raw else None, ctypes.byref(h)))
+        if isinstance(stream, str):
+            if stream != "own":
+                raise ValueError("stream must be a torch stream, an int handle, None or 'own'")
+            _check(lib.ts_target_create_owned(int(device), ctypes.byref(h)))
+        else:
+            if stream is None:
+                stream = torch.cuda.current_stream(device)
+            if isinstance(stream, torch.cuda.Stream):
+                self._torch_stream = stream
+                raw = stream.cuda_stream
+            else:
+                raw = int(stream)
+            _check(lib.ts_target_create(int(device), ctypes.c_void_p(raw) if raw else None, ctypes.byref(h)))
         self.handle = h
         self.device = int(device)
         self._callbacks = []
@@ -133,6 +136,12 @@ class Target:
         cb = _lib.CALLBACK(tramp)
         self._callbacks.append(cb)  # keep alive until the target goes away
         _check(lib.ts_target_then(self.handle, cb, None))
+
+    def async_(self) -> "Future":
+        """Future of all work enqueued so far (ready from a stream callback)."""
+        h = ctypes.c_void_p()
+        _check(lib.ts_target_async(self.handle, ctypes.byref(h)))
+        return Future(h)
 
     def close(self) -> None:
         if getattr(self, "handle", None):
@@ -475,6 +484,31 @@ class Event:
     def close(self) -> None:
         if getattr(self, "handle", None):
             lib.ts_event_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Future:
+    """Completion of asynchronous work, made ready by a stream callback
+    (the futures of Listing 2's async_execute)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def wait(self) -> None:
+        _check(lib.ts_future_wait(self.handle))
+
+    def ready(self) -> bool:
+        return _check(lib.ts_future_ready(self.handle)) == 1
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib.ts_future_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -92,6 +92,7 @@ PROTOTYPES = {
     "ts_last_error": [],
     "ts_version": [ctypes.POINTER(I), ctypes.POINTER(I)],
     "ts_target_create": [I, P, ctypes.POINTER(H)],
+    "ts_target_create_owned": [I, ctypes.POINTER(H)],
     "ts_target_destroy": [H],
     "ts_target_synchronize": [H],
     "ts_target_info": [H, ctypes.POINTER(DeviceInfo)],
@@ -141,6 +142,10 @@ PROTOTYPES = {
     "ts_event_synchronize": [H],
     "ts_event_query": [H],
     "ts_event_elapsed_ms": [H, H, ctypes.POINTER(F)],
+    "ts_target_async": [H, ctypes.POINTER(H)],
+    "ts_future_wait": [H],
+    "ts_future_ready": [H],
+    "ts_future_destroy": [H],
 }
 RESTYPES = {"ts_last_error": ctypes.c_char_p}
 
@@ -149,7 +154,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(
             f"libtstream.so not found at {path}; build it with "
-            "`python -m paper_2206_06302_amd.build` (hipcc, gfx950)")
+            "`python paper_2206_06302_amd/build.py` (hipcc, gfx950)")
     lib = ctypes.CDLL(path)
     for name, args in PROTOTYPES.items():
         fn = getattr(lib, name)

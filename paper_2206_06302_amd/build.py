@@ -1,7 +1,9 @@
 """Build libtstream.so for gfx950 with hipcc (works without a GPU).
 
-    python -m paper_2206_06302_amd.build            # rebuild everything
-    python -m paper_2206_06302_amd.build --if-stale # only when sources changed
+    python paper_2206_06302_amd/build.py            # rebuild everything
+    python paper_2206_06302_amd/build.py --if-stale # only when sources changed
+
+(Run by path: importing the package itself loads the library.)
 
 Every translation unit is compiled with -ffp-contract=off (no contraction
 beyond the explicit fma of the triad), without fast-math, and with the

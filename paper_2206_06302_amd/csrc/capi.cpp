@@ -8,6 +8,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -67,6 +68,7 @@ constexpr uint32_t kArrayMagic = 0x41525231u;
 constexpr uint32_t kBatchMagic = 0x42415431u;
 constexpr uint32_t kGraphMagic = 0x47524631u;
 constexpr uint32_t kEventMagic = 0x45564e31u;
+constexpr uint32_t kFutureMagic = 0x46555431u;
 constexpr uint32_t kDead = 0xdeadbeefu;
 constexpr double kPeakBytesPerS = 8.0e12;  // MI355X HBM3E, the % of peak denominator
 
@@ -98,9 +100,8 @@ struct ts_batch_s {
   int device;
   int dtype;
   std::vector<HostDesc> host;
-  std::vector<BatchDesc> descs;
+  std::vector<BatchDesc> descs;  // host-side metadata (alignment per instance)
   std::vector<BatchTile> tiles;
-  BatchDesc* d_descs;
   BatchTile* d_tiles;
   double* d_expected;
   unsigned long long* d_counts;
@@ -122,6 +123,13 @@ struct ts_event_s {
   bool recorded;
 };
 
+struct ts_future_s {
+  uint32_t magic;
+  std::mutex mu;
+  std::condition_variable cv;
+  bool ready;
+};
+
 namespace {
 
 bool ok_target(const ts_target_s* t) { return t && t->magic == kTargetMagic; }
@@ -129,6 +137,17 @@ bool ok_array(const ts_array_s* a) { return a && a->magic == kArrayMagic; }
 bool ok_batch(const ts_batch_s* b) { return b && b->magic == kBatchMagic; }
 bool ok_graph(const ts_graph_s* g) { return g && g->magic == kGraphMagic; }
 bool ok_event(const ts_event_s* e) { return e && e->magic == kEventMagic; }
+bool ok_future(const ts_future_s* f) { return f && f->magic == kFutureMagic; }
+
+// Stream callback that makes a future ready (runs on a runtime thread).
+void future_ready_cb(void* p) {
+  ts_future_s* f = static_cast<ts_future_s*>(p);
+  {
+    std::lock_guard<std::mutex> lk(f->mu);
+    f->ready = true;
+  }
+  f->cv.notify_all();
+}
 
 // Make `device` current for the calling thread (cheap when it already is).
 int use_device(int device) {
@@ -253,25 +272,22 @@ int run_map(ts_target_s* t, int op, ts_array_s* x, ts_array_s* y, ts_array_s* d,
   return launch_map(t, op, x->dtype, x->ptr, has_y ? y->ptr : nullptr, d->ptr, count, q, cfg);
 }
 
-// Upload a batch's descriptor and tile tables (blocking).
+// Upload a batch's tile table (blocking).
 int batch_upload(ts_batch_s* b) {
   ts_target_s* t = b->target;
   if (b->d_tiles) {
     (void)hipFree(b->d_tiles);
     b->d_tiles = nullptr;
   }
-  if (!b->d_descs && !b->descs.empty()) {
-    TS_HIP(hipMalloc(&b->d_descs, b->descs.size() * sizeof(BatchDesc)));
+  if (!b->d_expected && !b->descs.empty()) {
     TS_HIP(hipMalloc(&b->d_expected, b->descs.size() * sizeof(double)));
     TS_HIP(hipMalloc(&b->d_counts, b->descs.size() * sizeof(unsigned long long)));
   }
-  if (!b->tiles.empty()) TS_HIP(hipMalloc(&b->d_tiles, b->tiles.size() * sizeof(BatchTile)));
-  if (!b->descs.empty())
-    TS_HIP(hipMemcpyAsync(b->d_descs, b->descs.data(), b->descs.size() * sizeof(BatchDesc),
-                          hipMemcpyHostToDevice, t->stream));
-  if (!b->tiles.empty())
+  if (!b->tiles.empty()) {
+    TS_HIP(hipMalloc(&b->d_tiles, b->tiles.size() * sizeof(BatchTile)));
     TS_HIP(hipMemcpyAsync(b->d_tiles, b->tiles.data(), b->tiles.size() * sizeof(BatchTile),
                           hipMemcpyHostToDevice, t->stream));
+  }
   TS_HIP(hipStreamSynchronize(t->stream));
   return TS_OK;
 }
@@ -294,7 +310,6 @@ int batch_replan(ts_batch_s* b, int64_t tile_elems) {
 int launch_batch(ts_target_s* t, ts_batch_s* b, int op, const ts_kernel_cfg& cfg) {
   if (b->tiles.empty()) return TS_OK;
   BatchLaunch L{};
-  L.descs = b->d_descs;
   L.tiles = b->d_tiles;
   L.ntiles = b->tiles.size();
   uint64_t grid = static_cast<uint64_t>(cfg.grid_per_cu) * static_cast<uint64_t>(t->info.compute_units);
@@ -401,11 +416,14 @@ int ts_version(int* major, int* minor) {
   return TS_OK;
 }
 
+}  // extern "C"
+
 // ---------------------------------------------------------------------------
 // Targets
 // ---------------------------------------------------------------------------
-int ts_target_create(int device, void* hip_stream, ts_target* out) {
-  TS_GUARD_BEGIN
+namespace {
+
+int create_target(int device, void* hip_stream, bool owned, ts_target* out) {
   if (!out) return fail(TS_E_INVALID, "NULL out-parameter");
   std::call_once(g_env_cache_once, load_env_cache);
   int count = 0;
@@ -435,7 +453,7 @@ int ts_target_create(int device, void* hip_stream, ts_target* out) {
   t->info.peak_bytes_per_s = kPeakBytesPerS;
   std::snprintf(t->info.arch, sizeof t->info.arch, "%s", p.gcnArchName);
   std::snprintf(t->info.name, sizeof t->info.name, "%s", p.name);
-  if (hip_stream) {
+  if (!owned) {
     t->stream = static_cast<hipStream_t>(hip_stream);
     t->owns_stream = false;
   } else {
@@ -457,6 +475,21 @@ int ts_target_create(int device, void* hip_stream, ts_target* out) {
   t->magic = kTargetMagic;
   *out = t;
   return TS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ts_target_create(int device, void* hip_stream, ts_target* out) {
+  TS_GUARD_BEGIN
+  return create_target(device, hip_stream, false, out);
+  TS_GUARD_END
+}
+
+int ts_target_create_owned(int device, ts_target* out) {
+  TS_GUARD_BEGIN
+  return create_target(device, nullptr, true, out);
   TS_GUARD_END
 }
 
@@ -937,7 +970,6 @@ int ts_batch_create(ts_target t, ts_dtype dtype, const ts_batch_desc* descs, siz
                           reinterpret_cast<uintptr_t>(d.c), d.len, d.q};
   }
   auto cleanup = [&](int status) {
-    if (b->d_descs) (void)hipFree(b->d_descs);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     if (b->d_expected) (void)hipFree(b->d_expected);
     if (b->d_counts) (void)hipFree(b->d_counts);
@@ -980,7 +1012,6 @@ int ts_batch_destroy(ts_batch b) {
   if (!ok_batch(b)) return fail(TS_E_INVALID, "invalid batch handle");
   (void)use_device(b->device);
   if (ok_target(b->target)) (void)hipStreamSynchronize(b->target->stream);
-  if (b->d_descs) (void)hipFree(b->d_descs);
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   if (b->d_expected) (void)hipFree(b->d_expected);
   if (b->d_counts) (void)hipFree(b->d_counts);
@@ -1047,7 +1078,7 @@ int ts_batch_fill(ts_target exec, ts_batch b, int which, double value) {
   if (st != TS_OK) return st;
   if (which < 0 || which > 2) return fail(TS_E_INVALID, "which must be 0 (a), 1 (b) or 2 (c)");
   if (b->tiles.empty()) return TS_OK;
-  const hipError_t e = launch_batch_fill(b->dtype, b->d_descs, b->d_tiles, b->tiles.size(), which, 0,
+  const hipError_t e = launch_batch_fill(b->dtype, b->d_tiles, b->tiles.size(), which, 0,
                                          value, 0, aux_grid(exec, b->tiles.size()), exec->stream);
   if (e != hipSuccess) return hip_fail(e, "batched fill launch");
   return TS_OK;
@@ -1062,7 +1093,7 @@ int ts_batch_fill_uniform(ts_target exec, ts_batch b, int which, uint64_t seed) 
   if (b->host.size() > (((1ull << 16) - 16) / 3))
     return fail(TS_E_UNSUPPORTED, "too many instances for 16-bit stream ids");
   if (b->tiles.empty()) return TS_OK;
-  const hipError_t e = launch_batch_fill(b->dtype, b->d_descs, b->d_tiles, b->tiles.size(), which, 1,
+  const hipError_t e = launch_batch_fill(b->dtype, b->d_tiles, b->tiles.size(), which, 1,
                                          0.0, seed, aux_grid(exec, b->tiles.size()), exec->stream);
   if (e != hipSuccess) return hip_fail(e, "batched uniform fill launch");
   return TS_OK;
@@ -1082,7 +1113,7 @@ int ts_batch_mismatch_count(ts_target exec, ts_batch b, int which, const double*
   hipError_t e = launch_zero_u64(b->d_counts, n, exec->stream);
   if (e != hipSuccess) return hip_fail(e, "zero kernel launch");
   if (!b->tiles.empty()) {
-    e = launch_batch_mismatch(b->dtype, b->d_descs, b->d_tiles, b->tiles.size(), which, b->d_expected,
+    e = launch_batch_mismatch(b->dtype, b->d_tiles, b->tiles.size(), which, b->d_expected,
                               b->d_counts, aux_grid(exec, b->tiles.size()), exec->stream);
     if (e != hipSuccess) return hip_fail(e, "batched mismatch launch");
   }
@@ -1249,6 +1280,57 @@ int ts_event_query(ts_event e) {
 int ts_event_elapsed_ms(ts_event start, ts_event end, float* ms) {
   if (!ok_event(start) || !ok_event(end) || !ms) return fail(TS_E_INVALID, "invalid event handle or NULL out");
   TS_HIP(hipEventElapsedTime(ms, start->ev, end->ev));
+  return TS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Futures
+// ---------------------------------------------------------------------------
+int ts_target_async(ts_target t, ts_future* out) {
+  TS_GUARD_BEGIN
+  if (!ok_target(t) || !out) return fail(TS_E_INVALID, "invalid target handle or NULL out");
+  int st = use_device(t->device);
+  if (st != TS_OK) return st;
+  ts_future_s* f = new ts_future_s();
+  f->ready = false;
+  f->magic = kFutureMagic;
+  const hipError_t e = hipLaunchHostFunc(t->stream, future_ready_cb, f);
+  if (e != hipSuccess) {
+    f->magic = kDead;
+    delete f;
+    return hip_fail(e, "hipLaunchHostFunc");
+  }
+  *out = f;
+  return TS_OK;
+  TS_GUARD_END
+}
+
+int ts_future_wait(ts_future f) {
+  TS_GUARD_BEGIN
+  if (!ok_future(f)) return fail(TS_E_INVALID, "invalid future handle");
+  std::unique_lock<std::mutex> lk(f->mu);
+  f->cv.wait(lk, [f] { return f->ready; });
+  return TS_OK;
+  TS_GUARD_END
+}
+
+int ts_future_ready(ts_future f) {
+  TS_GUARD_BEGIN
+  if (!ok_future(f)) return fail(TS_E_INVALID, "invalid future handle");
+  std::lock_guard<std::mutex> lk(f->mu);
+  return f->ready ? 1 : 0;
+  TS_GUARD_END
+}
+
+int ts_future_destroy(ts_future f) {
+  if (!f) return TS_OK;
+  if (!ok_future(f)) return fail(TS_E_INVALID, "invalid future handle");
+  {
+    std::unique_lock<std::mutex> lk(f->mu);
+    f->cv.wait(lk, [f] { return f->ready; });  // the callback still refers to it
+  }
+  f->magic = kDead;
+  delete f;
   return TS_OK;
 }
 

@@ -145,34 +145,33 @@ __global__ __launch_bounds__(256) void mismatch_pass1(const void* xv, const void
 }
 
 template <int DT>
-__global__ __launch_bounds__(256) void batch_fill_kernel(const BatchDesc* descs, const BatchTile* tiles,
-                                                         uint64_t ntiles, int which, int uniform,
-                                                         double value, uint64_t seed) {
+__global__ __launch_bounds__(256) void batch_fill_kernel(const BatchTile* tiles, uint64_t ntiles,
+                                                         int which, int uniform, double value,
+                                                         uint64_t seed) {
   using T = typename Fmt<DT>::T;
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const BatchTile tl = tiles[t];
-    const BatchDesc ds = descs[tl.inst];
-    T* d = static_cast<T*>(const_cast<void*>(which == 0 ? ds.a : which == 1 ? ds.b : ds.c));
+    T* d = static_cast<T*>(const_cast<void*>(which == 0 ? tl.a : which == 1 ? tl.b : tl.c));
     const uint64_t state0 = seed ^ ((16ull + 3ull * tl.inst + static_cast<uint64_t>(which)) << 48);
     const T cv = from_f64<DT>(value);
-    for (uint64_t j = tl.start + threadIdx.x; j < tl.end; j += blockDim.x)
+    const uint64_t end = tl.start + tl.count;
+    for (uint64_t j = tl.start + threadIdx.x; j < end; j += blockDim.x)
       d[j] = uniform ? from_f64<DT>(uniform_pm1(state0, j + 1)) : cv;
   }
 }
 
 template <int DT>
-__global__ __launch_bounds__(256) void batch_mismatch_kernel(const BatchDesc* descs,
-                                                             const BatchTile* tiles, uint64_t ntiles,
+__global__ __launch_bounds__(256) void batch_mismatch_kernel(const BatchTile* tiles, uint64_t ntiles,
                                                              int which, const double* expected,
                                                              unsigned long long* counts) {
   using T = typename Fmt<DT>::T;
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const BatchTile tl = tiles[t];
-    const BatchDesc ds = descs[tl.inst];
-    const T* x = static_cast<const T*>(which == 0 ? ds.a : which == 1 ? ds.b : ds.c);
+    const T* x = static_cast<const T*>(which == 0 ? tl.a : which == 1 ? tl.b : tl.c);
     const double e = expected[tl.inst];
+    const uint64_t end = tl.start + tl.count;
     CsPart acc{0.0, 0.0, 0.0, 0ull};
-    for (uint64_t j = tl.start + threadIdx.x; j < tl.end; j += kReduceBlock)
+    for (uint64_t j = tl.start + threadIdx.x; j < end; j += kReduceBlock)
       acc.mism += differs(to_f64<DT>(x[j]), e) ? 1ull : 0ull;
     const CsPart r = block_reduce(acc);
     if (threadIdx.x == 0 && r.mism) atomicAdd(&counts[tl.inst], r.mism);
@@ -252,18 +251,17 @@ hipError_t launch_mismatch(int dt, const void* x, const void* ref, uint64_t n, v
   return hipGetLastError();
 }
 
-hipError_t launch_batch_fill(int dt, const BatchDesc* descs, const BatchTile* tiles, uint64_t ntiles,
-                             int which, int uniform, double value, uint64_t seed, uint32_t grid,
-                             hipStream_t s) {
-  TS_BY_FORMAT(dt, batch_fill_kernel, dim3(grid), dim3(256), 0, s, descs, tiles, ntiles, which,
-               uniform, value, seed)
+hipError_t launch_batch_fill(int dt, const BatchTile* tiles, uint64_t ntiles, int which, int uniform,
+                             double value, uint64_t seed, uint32_t grid, hipStream_t s) {
+  TS_BY_FORMAT(dt, batch_fill_kernel, dim3(grid), dim3(256), 0, s, tiles, ntiles, which, uniform, value,
+               seed)
 }
 
-hipError_t launch_batch_mismatch(int dt, const BatchDesc* descs, const BatchTile* tiles,
-                                 uint64_t ntiles, int which, const double* expected,
-                                 unsigned long long* counts, uint32_t grid, hipStream_t s) {
-  TS_BY_FORMAT(dt, batch_mismatch_kernel, dim3(grid), dim3(kReduceBlock), 0, s, descs, tiles, ntiles,
-               which, expected, counts)
+hipError_t launch_batch_mismatch(int dt, const BatchTile* tiles, uint64_t ntiles, int which,
+                                 const double* expected, unsigned long long* counts, uint32_t grid,
+                                 hipStream_t s) {
+  TS_BY_FORMAT(dt, batch_mismatch_kernel, dim3(grid), dim3(kReduceBlock), 0, s, tiles, ntiles, which,
+               expected, counts)
 }
 
 hipError_t launch_zero_u64(unsigned long long* p, uint64_t n, hipStream_t s) {

@@ -211,44 +211,49 @@ __global__ __launch_bounds__(1024) void stream_kernel(const void* xv, const void
 // ---------------------------------------------------------------------------
 
 template <int OP>
-__device__ __forceinline__ void roles(const BatchDesc& ds, const void*& x, const void*& y, void*& d) {
+__device__ __forceinline__ void roles(const BatchTile& tl, const void*& x, const void*& y, void*& d) {
   // Listing 4 roles inside every instance.
-  if constexpr (OP == OP_COPY) { x = ds.a; y = nullptr; d = const_cast<void*>(ds.c); }
-  else if constexpr (OP == OP_SCALE) { x = ds.c; y = nullptr; d = const_cast<void*>(ds.b); }
-  else if constexpr (OP == OP_ADD) { x = ds.a; y = ds.b; d = const_cast<void*>(ds.c); }
-  else { x = ds.b; y = ds.c; d = const_cast<void*>(ds.a); }
+  if constexpr (OP == OP_COPY) { x = tl.a; y = nullptr; d = const_cast<void*>(tl.c); }
+  else if constexpr (OP == OP_SCALE) { x = tl.c; y = nullptr; d = const_cast<void*>(tl.b); }
+  else if constexpr (OP == OP_ADD) { x = tl.a; y = tl.b; d = const_cast<void*>(tl.c); }
+  else { x = tl.b; y = tl.c; d = const_cast<void*>(tl.a); }
 }
 
 // Persistent kernel: workgroup w takes tiles w, w + G, w + 2G, ... (static
-// stride, G = grid size); inside a tile the lanes stream 16-byte vectors.
+// stride, G = grid size).  Each tile record is self-contained, and the next
+// one is fetched while the current tile streams; inside a tile the lanes
+// stream 16-byte vectors like the plain kernel.
 template <int DT, int OP, int U, bool NTL, bool NTS>
-__global__ __launch_bounds__(1024) void batch_kernel(const BatchDesc* __restrict__ descs,
-                                                     const BatchTile* __restrict__ tiles,
+__global__ __launch_bounds__(1024) void batch_kernel(const BatchTile* __restrict__ tiles,
                                                      uint64_t ntiles) {
   using T = typename Fmt<DT>::T;
   constexpr int VB = 16;
   constexpr uint64_t V = VB / sizeof(T);
   const uint64_t width = blockDim.x;
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const BatchTile tl = tiles[t];
-    const BatchDesc ds = descs[tl.inst];
+  uint64_t t = blockIdx.x;
+  if (t >= ntiles) return;
+  BatchTile cur = tiles[t];
+  for (; t < ntiles; t += gridDim.x) {
+    BatchTile nxt = cur;
+    if (t + gridDim.x < ntiles) nxt = tiles[t + gridDim.x];
     const void *xv, *yv;
     void* dv;
-    roles<OP>(ds, xv, yv, dv);
+    roles<OP>(cur, xv, yv, dv);
     const T* x = static_cast<const T*>(xv);
     const T* y = static_cast<const T*>(yv);
     T* d = static_cast<T*>(dv);
-    const typename Fmt<DT>::C qc = pick_q<DT>(ds.q, ds.qf);
-    uint64_t vs = tl.end, ve = tl.end;  // vector range [vs, ve)
-    if (ds.vec_ok) {
-      const uint64_t h = ds.head;
-      vs = tl.start < h ? h : h + (tl.start - h + V - 1) / V * V;
-      if (vs > tl.end) vs = tl.end;
-      ve = tl.end < h ? vs : h + (tl.end - h) / V * V;
+    const typename Fmt<DT>::C qc = pick_q<DT>(cur.q, cur.qf);
+    const uint64_t start = cur.start, end = cur.start + cur.count;
+    uint64_t vs = end, ve = end;  // vector range [vs, ve)
+    if (cur.vec_ok) {
+      const uint64_t h = cur.head;
+      vs = start < h ? h : h + (start - h + V - 1) / V * V;
+      if (vs > end) vs = end;
+      ve = end < h ? vs : h + (end - h) / V * V;
       if (ve < vs) ve = vs;
     }
-    for (uint64_t j = tl.start + threadIdx.x; j < vs; j += width) map_elem<DT, OP>(x, y, d, qc, j);
-    for (uint64_t j = ve + threadIdx.x; j < tl.end; j += width) map_elem<DT, OP>(x, y, d, qc, j);
+    for (uint64_t j = start + threadIdx.x; j < vs; j += width) map_elem<DT, OP>(x, y, d, qc, j);
+    for (uint64_t j = ve + threadIdx.x; j < end; j += width) map_elem<DT, OP>(x, y, d, qc, j);
     const uint64_t nvec = (ve - vs) / V;
     if (nvec) {
       vec_body<DT, OP, VB, U, NTL, NTS>(reinterpret_cast<const char*>(x + vs),
@@ -256,6 +261,7 @@ __global__ __launch_bounds__(1024) void batch_kernel(const BatchDesc* __restrict
                                         reinterpret_cast<char*>(d + vs), qc, nvec, threadIdx.x,
                                         width, width * U);
     }
+    cur = nxt;
   }
 }
 
@@ -313,7 +319,7 @@ hipError_t plain_dispatch(const PlainLaunch& L) {
 template <int DT, int OP, int U, bool NTL, bool NTS>
 hipError_t launch_batch_inst(const BatchLaunch& L) {
   hipLaunchKernelGGL((batch_kernel<DT, OP, U, NTL, NTS>), dim3(L.grid), dim3(L.block), 0, L.stream,
-                     L.descs, L.tiles, L.ntiles);
+                     L.tiles, L.ntiles);
   return hipGetLastError();
 }
 

@@ -158,15 +158,24 @@ struct BatchDesc {
   uint32_t pad;
 };
 
-// Element range [start, end) of one instance.  Boundaries other than 0 and
-// len sit at head + k * tile_elems, so only an instance's first tile has an
-// unaligned head and only its last tile a ragged tail.
+// One tile: the element range [start, start + count) of one instance, with
+// everything a workgroup needs to stream it (64 bytes, one scalar load).
+// Boundaries other than 0 and len sit at head + k * tile_elems, so only an
+// instance's first tile has an unaligned head and only its last tile a
+// ragged tail.
 struct BatchTile {
-  uint32_t inst;
-  uint32_t pad;
+  const void* a;
+  const void* b;
+  const void* c;
   uint64_t start;
-  uint64_t end;
+  uint64_t count;
+  double q;
+  float qf;
+  uint32_t head;    // the instance's head (elements before 16-byte alignment)
+  uint32_t inst;
+  uint32_t vec_ok;  // a, b and c share one misalignment
 };
+static_assert(sizeof(BatchTile) == 64, "tile records are one 64-byte scalar load");
 
 struct HostDesc {
   uintptr_t a, b, c;
@@ -221,7 +230,8 @@ inline int plan_batch(const HostDesc* in, size_t count, size_t es, int64_t tile_
     uint64_t start = 0;
     uint64_t end = hd + T < h.len ? hd + T : h.len;
     for (;;) {
-      tiles.push_back(BatchTile{static_cast<uint32_t>(i), 0u, start, end});
+      tiles.push_back(BatchTile{d.a, d.b, d.c, start, end - start, d.q, d.qf, d.head,
+                                static_cast<uint32_t>(i), d.vec_ok});
       if (end >= h.len) break;
       start = end;
       end = end + T < h.len ? end + T : h.len;

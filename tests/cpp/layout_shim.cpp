@@ -54,7 +54,12 @@ int shim_plan_batch(const uint64_t* descs, size_t count, uint64_t es, int64_t ti
   for (size_t t = 0; t < bt.size() && t < cap; ++t) {
     tiles_out[3 * t] = bt[t].inst;
     tiles_out[3 * t + 1] = bt[t].start;
-    tiles_out[3 * t + 2] = bt[t].end;
+    tiles_out[3 * t + 2] = bt[t].start + bt[t].count;
+    // every tile carries its instance's pointers, scalar and alignment
+    const ts::BatchDesc& d = bd[bt[t].inst];
+    if (bt[t].a != d.a || bt[t].b != d.b || bt[t].c != d.c || bt[t].head != d.head ||
+        bt[t].vec_ok != d.vec_ok || bt[t].q != d.q)
+      return -100;
   }
   for (size_t i = 0; i < count; ++i) {
     meta_out[2 * i] = bd[i].head;

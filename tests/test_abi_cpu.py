@@ -64,11 +64,16 @@ def test_version_and_errors(ts):
     assert L.ts_array_info(None, None, None, None) == TS_E_INVALID
     assert L.ts_version(None, None) == TS_E_INVALID
     # destroy/free accept NULL as a no-op and never fail on it
-    for fn in ("ts_target_destroy", "ts_array_free", "ts_batch_destroy", "ts_graph_destroy", "ts_event_destroy"):
+    for fn in ("ts_target_destroy", "ts_array_free", "ts_batch_destroy", "ts_graph_destroy", "ts_event_destroy",
+               "ts_future_destroy"):
         assert getattr(L, fn)(None) == TS_OK
     assert L.ts_batch_op(None, None, 3) == TS_E_INVALID
     assert L.ts_graph_launch(None, None, 1) == TS_E_INVALID
     assert L.ts_event_query(None) == TS_E_INVALID
+    assert L.ts_future_wait(None) == TS_E_INVALID
+    assert L.ts_future_ready(None) == TS_E_INVALID
+    assert L.ts_future_destroy(None) == TS_OK
+    assert L.ts_target_async(None, None) == TS_E_INVALID
 
 
 def test_target_create_without_gpu_reports_device_error(ts):

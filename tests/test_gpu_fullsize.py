@@ -1,0 +1,226 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark uses (the committed tuning table).  Whole arrays are checked on the
+GPU against the oracle's scalar recurrence where every element follows the
+same chain; seeded random inputs are checked on sampled elements, which the
+oracle computes one by one (every output element depends only on the same
+element of the inputs)."""
+import numpy as np
+import pytest
+
+import oracle
+import tsgen
+from gpu_util import mismatches, say, widen
+
+pytestmark = pytest.mark.gpu
+
+N27 = 1 << 27
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_2206_06302_amd as ts
+
+    ts.tune_cache_clear()
+    ts.load_default_tuning()
+    tgt = ts.Target(0, torch.cuda.Stream())
+    yield ts, torch, tgt
+    tgt.synchronize()
+    tgt.close()
+    torch.cuda.empty_cache()
+
+
+def _free(torch):
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def _sample_indices(n, rng, count=1 << 15):
+    idx = set(rng.integers(0, n, count).tolist())
+    idx.update(range(min(n, 64)))
+    idx.update(range(max(0, n - 64), n))
+    for j in range(1, 64):  # around workgroup-chunk boundaries of the vector body
+        b = j * 4096
+        idx.update(k for k in (b - 1, b, b + 1) if 0 <= k < n)
+    return np.array(sorted(idx), np.int64)
+
+
+def _gather(torch, t, idx):
+    return t[torch.from_numpy(idx).to(t.device)].cpu()
+
+
+def test_headline_constant_init_whole_arrays(env):
+    """N = 2^27 doubles from (1, 2, 0), q = 3: after 21 and 50 iterations every
+    element of a, b, c equals the oracle's recurrence bit for bit (50
+    distinguishes a fused triad from an unfused one)."""
+    ts, torch, tgt = env
+    A, B, C = (ts.Array.alloc(tgt, "f64", N27) for _ in range(3))
+    A.fill(1.0), B.fill(2.0), C.fill(0.0)
+    say("[headline constant init N=2^27]")
+    for k in range(1, 51):
+        ts.stream_iteration(tgt, A, B, C, 3.0)
+        if k in (1, 13, 21, 50):
+            exp = oracle.stream_scalar_f64(1.0, 2.0, 0.0, 3.0, k)
+            for arr, e, nm in zip((A, B, C), exp, "abc"):
+                cs = ts.checksum(tgt, arr, e)
+                assert cs["mismatches"] == 0 and cs["max_abs_dev"] == 0.0, (k, nm, cs)
+    for arr in (A, B, C):
+        arr.free()
+    _free(torch)
+
+
+def test_headline_random_init_sampled(env):
+    ts, torch, tgt = env
+    ts_ = [torch.empty(N27, dtype=torch.float64, device="cuda") for _ in range(3)]
+    torch.cuda.synchronize()
+    A, B, C = (ts.Array.wrap(tgt, t) for t in ts_)
+    for k, arr in enumerate((A, B, C)):
+        arr.fill_uniform(2, k)
+    say("[headline random init N=2^27, 21 iterations]")
+    for _ in range(21):
+        ts.stream_iteration(tgt, A, B, C, 3.0)
+    tgt.synchronize()
+    idx = _sample_indices(N27, np.random.default_rng(1))
+    a0, b0, c0 = (tsgen.uniform_pm1(2, k, idx.astype(np.uint64)) for k in range(3))
+    ra, rb, rc = oracle.stream_elements_f64(a0, b0, c0, 3.0, 21)
+    for t, r, nm in zip(ts_, (ra, rb, rc), "abc"):
+        got = _gather(torch, t, idx).numpy()
+        bad = np.nonzero(got.view(np.uint64) != r.view(np.uint64))[0]
+        assert bad.size == 0, (nm, idx[bad[:5]], got[bad[:5]], r[bad[:5]])
+    del A, B, C, ts_
+    _free(torch)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("p", [16, 20, 24, 27, 29])
+@pytest.mark.parametrize("misaligned", [False, True])
+def test_size_sweep(env, dtype, p, misaligned):
+    """Sizes 2^p and 2^p + 7 starting one element past an aligned base:
+    one iteration of the four maps from seeded inputs."""
+    ts, torch, tgt = env
+    n = (1 << p) + (7 if misaligned else 0)
+    off = 1 if misaligned else 0
+    tt = [torch.empty(n + off + 8, dtype=ts.TORCH_DTYPES[dtype], device="cuda") for _ in range(3)]
+    torch.cuda.synchronize()
+    views = [t[off:off + n] for t in tt]
+    A, B, C = (ts.Array.wrap(tgt, v) for v in views)
+    for k, arr in enumerate((A, B, C)):
+        arr.fill_uniform(3, k)
+    say(f"[sweep {dtype} 2^{p}{' +7 off1' if misaligned else ''}]")
+    ts.stream_iteration(tgt, A, B, C, 3.0)
+    tgt.synchronize()
+    if p <= 20:
+        idx = np.arange(n, dtype=np.int64)
+    else:
+        idx = _sample_indices(n, np.random.default_rng(p))
+    host = [tsgen.narrow(tsgen.uniform_pm1(3, k, idx.astype(np.uint64)), dtype) for k in range(3)]
+    oracle.stream_run(oracle.DTYPES[dtype], host[0], host[1], host[2], 3.0, 1)
+    for v, r, nm in zip(views, host, "abc"):
+        got = _gather(torch, v, idx).numpy()
+        bad = mismatches(got, r, dtype)
+        assert bad.size == 0, (nm, idx[bad[:5]])
+    del A, B, C, views, tt
+    _free(torch)
+
+
+# Relative error bound of one standalone map in each storage format: one
+# binary32 rounding (unit roundoff 2^-24), then one rounding into the storage
+# format (2^-8 for bfloat16, 2^-11 for binary16): (1+e1)(1+e2) - 1.
+U32 = 2.0 ** -24
+REL_BOUND = {"f32": U32, "bf16": 2.0 ** -8 + U32 + 2.0 ** -8 * U32, "f16": 2.0 ** -11 + U32 + 2.0 ** -11 * U32}
+SMALLEST_NORMAL = {"f32": 2.0 ** -126, "bf16": 2.0 ** -126, "f16": 2.0 ** -14}
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+def test_reduced_precision_2p28(env, dtype):
+    """N = 2^28 per array in reduced storage: every map standalone equals the
+    binary32-math oracle bit for bit on sampled elements, and its relative
+    error against binary64 arithmetic on the same stored inputs stays within
+    one rounding of binary32 plus one of the storage format."""
+    ts, torch, tgt = env
+    n = 1 << 28
+    tt = [torch.empty(n, dtype=ts.TORCH_DTYPES[dtype], device="cuda") for _ in range(3)]
+    torch.cuda.synchronize()
+    X, Y, D = (ts.Array.wrap(tgt, t) for t in tt)
+    X.fill_uniform(4, 0), Y.fill_uniform(4, 1)
+    idx = _sample_indices(n, np.random.default_rng(7))
+    xs = tsgen.narrow(tsgen.uniform_pm1(4, 0, idx.astype(np.uint64)), dtype)
+    ys = tsgen.narrow(tsgen.uniform_pm1(4, 1, idx.astype(np.uint64)), dtype)
+    xw, yw = widen(dtype, xs), widen(dtype, ys)
+    worst = {}
+    for op in ("copy", "scale", "add", "triad"):
+        say(f"[reduced {dtype} {op} 2^28]")
+        ts.run_op(tgt, op, X, Y, D, 3.0)
+        tgt.synchronize()
+        got = _gather(torch, tt[2], idx)
+        got = got.view(torch.int16).numpy().view(np.uint16) if dtype != "f32" else got.numpy()
+        ref = np.zeros_like(xs)
+        oracle.op(oracle.DTYPES[dtype], oracle.OPS[op], xs, ys if op in ("add", "triad") else None, ref, 3.0)
+        bad = mismatches(got, ref, dtype)
+        assert bad.size == 0, (op, idx[bad[:5]])
+        # error against binary64 arithmetic on the exact stored inputs
+        r64 = np.zeros_like(xw)
+        oracle.op(oracle.F64, oracle.OPS[op], xw, yw if op in ("add", "triad") else None, r64, float(np.float32(3.0)))
+        gw = widen(dtype, got)
+        normal = np.abs(r64) >= SMALLEST_NORMAL[dtype]
+        rel = np.abs(gw[normal] - r64[normal]) / np.abs(r64[normal])
+        worst[op] = float(rel.max()) if rel.size else 0.0
+        if op == "copy":
+            assert worst[op] == 0.0
+        else:
+            assert worst[op] <= REL_BOUND[dtype], (op, worst[op])
+    print(f"max relative error vs binary64 ({dtype}): {worst}", flush=True)
+    del X, Y, D, tt
+    _free(torch)
+
+
+def test_batched_full_4096_instances(env):
+    """The benchmark's batch: 4096 instances, log-uniform lengths in
+    [1e3, 1e7) (about 4.2e9 elements, 102 GB), q_i in [0.5, 4).  The captured
+    four-map iteration replayed 50 times: from (1, 2, 0) every element of
+    instance i equals the scalar chain with q_i; from seeded random inputs,
+    sampled elements equal the oracle's chain."""
+    ts, torch, tgt = env
+    count, seed = 4096, 5
+    lens = tsgen.batched_lengths(seed, count)
+    qs = tsgen.batched_scalars(seed, count)
+    offs, pos = [], 0
+    for n in lens:
+        start = (pos + 31) // 32 * 32
+        offs.append(start)
+        pos = start + int(n)
+    pools = [torch.empty(pos + 32, dtype=torch.float64, device="cuda") for _ in range(3)]
+    torch.cuda.synchronize()
+    descs = [(pools[0].data_ptr() + o * 8, pools[1].data_ptr() + o * 8, pools[2].data_ptr() + o * 8, int(n), float(q))
+             for o, n, q in zip(offs, lens, qs)]
+    batch = ts.Batch(tgt, "f64", descs)
+    g = ts.Graph.capture_stream_iteration(tgt, batch)
+    batch.fill(tgt, 0, 1.0), batch.fill(tgt, 1, 2.0), batch.fill(tgt, 2, 0.0)
+    say(f"[batched 4096 constant init, {batch.info()}]")
+    g.launch(tgt, 50)
+    exp = [oracle.stream_scalar_f64(1.0, 2.0, 0.0, float(q), 50) for q in qs]
+    for k in range(3):
+        counts = batch.mismatch_count(tgt, k, [e[k] for e in exp])
+        assert int(counts.sum()) == 0, (k, np.nonzero(counts)[0][:8])
+    for k in range(3):
+        batch.fill_uniform(tgt, k, seed)
+    say("[batched 4096 random init]")
+    g.launch(tgt, 50)
+    tgt.synchronize()
+    rng = np.random.default_rng(11)
+    inst = np.concatenate([rng.integers(0, count, 4000), np.arange(64), np.arange(64)])
+    pos_in = np.concatenate([np.array([int(rng.integers(0, lens[i])) for i in inst[:4000]]),
+                             np.zeros(64, np.int64), np.array([int(lens[i]) - 1 for i in range(64)])])
+    flat = np.array([offs[i] for i in inst], np.int64) + pos_in
+    init = [np.array([tsgen.uniform_pm1(seed, tsgen.instance_stream(int(i), k), [int(j)])[0]
+                      for i, j in zip(inst, pos_in)]) for k in range(3)]
+    ra, rb, rc = oracle.stream_elements_f64(init[0], init[1], init[2], qs[inst], 50)
+    for t, r, nm in zip(pools, (ra, rb, rc), "abc"):
+        got = _gather(torch, t, flat).numpy()
+        bad = np.nonzero(got.view(np.uint64) != r.view(np.uint64))[0]
+        assert bad.size == 0, (nm, inst[bad[:5]], pos_in[bad[:5]])
+    g.close()
+    batch.close()
+    del pools
+    _free(torch)

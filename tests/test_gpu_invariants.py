@@ -1,0 +1,94 @@
+"""Launch-shape invariance: every configuration the tuner may pick (block,
+unroll, vector width, nontemporal hints, grid shape; batched tile walk) gives
+the oracle's result bit for bit, so tuning can change speed only."""
+import numpy as np
+import pytest
+
+import oracle
+import tsgen
+from gpu_util import device_array, say
+
+pytestmark = pytest.mark.gpu
+
+OPS = ("copy", "scale", "add", "triad")
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_2206_06302_amd as ts
+
+    tgt = ts.Target(0, torch.cuda.Stream())
+    yield ts, torch, tgt
+    for op in OPS:
+        for dt in ("f64", "f32", "bf16", "f16"):
+            ts.set_kernel_cfg(op, dt, None)
+            ts.set_kernel_cfg(op, dt, None, batched=True)
+    tgt.synchronize()
+    tgt.close()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+@pytest.mark.parametrize("offset", [0, 1])
+def test_every_plain_candidate_matches_oracle(env, dtype, offset):
+    ts, torch, tgt = env
+    n = (1 << 17) + 13
+    x = tsgen.uniform_array(31, 0, n, dtype)
+    y = tsgen.uniform_array(31, 1, n, dtype)
+    X = device_array(ts, torch, tgt, x, dtype, offset)
+    Y = device_array(ts, torch, tgt, y, dtype, offset)
+    D = device_array(ts, torch, tgt, np.zeros_like(x), dtype, offset)
+    cands = ts.candidates()
+    for op in OPS:
+        ref = np.zeros_like(x)
+        oracle.op(oracle.DTYPES[dtype], oracle.OPS[op], x, y if op in ("add", "triad") else None, ref, 3.0)
+        R = device_array(ts, torch, tgt, ref, dtype, 0)
+        say(f"[invariance {dtype} off={offset} {op}] {len(cands)} candidates")
+        for cfg in cands:
+            ts.set_kernel_cfg(op, dtype, cfg)
+            D.fill(0.0)
+            ts.run_op(tgt, op, X, Y, D, 3.0)
+            assert ts.mismatch_count(tgt, D, R) == 0, (op, cfg)
+        ts.set_kernel_cfg(op, dtype, None)
+
+
+def test_every_batched_candidate_matches_plain(env):
+    ts, torch, tgt = env
+    rng = np.random.default_rng(19)
+    lens = [0, 1, 7, 9, 1000, 16385, 70001] + list(rng.integers(1, 40000, 9))
+    es = 8
+    offs, pos = [], 0
+    for i, n in enumerate(lens):
+        start = (pos + 31) // 32 * 32 + (i % 2)  # every other instance misaligned by one element
+        offs.append(start)
+        pos = start + int(n)
+    init = [torch.from_numpy(tsgen.uniform_array(3, k, pos + 32)).cuda() for k in range(3)]
+    work = [t.clone() for t in init]
+    ref = [t.clone() for t in init]
+    torch.cuda.synchronize()
+    qs = tsgen.batched_scalars(2, len(lens))
+    mk = lambda pools: [(pools[0].data_ptr() + o * es, pools[1].data_ptr() + o * es, pools[2].data_ptr() + o * es,
+                         int(n), float(q)) for o, n, q in zip(offs, lens, qs)]
+    bref = ts.Batch(tgt, "f64", mk(ref))
+    bw = ts.Batch(tgt, "f64", mk(work))
+    for op in OPS:
+        bref.op_plain(tgt, op)
+    tgt.synchronize()
+    cands = ts.candidates(batched=True)
+    say(f"[batched invariance] {len(cands)} candidates")
+    for cfg in cands:
+        for op in OPS:
+            ts.set_kernel_cfg(op, "f64", cfg, batched=True)
+        for k in range(3):
+            work[k].copy_(init[k])
+        torch.cuda.synchronize()
+        for op in OPS:
+            bw.op(tgt, op)
+        tgt.synchronize()
+        for k in range(3):
+            assert torch.equal(work[k].view(torch.int64), ref[k].view(torch.int64)), (cfg, k)
+    for op in OPS:
+        ts.set_kernel_cfg(op, "f64", None, batched=True)
+    bref.close(), bw.close()

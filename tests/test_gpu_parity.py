@@ -263,3 +263,28 @@ def test_plain_graph_matches_eager(env):
     g.close()
     oracle.stream_run(oracle.F64, a, b, c, 3.0, 6)
     assert_same_bits(A1.to_host(), a, "f64", "a after graph")
+
+
+def test_futures_become_ready_after_the_work(env):
+    """A future of the work enqueued so far is made ready by a stream callback
+    once that work has finished; its results are then visible to the host."""
+    ts, torch, tgt = env
+    n = 1 << 24
+    A, B, C = (empty_array(ts, torch, tgt, n, "f64") for _ in range(3))
+    A.fill(1.0), B.fill(2.0), C.fill(0.0)
+    futs = []
+    for k in range(6):
+        ts.stream_iteration(tgt, A, B, C, 3.0)
+        futs.append(tgt.async_())
+    futs[-1].wait()
+    assert all(f.ready() for f in futs)  # callbacks run in stream order
+    a = A.to_host()
+    assert np.all(a == 15.0 ** 6)
+    pending = []
+    for _ in range(3):
+        ts.stream_iteration(tgt, A, B, C, 3.0)
+        pending.append(tgt.async_())
+    for f in pending:  # destroying a pending future waits for its callback
+        f.close()
+    tgt.synchronize()
+    assert ts.checksum(tgt, A, 15.0 ** 9)["mismatches"] == 0
