@@ -257,6 +257,35 @@ def cpu_baseline_leg(n, target_seconds=12.0):
             "best_GBps_per_kernel": best, "valid": bool(ok)}
 
 
+def host_target_leg(ts, n, threads, iters=10):
+    """STREAM on the library's host-CPU target (pinned workers over equal
+    blocks, first-touch bulk construction): the paper's NUMA back-end,
+    measured beside the oracle's plain threaded loops on the same cores."""
+    cpus = [c for dom in ts.host_numa_domains() for c in dom][:threads]
+    tgt = ts.Target.host(cpus)
+    A, B, C = (ts.Array.alloc(tgt, "f64", n) for _ in range(3))
+    A.fill(1.0), B.fill(2.0), C.fill(0.0)
+    roles = {"copy": (A, None, C), "scale": (C, None, B), "add": (A, B, C), "triad": (B, C, A)}
+    best = {op: float("inf") for op in OPS}
+    total = 0.0
+    ts.stream_iteration(tgt, A, B, C, 3.0)  # warm-up
+    for _ in range(iters):
+        for op in OPS:
+            x, y, d = roles[op]
+            ms = ts.time_op(tgt, op, x, y, d, 3.0, reps=1)
+            best[op] = min(best[op], ms)
+            total += ms
+    import oracle
+    exp = oracle.stream_scalar_f64(1.0, 2.0, 0.0, 3.0, iters + 1)
+    valid = all(ts.checksum(tgt, arr, e)["mismatches"] == 0 for arr, e in zip((A, B, C), exp))
+    for arr in (A, B, C):
+        arr.free()
+    tgt.close()
+    return {"value": round(80 * n * iters / total / 1e6, 2), "unit": "GB/s", "cores": len(cpus),
+            "best_GBps_per_kernel": {op: round(ts.stream_bytes(op, n) / best[op] / 1e6, 2) for op in OPS},
+            "iterations": iters, "valid": valid}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -344,6 +373,14 @@ def main():
     if not a.no_cpu:
         log("cpu baseline leg (oracle)")
         result["cpu_baseline"] = cpu_baseline_leg(a.n)
+        if not a.quick:
+            log("host target leg")
+            try:
+                result["host_target"] = host_target_leg(ts, a.n, result["cpu_baseline"]["cores"])
+                result["host_target"]["vs_oracle_threads"] = round(
+                    result["host_target"]["value"] / result["cpu_baseline"]["value"], 3)
+            except Exception as e:
+                result["host_target"] = {"error": f"{type(e).__name__}: {e}"}
     tgt.close()
     print(json.dumps(result))
 

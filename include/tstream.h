@@ -118,6 +118,24 @@ TS_API int ts_target_create(int device, void *hip_stream, ts_target *out);
 /* Same, on a non-blocking stream the library creates and destroys with the
  * target. */
 TS_API int ts_target_create_owned(int device, ts_target *out);
+/* Host-CPU target (the paper's NUMA back-end, Section 4.1): a set of CPUs,
+ * one worker thread pinned to each.  Arrays allocated on it live in host
+ * memory and are divided into equal contiguous blocks over the workers in
+ * the order of `cpus` (the block allocator); bulk construction and every
+ * algorithm call run each block on its own worker (the pinned executor), so
+ * the first touch places a block's pages on its worker's NUMA node.  `cpus`
+ * NULL (or ncpus 0) takes every CPU the process may run on, grouped by NUMA
+ * domain.  Calls on a host target complete before they return.  Binary64
+ * and binary32 storage only (TS_E_UNSUPPORTED otherwise); batches, graphs,
+ * events and tuning are GPU-only (TS_E_UNSUPPORTED).  Its arrays and its
+ * executor report device -1, so host and GPU arrays never mix
+ * (TS_E_PLACEMENT). */
+TS_API int ts_target_create_host(const int *cpus, int ncpus, ts_target *out);
+/* NUMA domains of the CPUs this process may use (1 when the machine does
+ * not expose its topology), and the CPU ids of one domain: writes up to
+ * `cap` ids and the full count. */
+TS_API int ts_host_numa_domains(int *count);
+TS_API int ts_host_domain_cpus(int domain, int *cpus, int cap, int *count);
 TS_API int ts_target_destroy(ts_target target);
 /* Block until all work enqueued on the target's stream has finished. */
 TS_API int ts_target_synchronize(ts_target target);

@@ -77,6 +77,20 @@ def _op(op) -> int:
     return OPS[op] if isinstance(op, str) else int(op)
 
 
+def host_numa_domains() -> list[list[int]]:
+    """CPU ids of each NUMA domain the process may run on."""
+    cnt = ctypes.c_int()
+    _check(lib.ts_host_numa_domains(ctypes.byref(cnt)))
+    out = []
+    for d in range(cnt.value):
+        n = ctypes.c_int()
+        _check(lib.ts_host_domain_cpus(d, None, 0, ctypes.byref(n)))
+        buf = (ctypes.c_int * max(1, n.value))()
+        _check(lib.ts_host_domain_cpus(d, buf, n.value, ctypes.byref(n)))
+        out.append(list(buf[:n.value]))
+    return out
+
+
 def version() -> tuple[int, int]:
     ma, mi = ctypes.c_int(), ctypes.c_int()
     _check(lib.ts_version(ctypes.byref(ma), ctypes.byref(mi)))
@@ -112,6 +126,24 @@ class Target:
         self.handle = h
         self.device = int(device)
         self._callbacks = []
+
+    @classmethod
+    def host(cls, cpus=None) -> "Target":
+        """Host-CPU target: one pinned worker per CPU in `cpus` (default: every
+        CPU the process may use, grouped by NUMA domain); arrays on it are
+        divided into equal blocks over the workers (Section 4.1)."""
+        self = cls.__new__(cls)
+        self._torch_stream = None
+        self._callbacks = []
+        h = ctypes.c_void_p()
+        if cpus:
+            arr = (ctypes.c_int * len(cpus))(*[int(c) for c in cpus])
+            _check(lib.ts_target_create_host(arr, len(cpus), ctypes.byref(h)))
+        else:
+            _check(lib.ts_target_create_host(None, 0, ctypes.byref(h)))
+        self.handle = h
+        self.device = -1
+        return self
 
     def synchronize(self) -> None:
         _check(lib.ts_target_synchronize(self.handle))
@@ -183,6 +215,18 @@ class Array:
         _check(lib.ts_array_wrap(target.handle, DTYPES[dtype], ctypes.c_void_p(tensor.data_ptr()), n,
                                  ctypes.byref(h)))
         return cls(h, target, dtype, n, keep=tensor)
+
+    @classmethod
+    def wrap_numpy(cls, target: Target, arr: np.ndarray) -> "Array":
+        """Borrow a contiguous 1-D numpy array (host memory; host targets)."""
+        names = {np.dtype(np.float64): "f64", np.dtype(np.float32): "f32"}
+        dtype = names.get(arr.dtype)
+        if dtype is None or arr.ndim != 1 or not arr.flags.c_contiguous:
+            raise TSError(-3, "need a contiguous 1-D float64 or float32 array")
+        h = ctypes.c_void_p()
+        _check(lib.ts_array_wrap(target.handle, DTYPES[dtype], ctypes.c_void_p(arr.ctypes.data), arr.size,
+                                 ctypes.byref(h)))
+        return cls(h, target, dtype, arr.size, keep=arr)
 
     @classmethod
     def alloc(cls, target: Target, dtype: str, n: int, offset: int = 0) -> "Array":

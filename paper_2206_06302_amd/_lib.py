@@ -93,6 +93,9 @@ PROTOTYPES = {
     "ts_version": [ctypes.POINTER(I), ctypes.POINTER(I)],
     "ts_target_create": [I, P, ctypes.POINTER(H)],
     "ts_target_create_owned": [I, ctypes.POINTER(H)],
+    "ts_target_create_host": [ctypes.POINTER(I), I, ctypes.POINTER(H)],
+    "ts_host_numa_domains": [ctypes.POINTER(I)],
+    "ts_host_domain_cpus": [I, ctypes.POINTER(I), I, ctypes.POINTER(I)],
     "ts_target_destroy": [H],
     "ts_target_synchronize": [H],
     "ts_target_info": [H, ctypes.POINTER(DeviceInfo)],

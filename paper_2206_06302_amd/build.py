@@ -29,7 +29,7 @@ LIB = os.path.join(PKG, "libtstream.so")
 ARCH = os.environ.get("TS_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["kern_f64.hip", "kern_f32.hip", "kern_bf16.hip", "kern_f16.hip", "kern_aux.hip",
-           "capi.cpp", "tune.cpp"]
+           "capi.cpp", "tune.cpp", "host_target.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",

@@ -7,7 +7,10 @@
 // status and leaves a thread-local message on failure.
 #include <hip/hip_runtime_api.h>
 
+#include <unistd.h>
+
 #include <algorithm>
+#include <chrono>
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
@@ -19,6 +22,7 @@
 #include <vector>
 
 #include "../../include/tstream.h"
+#include "host_target.hpp"
 #include "ts_internal.hpp"
 #include "tune.hpp"
 
@@ -76,7 +80,9 @@ constexpr double kPeakBytesPerS = 8.0e12;  // MI355X HBM3E, the % of peak denomi
 
 struct ts_target_s {
   uint32_t magic;
-  int device;
+  int device;  // -1 for a host-CPU target
+  bool host;
+  ts::HostPool* pool;  // host targets: the pinned workers
   hipStream_t stream;
   bool owns_stream;
   ts_device_info info;
@@ -87,7 +93,7 @@ struct ts_target_s {
 struct ts_array_s {
   uint32_t magic;
   ts_target_s* target;
-  int device;
+  int device;  // -1: host memory of a host target
   int dtype;
   void* ptr;
   uint64_t n;
@@ -138,6 +144,23 @@ bool ok_batch(const ts_batch_s* b) { return b && b->magic == kBatchMagic; }
 bool ok_graph(const ts_graph_s* g) { return g && g->magic == kGraphMagic; }
 bool ok_event(const ts_event_s* e) { return e && e->magic == kEventMagic; }
 bool ok_future(const ts_future_s* f) { return f && f->magic == kFutureMagic; }
+
+constexpr int kHostDevice = -1;
+
+int host_only_gpu(const char* what) {
+  return fail(TS_E_UNSUPPORTED, "%s needs a GPU target (this is a host-CPU target)", what);
+}
+
+// Run fn(lo, hi, w) on every worker of a host target over its block of n.
+template <class F>
+void host_blocks(ts_target_s* t, uint64_t n, F&& fn) {
+  const int W = t->pool->size();
+  t->pool->run([&](int w) {
+    uint64_t lo, hi;
+    HostPool::block(n, W, w, &lo, &hi);
+    fn(lo, hi, w);
+  });
+}
 
 // Stream callback that makes a future ready (runs on a runtime thread).
 void future_ready_cb(void* p) {
@@ -263,8 +286,25 @@ int run_map(ts_target_s* t, int op, ts_array_s* x, ts_array_s* y, ts_array_s* d,
   int st = check_exec_arrays(t, op, x, y, d, &count);
   if (st != TS_OK) return st;
   if (count == 0) return TS_OK;
-  if ((st = use_device(t->device)) != TS_OK) return st;
   const bool has_y = op == TS_ADD || op == TS_TRIAD;
+  if (t->host) {
+    if (x->dtype == TS_F64) {
+      const double* xp = static_cast<const double*>(x->ptr);
+      const double* yp = has_y ? static_cast<const double*>(y->ptr) : nullptr;
+      double* dp = static_cast<double*>(d->ptr);
+      host_blocks(t, count, [&](uint64_t lo, uint64_t hi, int) { host_map_f64(op, xp, yp, dp, lo, hi, q); });
+    } else if (x->dtype == TS_F32) {
+      const float* xp = static_cast<const float*>(x->ptr);
+      const float* yp = has_y ? static_cast<const float*>(y->ptr) : nullptr;
+      float* dp = static_cast<float*>(d->ptr);
+      const float qf = static_cast<float>(q);
+      host_blocks(t, count, [&](uint64_t lo, uint64_t hi, int) { host_map_f32(op, xp, yp, dp, lo, hi, qf); });
+    } else {
+      return fail(TS_E_UNSUPPORTED, "host targets support binary64 and binary32 storage");
+    }
+    return TS_OK;
+  }
+  if ((st = use_device(t->device)) != TS_OK) return st;
   const uintptr_t ya = has_y ? reinterpret_cast<uintptr_t>(y->ptr) : 0;
   const int cls = align_class(reinterpret_cast<uintptr_t>(x->ptr), has_y ? &ya : nullptr,
                               reinterpret_cast<uintptr_t>(d->ptr));
@@ -333,6 +373,7 @@ ts_kernel_cfg batch_cfg(const ts_batch_s* b, int op) {
 
 int check_batch_exec(ts_target_s* t, ts_batch_s* b) {
   if (!ok_target(t)) return fail(TS_E_INVALID, "invalid target handle");
+  if (t->host) return host_only_gpu("batched execution");
   if (!ok_batch(b)) return fail(TS_E_INVALID, "invalid batch handle");
   if (b->device != t->device)
     return fail(TS_E_PLACEMENT, "batch is placed on device %d, the executor runs on device %d",
@@ -477,9 +518,70 @@ int create_target(int device, void* hip_stream, bool owned, ts_target* out) {
   return TS_OK;
 }
 
+int create_host_target(const int* cpus, int ncpus, ts_target* out) {
+  if (!out) return fail(TS_E_INVALID, "NULL out-parameter");
+  if (ncpus < 0 || (ncpus > 0 && !cpus)) return fail(TS_E_INVALID, "bad CPU list");
+  std::vector<int> list;
+  if (ncpus > 0) {
+    const std::vector<int> allowed = host_allowed_cpus();
+    for (int i = 0; i < ncpus; ++i) {
+      if (std::find(allowed.begin(), allowed.end(), cpus[i]) == allowed.end())
+        return fail(TS_E_INVALID, "CPU %d is not in the process's affinity set", cpus[i]);
+      list.push_back(cpus[i]);
+    }
+  } else {
+    for (const auto& dom : host_domains()) list.insert(list.end(), dom.begin(), dom.end());
+  }
+  if (list.empty()) return fail(TS_E_INVALID, "no CPU to run on");
+  if (list.size() > 4096) return fail(TS_E_INVALID, "too many CPUs");
+  ts_target_s* t = new ts_target_s();
+  t->device = kHostDevice;
+  t->host = true;
+  t->pool = new HostPool(list);
+  t->stream = nullptr;
+  t->owns_stream = false;
+  t->info = ts_device_info{};
+  t->info.device = kHostDevice;
+  t->info.compute_units = static_cast<int>(list.size());
+  const long pages = sysconf(_SC_PHYS_PAGES), page = sysconf(_SC_PAGESIZE);
+  t->info.hbm_bytes = pages > 0 && page > 0 ? static_cast<uint64_t>(pages) * static_cast<uint64_t>(page) : 0;
+  t->info.peak_bytes_per_s = 0.0;  // not known for the host
+  std::snprintf(t->info.arch, sizeof t->info.arch, "host");
+  std::snprintf(t->info.name, sizeof t->info.name, "host CPUs (%zu pinned workers)", list.size());
+  t->magic = kTargetMagic;
+  *out = t;
+  return TS_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int ts_target_create_host(const int* cpus, int ncpus, ts_target* out) {
+  TS_GUARD_BEGIN
+  return create_host_target(cpus, ncpus, out);
+  TS_GUARD_END
+}
+
+int ts_host_numa_domains(int* count) {
+  TS_GUARD_BEGIN
+  if (!count) return fail(TS_E_INVALID, "NULL out-parameter");
+  *count = static_cast<int>(host_domains().size());
+  return TS_OK;
+  TS_GUARD_END
+}
+
+int ts_host_domain_cpus(int domain, int* cpus, int cap, int* count) {
+  TS_GUARD_BEGIN
+  if (!count || cap < 0 || (cap > 0 && !cpus)) return fail(TS_E_INVALID, "bad arguments");
+  const auto doms = host_domains();
+  if (domain < 0 || domain >= static_cast<int>(doms.size())) return fail(TS_E_INVALID, "no such domain");
+  const auto& d = doms[static_cast<size_t>(domain)];
+  for (int i = 0; i < cap && i < static_cast<int>(d.size()); ++i) cpus[i] = d[static_cast<size_t>(i)];
+  *count = static_cast<int>(d.size());
+  return TS_OK;
+  TS_GUARD_END
+}
 
 int ts_target_create(int device, void* hip_stream, ts_target* out) {
   TS_GUARD_BEGIN
@@ -496,6 +598,12 @@ int ts_target_create_owned(int device, ts_target* out) {
 int ts_target_destroy(ts_target t) {
   if (!t) return TS_OK;
   if (!ok_target(t)) return fail(TS_E_INVALID, "invalid target handle");
+  if (t->host) {
+    delete t->pool;
+    t->magic = kDead;
+    delete t;
+    return TS_OK;
+  }
   (void)use_device(t->device);
   (void)hipStreamSynchronize(t->stream);
   (void)hipFree(t->scratch);
@@ -508,6 +616,7 @@ int ts_target_destroy(ts_target t) {
 
 int ts_target_synchronize(ts_target t) {
   if (!ok_target(t)) return fail(TS_E_INVALID, "invalid target handle");
+  if (t->host) return TS_OK;  // host calls complete before they return
   int st = use_device(t->device);
   if (st != TS_OK) return st;
   TS_HIP(hipStreamSynchronize(t->stream));
@@ -522,12 +631,17 @@ int ts_target_info(ts_target t, ts_device_info* out) {
 
 int ts_target_stream(ts_target t, void** out) {
   if (!ok_target(t) || !out) return fail(TS_E_INVALID, "invalid target handle or NULL out");
+  if (t->host) return host_only_gpu("a stream");
   *out = t->stream;
   return TS_OK;
 }
 
 int ts_target_then(ts_target t, void (*fn)(void*), void* user) {
   if (!ok_target(t) || !fn) return fail(TS_E_INVALID, "invalid target handle or NULL callback");
+  if (t->host) {  // all earlier work has completed: run the continuation now
+    fn(user);
+    return TS_OK;
+  }
   int st = use_device(t->device);
   if (st != TS_OK) return st;
   TS_HIP(hipLaunchHostFunc(t->stream, fn, user));
@@ -543,11 +657,19 @@ int ts_array_alloc(ts_target t, ts_dtype dtype, size_t n, size_t offset_elems, t
   if (!valid_dtype(dtype)) return fail(TS_E_INVALID, "unknown dtype %d", static_cast<int>(dtype));
   const size_t es = dtype_size(dtype);
   if (n > (SIZE_MAX / es) - offset_elems - 1) return fail(TS_E_INVALID, "size overflow");
-  int st = use_device(t->device);
-  if (st != TS_OK) return st;
   void* base = nullptr;
   const size_t bytes = (n + offset_elems) * es;
-  if (bytes > 0) {
+  if (t->host) {
+    // Pages are not touched here: bulk construction (ts_fill*) writes each
+    // block from its own worker, which places it on that worker's node.
+    if (bytes > 0) {
+      const size_t rounded = (bytes + 4095) / 4096 * 4096;
+      base = std::aligned_alloc(4096, rounded);
+      if (!base) return fail(TS_E_OOM, "host allocation of %zu bytes failed", rounded);
+    }
+  } else if (bytes > 0) {
+    int st = use_device(t->device);
+    if (st != TS_OK) return st;
     const hipError_t e = hipMalloc(&base, bytes);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc");
     if (reinterpret_cast<uintptr_t>(base) % 256 != 0) {
@@ -576,7 +698,16 @@ int ts_array_wrap(ts_target t, ts_dtype dtype, void* dev_ptr, size_t n, ts_array
   if (n > 0 && !dev_ptr) return fail(TS_E_INVALID, "NULL pointer with n > 0");
   if (reinterpret_cast<uintptr_t>(dev_ptr) % es != 0)
     return fail(TS_E_INVALID, "pointer not aligned to the element size (%zu bytes)", es);
-  if (n > 0) {
+  if (n > 0 && t->host) {
+    // Host targets borrow host memory: refuse memory the HIP runtime knows
+    // as device memory (an unknown pointer is ordinary host memory).
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof attr);
+    const hipError_t e = hipPointerGetAttributes(&attr, dev_ptr);
+    if (e != hipSuccess) (void)hipGetLastError();
+    else if (attr.type == hipMemoryTypeDevice)
+      return fail(TS_E_PLACEMENT, "pointer is device memory; a host target needs host memory");
+  } else if (n > 0) {
     int st = use_device(t->device);
     if (st != TS_OK) return st;
     hipPointerAttribute_t attr;
@@ -607,7 +738,9 @@ int ts_array_wrap(ts_target t, ts_dtype dtype, void* dev_ptr, size_t n, ts_array
 int ts_array_free(ts_array a) {
   if (!a) return TS_OK;
   if (!ok_array(a)) return fail(TS_E_INVALID, "invalid array handle");
-  if (a->owned_base) {
+  if (a->owned_base && a->device == kHostDevice) {
+    std::free(a->owned_base);
+  } else if (a->owned_base) {
     (void)use_device(a->device);
     (void)hipFree(a->owned_base);
   }
@@ -627,6 +760,17 @@ int ts_array_info(ts_array a, void** ptr, size_t* n, ts_dtype* dtype) {
 int ts_fill(ts_array a, double value) {
   if (!ok_array(a) || !ok_target(a->target)) return fail(TS_E_INVALID, "invalid array handle");
   if (a->n == 0) return TS_OK;
+  if (a->target->host) {
+    if (a->dtype == TS_F64)
+      host_blocks(a->target, a->n, [&](uint64_t lo, uint64_t hi, int) { host_fill_f64(static_cast<double*>(a->ptr), lo, hi, value); });
+    else if (a->dtype == TS_F32)
+      host_blocks(a->target, a->n, [&](uint64_t lo, uint64_t hi, int) {
+        host_fill_f32(static_cast<float*>(a->ptr), lo, hi, static_cast<float>(value));
+      });
+    else
+      return fail(TS_E_UNSUPPORTED, "host targets support binary64 and binary32 storage");
+    return TS_OK;
+  }
   int st = use_device(a->device);
   if (st != TS_OK) return st;
   const hipError_t e = launch_fill_const(a->dtype, a->ptr, a->n, value, a->target->stream);
@@ -638,6 +782,20 @@ int ts_fill_uniform(ts_array a, uint64_t seed, uint64_t stream_id, uint64_t firs
   if (!ok_array(a) || !ok_target(a->target)) return fail(TS_E_INVALID, "invalid array handle");
   if (stream_id >= (1ull << 16)) return fail(TS_E_INVALID, "stream_id must be below 2^16");
   if (a->n == 0) return TS_OK;
+  if (a->target->host) {
+    const uint64_t state0 = seed ^ (stream_id << 48);
+    if (a->dtype == TS_F64)
+      host_blocks(a->target, a->n, [&](uint64_t lo, uint64_t hi, int) {
+        host_fill_uniform_f64(static_cast<double*>(a->ptr), lo, hi, state0, first_index);
+      });
+    else if (a->dtype == TS_F32)
+      host_blocks(a->target, a->n, [&](uint64_t lo, uint64_t hi, int) {
+        host_fill_uniform_f32(static_cast<float*>(a->ptr), lo, hi, state0, first_index);
+      });
+    else
+      return fail(TS_E_UNSUPPORTED, "host targets support binary64 and binary32 storage");
+    return TS_OK;
+  }
   int st = use_device(a->device);
   if (st != TS_OK) return st;
   const hipError_t e =
@@ -652,6 +810,10 @@ int ts_copy_from_host(ts_array dst, const void* src, size_t n) {
                               static_cast<unsigned long long>(dst->n));
   if (n == 0) return TS_OK;
   if (!src) return fail(TS_E_INVALID, "NULL host pointer");
+  if (dst->target->host) {
+    std::memcpy(dst->ptr, src, n * dtype_size(dst->dtype));
+    return TS_OK;
+  }
   int st = use_device(dst->device);
   if (st != TS_OK) return st;
   TS_HIP(hipMemcpyAsync(dst->ptr, src, n * dtype_size(dst->dtype), hipMemcpyHostToDevice,
@@ -665,6 +827,10 @@ int ts_copy_to_host(void* dst, ts_array src, size_t n) {
                               static_cast<unsigned long long>(src->n));
   if (n == 0) return TS_OK;
   if (!dst) return fail(TS_E_INVALID, "NULL host pointer");
+  if (src->target->host) {
+    std::memcpy(dst, src->ptr, n * dtype_size(src->dtype));
+    return TS_OK;
+  }
   int st = use_device(src->device);
   if (st != TS_OK) return st;
   TS_HIP(hipMemcpyAsync(dst, src->ptr, n * dtype_size(src->dtype), hipMemcpyDeviceToHost,
@@ -728,6 +894,25 @@ int ts_checksum(ts_target t, ts_array x, double expected, ts_checksum_out* out) 
     *out = ts_checksum_out{0.0, 0.0, 0.0, 0};
     return TS_OK;
   }
+  if (t->host) {
+    if (x->dtype != TS_F64 && x->dtype != TS_F32)
+      return fail(TS_E_UNSUPPORTED, "host targets support binary64 and binary32 storage");
+    std::vector<HostPart> parts(static_cast<size_t>(t->pool->size()));
+    host_blocks(t, x->n, [&](uint64_t lo, uint64_t hi, int w) {
+      parts[static_cast<size_t>(w)] = x->dtype == TS_F64
+          ? host_checksum_f64(static_cast<const double*>(x->ptr), lo, hi, expected)
+          : host_checksum_f32(static_cast<const float*>(x->ptr), lo, hi, expected);
+    });
+    ts_checksum_out r{0.0, 0.0, std::nan(""), 0};
+    for (const HostPart& p : parts) {  // fixed order: worker 0, 1, ...
+      r.sum += p.sum;
+      r.abs_dev_sum += p.absdev;
+      r.max_abs_dev = std::fmax(r.max_abs_dev, p.maxdev);
+      r.mismatches += p.mism;
+    }
+    *out = r;
+    return TS_OK;
+  }
   int st = use_device(t->device);
   if (st != TS_OK) return st;
   hipError_t e = launch_checksum(x->dtype, x->ptr, x->n, expected, t->scratch, t->stream);
@@ -751,6 +936,19 @@ int ts_mismatch_count(ts_target t, ts_array x, ts_array ref, uint64_t* out) {
   if (ref->n < x->n) return fail(TS_E_SHAPE, "ref holds fewer elements than x");
   if (x->n == 0) {
     *out = 0;
+    return TS_OK;
+  }
+  if (t->host) {
+    if (x->dtype != TS_F64 && x->dtype != TS_F32)
+      return fail(TS_E_UNSUPPORTED, "host targets support binary64 and binary32 storage");
+    std::vector<uint64_t> parts(static_cast<size_t>(t->pool->size()), 0);
+    const size_t es = dtype_size(x->dtype);
+    host_blocks(t, x->n, [&](uint64_t lo, uint64_t hi, int w) {
+      parts[static_cast<size_t>(w)] = host_mismatch(x->ptr, ref->ptr, lo, hi, es, x->dtype == TS_F64);
+    });
+    uint64_t total = 0;
+    for (uint64_t c : parts) total += c;
+    *out = total;
     return TS_OK;
   }
   int st = use_device(t->device);
@@ -807,6 +1005,7 @@ int ts_autotune(ts_target t, ts_op op, ts_dtype dtype, size_t n, size_t offset_e
                 ts_kernel_cfg* best, double* best_bytes_per_s) {
   TS_GUARD_BEGIN
   if (!ok_target(t)) return fail(TS_E_INVALID, "invalid target handle");
+  if (t->host) return host_only_gpu("tuning");
   if (!valid_op(op) || !valid_dtype(dtype) || n == 0)
     return fail(TS_E_INVALID, "bad op, dtype or zero size");
   int st = use_device(t->device);
@@ -921,6 +1120,13 @@ int ts_time_op(ts_target exec, ts_op op, ts_array x, ts_array y, ts_array dst, d
   uint64_t count = 0;
   int st = check_exec_arrays(exec, op, x, y, dst, &count);
   if (st != TS_OK) return st;
+  if (exec->host) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int r = 0; r < reps && st == TS_OK; ++r) st = run_map(exec, op, x, y, dst, q);
+    if (st != TS_OK) return st;
+    *ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return TS_OK;
+  }
   if ((st = use_device(exec->device)) != TS_OK) return st;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   TS_HIP(hipEventCreate(&e0));
@@ -951,6 +1157,7 @@ int ts_batch_create(ts_target t, ts_dtype dtype, const ts_batch_desc* descs, siz
                     ts_batch* out) {
   TS_GUARD_BEGIN
   if (!ok_target(t) || !out) return fail(TS_E_INVALID, "invalid target handle or NULL out");
+  if (t->host) return host_only_gpu("batched execution");
   if (!valid_dtype(dtype)) return fail(TS_E_INVALID, "unknown dtype");
   if (count > 0 && !descs) return fail(TS_E_INVALID, "NULL descriptors");
   int st = use_device(t->device);
@@ -1133,6 +1340,7 @@ namespace {
 template <class Body>
 int capture(ts_target_s* t, Body&& body, ts_graph* out) {
   if (!out) return fail(TS_E_INVALID, "NULL out");
+  if (t->host) return host_only_gpu("graph capture");
   if (t->stream == nullptr)
     return fail(TS_E_UNSUPPORTED, "graph capture needs a target with a non-default stream");
   int st = use_device(t->device);
@@ -1195,6 +1403,7 @@ int ts_graph_capture_arrays_iteration(ts_target t, ts_array a, ts_array b, ts_ar
                                       ts_graph* out) {
   TS_GUARD_BEGIN
   if (!ok_target(t)) return fail(TS_E_INVALID, "invalid target handle");
+  if (t->host) return host_only_gpu("graph capture");
   return capture(t, [&]() { return ts_stream_iteration(t, a, b, c, q); }, out);
   TS_GUARD_END
 }
@@ -1202,6 +1411,7 @@ int ts_graph_capture_arrays_iteration(ts_target t, ts_array a, ts_array b, ts_ar
 int ts_graph_launch(ts_target t, ts_graph g, int repeats) {
   TS_GUARD_BEGIN
   if (!ok_target(t) || !ok_graph(g)) return fail(TS_E_INVALID, "invalid target or graph handle");
+  if (t->host) return host_only_gpu("graph launch");
   if (repeats < 0) return fail(TS_E_INVALID, "negative repeat count");
   if (g->device != t->device) return fail(TS_E_PLACEMENT, "graph belongs to another device");
   int st = use_device(t->device);
@@ -1253,6 +1463,7 @@ int ts_event_destroy(ts_event e) {
 
 int ts_event_record(ts_event e, ts_target t) {
   if (!ok_event(e) || !ok_target(t)) return fail(TS_E_INVALID, "invalid event or target handle");
+  if (t->host) return host_only_gpu("events");
   int st = use_device(t->device);
   if (st != TS_OK) return st;
   TS_HIP(hipEventRecord(e->ev, t->stream));
@@ -1289,11 +1500,20 @@ int ts_event_elapsed_ms(ts_event start, ts_event end, float* ms) {
 int ts_target_async(ts_target t, ts_future* out) {
   TS_GUARD_BEGIN
   if (!ok_target(t) || !out) return fail(TS_E_INVALID, "invalid target handle or NULL out");
-  int st = use_device(t->device);
-  if (st != TS_OK) return st;
   ts_future_s* f = new ts_future_s();
   f->ready = false;
   f->magic = kFutureMagic;
+  if (t->host) {  // host calls complete before they return
+    f->ready = true;
+    *out = f;
+    return TS_OK;
+  }
+  int st = use_device(t->device);
+  if (st != TS_OK) {
+    f->magic = kDead;
+    delete f;
+    return st;
+  }
   const hipError_t e = hipLaunchHostFunc(t->stream, future_ready_cb, f);
   if (e != hipSuccess) {
     f->magic = kDead;

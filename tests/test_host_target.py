@@ -1,0 +1,126 @@
+"""The host-CPU target (the paper's NUMA back-end, Section 4.1) through the
+C ABI: pinned workers over equal contiguous blocks.  Results must equal the
+CPU oracle bit for bit whatever the number of workers; runs without a GPU."""
+import numpy as np
+import pytest
+
+import oracle
+import tsgen
+
+OPS = ("copy", "scale", "add", "triad")
+E_UNSUPPORTED, E_SHAPE, E_ALIAS, E_INVALID = -8, -2, -5, -1
+
+
+@pytest.fixture(scope="module")
+def ts():
+    import paper_2206_06302_amd as ts
+    return ts
+
+
+def _cpus(ts, k):
+    allowed = [c for d in ts.host_numa_domains() for c in d]
+    return allowed[:k] if k <= len(allowed) else allowed
+
+
+@pytest.mark.parametrize("workers", [1, 3, 8])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [0, 1, 2, 7, 1000, 100003])
+def test_host_maps_match_oracle(ts, workers, dtype, n):
+    tgt = ts.Target.host(_cpus(ts, workers))
+    x = tsgen.uniform_array(5, 0, n, dtype)
+    y = tsgen.uniform_array(5, 1, n, dtype)
+    for op in OPS:
+        for q in (3.0, -0.1):
+            X = ts.Array.wrap_numpy(tgt, x.copy())
+            Y = ts.Array.wrap_numpy(tgt, y.copy())
+            D = ts.Array.alloc(tgt, dtype, n).fill(0.0)
+            ts.run_op(tgt, op, X, Y, D, q)
+            ref = np.zeros_like(x)
+            oracle.op(oracle.DTYPES[dtype], oracle.OPS[op], x, y if op in ("add", "triad") else None, ref, q)
+            got = D.to_host()
+            assert np.array_equal(got.view(np.uint8), ref.view(np.uint8)), (op, q)
+    tgt.close()
+
+
+@pytest.mark.parametrize("workers", [1, 5])
+def test_host_iteration_matches_oracle_chain(ts, workers):
+    """Random init, 50 iterations (the fused-triad detector length)."""
+    tgt = ts.Target.host(_cpus(ts, workers))
+    n = 65539
+    arrs = [ts.Array.alloc(tgt, "f64", n, offset=1) for _ in range(3)]
+    for k, arr in enumerate(arrs):
+        arr.fill_uniform(2, k)
+    for _ in range(50):
+        ts.stream_iteration(tgt, *arrs, 3.0)
+    host = [tsgen.uniform_array(2, k, n) for k in range(3)]
+    oracle.stream_run(oracle.F64, host[0], host[1], host[2], 3.0, 50)
+    for arr, ref in zip(arrs, host):
+        assert np.array_equal(arr.to_host().view(np.uint64), ref.view(np.uint64))
+    tgt.close()
+
+
+def test_host_closed_form_and_checksum(ts):
+    tgt = ts.Target.host()
+    n = 1 << 20
+    A, B, C = (ts.Array.alloc(tgt, "f64", n) for _ in range(3))
+    A.fill(1.0), B.fill(2.0), C.fill(0.0)
+    for _ in range(10):
+        ts.stream_iteration(tgt, A, B, C, 3.0)
+    for arr, e in zip((A, B, C), (576650390625.0, 115330078125.0, 153773437500.0)):
+        cs = ts.checksum(tgt, arr, e)
+        assert cs["mismatches"] == 0 and cs["max_abs_dev"] == 0.0
+        assert abs(cs["sum"] - e * n) <= n * 2.0 ** -53 * e * n  # rounding of the block sums
+    x = tsgen.uniform_array(9, 0, 12345)
+    X = ts.Array.wrap_numpy(tgt, x)
+    cs = ts.checksum(tgt, X, float(x[7]))
+    ref = oracle.checksum(oracle.F64, x, float(x[7]))
+    assert cs["mismatches"] == ref.mismatches and cs["max_abs_dev"] == ref.max_abs_dev
+    assert abs(cs["sum"] - ref.sum) <= x.size * 2.0 ** -53 * float(np.abs(x).sum())
+    r = x.copy()
+    r[[0, 100, 12344]] += 1.0
+    assert ts.mismatch_count(tgt, X, ts.Array.wrap_numpy(tgt, r)) == 3
+    tgt.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_host_fill_uniform_matches_generator(ts, dtype):
+    tgt = ts.Target.host(_cpus(ts, 3))
+    A = ts.Array.alloc(tgt, dtype, 100001)
+    A.fill_uniform(7, 2, 99)
+    assert np.array_equal(A.to_host().view(np.uint8), tsgen.uniform_array(7, 2, 100001, dtype, start=99).view(np.uint8))
+    tgt.close()
+
+
+def test_host_target_limits(ts):
+    tgt = ts.Target.host(_cpus(ts, 2))
+    with pytest.raises(ts.TSError) as e:
+        ts.Array.alloc(tgt, "bf16", 10).fill(1.0)
+    assert e.value.status == E_UNSUPPORTED
+    a, b = ts.Array.alloc(tgt, "f64", 100), ts.Array.alloc(tgt, "f64", 99)
+    with pytest.raises(ts.TSError) as e:
+        ts.copy(tgt, a, b)
+    assert e.value.status == E_SHAPE
+    with pytest.raises(ts.TSError) as e:
+        ts.Graph.capture_arrays_iteration(tgt, a, a, a)
+    assert e.value.status == E_UNSUPPORTED
+    with pytest.raises(ts.TSError) as e:
+        ts.Batch(tgt, "f64", [])
+    assert e.value.status == E_UNSUPPORTED
+    with pytest.raises(ts.TSError) as e:
+        ts.autotune(tgt, "triad", "f64", 1000)
+    assert e.value.status == E_UNSUPPORTED
+    with pytest.raises(ts.TSError):
+        ts.Event().record(tgt)
+    with pytest.raises(ts.TSError):
+        tgt.stream_handle()
+    with pytest.raises(ts.TSError):
+        ts.Target.host([100000])
+    done = []
+    tgt.then(lambda: done.append(1))
+    assert done == [1]
+    f = tgt.async_()
+    assert f.ready()
+    f.wait()
+    ms = ts.time_op(tgt, "triad", a, a, a, 3.0, reps=3)
+    assert ms >= 0
+    tgt.close()
