@@ -69,7 +69,11 @@ typedef enum {
     TS_E_UNSUPPORTED = -8  /* valid request this build cannot serve           */
 } ts_status;
 
-typedef enum { TS_F64 = 0, TS_F32 = 1, TS_BF16 = 2, TS_F16 = 3 } ts_dtype;
+/* Storage types.  TS_U8 (bytes, e.g. characters) is accepted by the array,
+ * host-copy and transform calls only; the STREAM maps, fills, checksums,
+ * batches and tuning take the four floating-point types (TS_E_UNSUPPORTED
+ * otherwise). */
+typedef enum { TS_F64 = 0, TS_F32 = 1, TS_BF16 = 2, TS_F16 = 3, TS_U8 = 4 } ts_dtype;
 
 /* The four maps of Listing 4, in the order the benchmark runs them. */
 typedef enum { TS_COPY = 0, TS_SCALE = 1, TS_ADD = 2, TS_TRIAD = 3 } ts_op;
@@ -80,6 +84,7 @@ typedef struct ts_batch_s *ts_batch;
 typedef struct ts_graph_s *ts_graph;
 typedef struct ts_event_s *ts_event;
 typedef struct ts_future_s *ts_future;
+typedef struct ts_transform_s *ts_transform;
 
 /* ------------------------------------------------------------------------ */
 /* Errors and version                                                        */
@@ -409,6 +414,33 @@ TS_API int ts_future_wait(ts_future future);
 TS_API int ts_future_ready(ts_future future);
 /* Release the future; waits for its callback first if it is still pending. */
 TS_API int ts_future_destroy(ts_future future);
+
+/* ------------------------------------------------------------------------ */
+/* Generic transforms: a user expression compiled at run time (hipRTC)       */
+/* ------------------------------------------------------------------------ */
+/* The paper's GPU executor runs any device callable (Section 4.2) and its
+ * hello-world example transforms a vector of chars with to_upper (Section
+ * 3.4, Listing 3).  Here the callable is the text of a C++ expression in the
+ * element values `x` (and `y` when n_inputs == 2) and the scalar `q`, all of
+ * the storage type's arithmetic type: double (TS_F64), float (TS_F32,
+ * TS_BF16, TS_F16; 16-bit values widen exactly and the result is rounded to
+ * nearest-even), int (TS_U8).  The result is converted to the storage type:
+ * dst[j] = expr(x[j], y[j], q).  Nothing is contracted (-ffp-contract=off);
+ * __builtin_fma(q, y, x) is a fused triad.  The expression is compiled once
+ * per (expression, inputs, type, GPU architecture) and cached for the life
+ * of the process.  Errors: TS_E_INVALID with the compiler's log when the
+ * expression does not compile; TS_E_UNSUPPORTED without hipRTC or on a host
+ * target.  ts_transform_apply follows the rules of the algorithm calls
+ * (count = n of x; shapes, types, placement, aliasing) and is asynchronous
+ * on the executor's stream; work using a transform must have finished
+ * before it is destroyed. */
+TS_API int ts_transform_create(ts_target target, const char *expr, int n_inputs,
+                               ts_dtype dtype, ts_transform *out);
+TS_API int ts_transform_apply(ts_target exec, ts_transform transform,
+                              ts_array x, ts_array y, ts_array dst, double q);
+/* Compiler messages of the transform's compilation (may be empty). */
+TS_API int ts_transform_log(ts_transform transform, const char **log);
+TS_API int ts_transform_destroy(ts_transform transform);
 
 #ifdef __cplusplus
 }

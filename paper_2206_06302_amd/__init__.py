@@ -33,12 +33,13 @@ if len(_runtimes) > 1:
     raise ImportError("two HIP runtimes are loaded in this process (%s); streams would not be "
                       "shared between torch and libtstream" % ", ".join(_runtimes))
 
-DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "u8": 4}
 DTYPE_NAMES = {v: k for k, v in DTYPES.items()}
-TORCH_DTYPES = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+TORCH_DTYPES = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16,
+                "u8": torch.uint8}
 _FROM_TORCH = {v: k for k, v in TORCH_DTYPES.items()}
-ELEM_SIZE = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
-NP_STORAGE = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16, "f16": np.uint16}
+ELEM_SIZE = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2, "u8": 1}
+NP_STORAGE = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16, "f16": np.uint16, "u8": np.uint8}
 OPS = {"copy": 0, "scale": 1, "add": 2, "triad": 3}
 ALIGN_16, ALIGN_SHARED, ALIGN_MIXED = 0, 1, 2
 # STREAM bytes per element: copy/scale move two arrays, add/triad three.
@@ -528,6 +529,39 @@ class Event:
     def close(self) -> None:
         if getattr(self, "handle", None):
             lib.ts_event_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Transform:
+    """dst[j] = expr(x[j], y[j], q): a C++ expression compiled at run time for
+    the target's GPU (the executor runs any device callable, Section 4.2;
+    e.g. the hello-world to_upper of Listing 3 over "u8" characters)."""
+
+    def __init__(self, target: Target, expr: str, n_inputs: int = 1, dtype="f64"):
+        h = ctypes.c_void_p()
+        _check(lib.ts_transform_create(target.handle, expr.encode(), int(n_inputs), _dt(dtype), ctypes.byref(h)))
+        self.handle = h
+        self.n_inputs = int(n_inputs)
+        self.dtype = dtype if isinstance(dtype, str) else DTYPE_NAMES[_dt(dtype)]
+
+    def __call__(self, target: Target, x: Array, dst: Array, y: Array | None = None, q: float = 0.0) -> None:
+        _check(lib.ts_transform_apply(target.handle, self.handle, x.handle, y.handle if y is not None else None,
+                                      dst.handle, float(q)))
+
+    def log(self) -> str:
+        p = ctypes.c_char_p()
+        _check(lib.ts_transform_log(self.handle, ctypes.byref(p)))
+        return p.value.decode() if p.value else ""
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib.ts_transform_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

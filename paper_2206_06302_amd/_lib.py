@@ -149,6 +149,10 @@ PROTOTYPES = {
     "ts_future_wait": [H],
     "ts_future_ready": [H],
     "ts_future_destroy": [H],
+    "ts_transform_create": [H, ctypes.c_char_p, I, I, ctypes.POINTER(H)],
+    "ts_transform_apply": [H, H, H, H, H, D],
+    "ts_transform_log": [H, ctypes.POINTER(ctypes.c_char_p)],
+    "ts_transform_destroy": [H],
 }
 RESTYPES = {"ts_last_error": ctypes.c_char_p}
 

@@ -29,7 +29,7 @@ LIB = os.path.join(PKG, "libtstream.so")
 ARCH = os.environ.get("TS_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["kern_f64.hip", "kern_f32.hip", "kern_bf16.hip", "kern_f16.hip", "kern_aux.hip",
-           "capi.cpp", "tune.cpp", "host_target.cpp"]
+           "capi.cpp", "tune.cpp", "host_target.cpp", "transform.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
@@ -82,7 +82,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
                 f.result()
         tmp_lib = LIB + ".tmp%d" % os.getpid()
         cmd = [cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp_lib, *objs,
-               "-Wl,-rpath,/opt/rocm/lib", "-Wl,--no-undefined"]
+               "-Wl,-rpath,/opt/rocm/lib", "-Wl,--no-undefined", "-ldl"]
         r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}")

@@ -23,6 +23,7 @@
 
 #include "../../include/tstream.h"
 #include "host_target.hpp"
+#include "ts_handles.hpp"
 #include "ts_internal.hpp"
 #include "tune.hpp"
 
@@ -67,8 +68,6 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(TS_E_INVALID, "internal error");                   \
   }
 
-constexpr uint32_t kTargetMagic = 0x54475431u;  // "TGT1"
-constexpr uint32_t kArrayMagic = 0x41525231u;
 constexpr uint32_t kBatchMagic = 0x42415431u;
 constexpr uint32_t kGraphMagic = 0x47524631u;
 constexpr uint32_t kEventMagic = 0x45564e31u;
@@ -78,27 +77,18 @@ constexpr double kPeakBytesPerS = 8.0e12;  // MI355X HBM3E, the % of peak denomi
 
 }  // namespace
 
-struct ts_target_s {
-  uint32_t magic;
-  int device;  // -1 for a host-CPU target
-  bool host;
-  ts::HostPool* pool;  // host targets: the pinned workers
-  hipStream_t stream;
-  bool owns_stream;
-  ts_device_info info;
-  void* scratch;  // reduction parts + result (kReduceScratchBytes)
-  void* host_result;
-};
-
-struct ts_array_s {
-  uint32_t magic;
-  ts_target_s* target;
-  int device;  // -1: host memory of a host target
-  int dtype;
-  void* ptr;
-  uint64_t n;
-  void* owned_base;
-};
+namespace ts {
+int api_fail(int status, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return status;
+}
+int api_hip_fail(hipError_t e, const char* what) { return hip_fail(e, what); }
+}  // namespace ts
 
 struct ts_batch_s {
   uint32_t magic;
@@ -180,7 +170,9 @@ int use_device(int device) {
   return TS_OK;
 }
 
-bool valid_dtype(int dt) { return dt >= TS_F64 && dt <= TS_F16; }
+// Storage types of arrays (bytes included) and of the STREAM maps.
+bool valid_dtype(int dt) { return dt >= TS_F64 && dt <= TS_U8; }
+bool map_dtype(int dt) { return dt >= TS_F64 && dt <= TS_F16; }
 bool valid_op(int op) { return op >= TS_COPY && op <= TS_TRIAD; }
 
 uint64_t stream_bytes(int op, uint64_t n, size_t es) {
@@ -285,6 +277,7 @@ int run_map(ts_target_s* t, int op, ts_array_s* x, ts_array_s* y, ts_array_s* d,
   uint64_t count = 0;
   int st = check_exec_arrays(t, op, x, y, d, &count);
   if (st != TS_OK) return st;
+  if (!map_dtype(x->dtype)) return fail(TS_E_UNSUPPORTED, "the STREAM maps take floating-point storage");
   if (count == 0) return TS_OK;
   const bool has_y = op == TS_ADD || op == TS_TRIAD;
   if (t->host) {
@@ -759,6 +752,7 @@ int ts_array_info(ts_array a, void** ptr, size_t* n, ts_dtype* dtype) {
 
 int ts_fill(ts_array a, double value) {
   if (!ok_array(a) || !ok_target(a->target)) return fail(TS_E_INVALID, "invalid array handle");
+  if (!map_dtype(a->dtype)) return fail(TS_E_UNSUPPORTED, "fills take floating-point storage");
   if (a->n == 0) return TS_OK;
   if (a->target->host) {
     if (a->dtype == TS_F64)
@@ -780,6 +774,7 @@ int ts_fill(ts_array a, double value) {
 
 int ts_fill_uniform(ts_array a, uint64_t seed, uint64_t stream_id, uint64_t first_index) {
   if (!ok_array(a) || !ok_target(a->target)) return fail(TS_E_INVALID, "invalid array handle");
+  if (!map_dtype(a->dtype)) return fail(TS_E_UNSUPPORTED, "fills take floating-point storage");
   if (stream_id >= (1ull << 16)) return fail(TS_E_INVALID, "stream_id must be below 2^16");
   if (a->n == 0) return TS_OK;
   if (a->target->host) {
@@ -889,6 +884,7 @@ int ts_stream_iteration(ts_target exec, ts_array a, ts_array b, ts_array c, doub
 int ts_checksum(ts_target t, ts_array x, double expected, ts_checksum_out* out) {
   TS_GUARD_BEGIN
   if (!ok_target(t) || !ok_array(x) || !out) return fail(TS_E_INVALID, "invalid handle or NULL out");
+  if (!map_dtype(x->dtype)) return fail(TS_E_UNSUPPORTED, "checksums take floating-point storage");
   if (x->device != t->device) return fail(TS_E_PLACEMENT, "array is not on the executor's device");
   if (x->n == 0) {
     *out = ts_checksum_out{0.0, 0.0, 0.0, 0};
@@ -931,6 +927,7 @@ int ts_mismatch_count(ts_target t, ts_array x, ts_array ref, uint64_t* out) {
   if (!ok_target(t) || !ok_array(x) || !ok_array(ref) || !out)
     return fail(TS_E_INVALID, "invalid handle or NULL out");
   if (x->dtype != ref->dtype) return fail(TS_E_DTYPE, "arrays of different storage types");
+  if (!map_dtype(x->dtype)) return fail(TS_E_UNSUPPORTED, "mismatch counts take floating-point storage");
   if (x->device != t->device || ref->device != t->device)
     return fail(TS_E_PLACEMENT, "array is not on the executor's device");
   if (ref->n < x->n) return fail(TS_E_SHAPE, "ref holds fewer elements than x");
@@ -969,7 +966,7 @@ int ts_mismatch_count(ts_target t, ts_array x, ts_array ref, uint64_t* out) {
 int ts_get_kernel_cfg(ts_op op, ts_dtype dtype, size_t n, int align_class, int batched,
                       ts_kernel_cfg* out) {
   TS_GUARD_BEGIN
-  if (!valid_op(op) || !valid_dtype(dtype) || !out || align_class < 0 || align_class > 2)
+  if (!valid_op(op) || !map_dtype(dtype) || !out || align_class < 0 || align_class > 2)
     return fail(TS_E_INVALID, "bad op, dtype, alignment class or NULL out");
   ts_kernel_cfg c = tune_table().lookup(op, dtype, n, align_class, batched ? 1 : 0);
   if (!batched && c.vec_bytes == 0) c.vec_bytes = static_cast<int32_t>(dtype_size(dtype));
@@ -980,7 +977,7 @@ int ts_get_kernel_cfg(ts_op op, ts_dtype dtype, size_t n, int align_class, int b
 
 int ts_set_kernel_cfg(ts_op op, ts_dtype dtype, int batched, const ts_kernel_cfg* cfg) {
   TS_GUARD_BEGIN
-  if (!valid_op(op) || !valid_dtype(dtype)) return fail(TS_E_INVALID, "bad op or dtype");
+  if (!valid_op(op) || !map_dtype(dtype)) return fail(TS_E_INVALID, "bad op or dtype");
   if (cfg) {
     const std::string why = cfg_problem(*cfg, batched ? 1 : 0);
     if (!why.empty()) return fail(TS_E_INVALID, "invalid configuration: %s", why.c_str());
@@ -1006,7 +1003,7 @@ int ts_autotune(ts_target t, ts_op op, ts_dtype dtype, size_t n, size_t offset_e
   TS_GUARD_BEGIN
   if (!ok_target(t)) return fail(TS_E_INVALID, "invalid target handle");
   if (t->host) return host_only_gpu("tuning");
-  if (!valid_op(op) || !valid_dtype(dtype) || n == 0)
+  if (!valid_op(op) || !map_dtype(dtype) || n == 0)
     return fail(TS_E_INVALID, "bad op, dtype or zero size");
   int st = use_device(t->device);
   if (st != TS_OK) return st;
@@ -1159,6 +1156,7 @@ int ts_batch_create(ts_target t, ts_dtype dtype, const ts_batch_desc* descs, siz
   if (!ok_target(t) || !out) return fail(TS_E_INVALID, "invalid target handle or NULL out");
   if (t->host) return host_only_gpu("batched execution");
   if (!valid_dtype(dtype)) return fail(TS_E_INVALID, "unknown dtype");
+  if (!map_dtype(dtype)) return fail(TS_E_UNSUPPORTED, "batches take floating-point storage");
   if (count > 0 && !descs) return fail(TS_E_INVALID, "NULL descriptors");
   int st = use_device(t->device);
   if (st != TS_OK) return st;

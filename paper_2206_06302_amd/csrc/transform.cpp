@@ -1,0 +1,266 @@
+// transform.cpp -- element-wise transforms with a user expression, compiled
+// at run time with hipRTC for the target's GPU.
+//
+// The paper's GPU executor runs any device callable (Section 4.2), and its
+// hello-world example transforms a vector of chars with to_upper (Section
+// 3.4, Listing 3).  A C ABI cannot carry a callable, so the callable arrives
+// as the text of a C++ expression in x, y and q; the library wraps it in a
+// grid-stride kernel, compiles it once per (expression, inputs, storage
+// type, architecture) and launches it on the executing target's stream.
+// hipRTC is opened lazily (dlopen), so it is needed only when transforms
+// are used.
+#include <dlfcn.h>
+#include <hip/hip_runtime_api.h>
+#include <hip/hiprtc.h>
+
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/tstream.h"
+#include "ts_handles.hpp"
+#include "ts_layout.hpp"
+
+using namespace ts;
+
+namespace {
+
+constexpr uint32_t kTransformMagic = 0x54524631u;
+
+// The hipRTC entry points used here, resolved from the loaded library.
+struct Rtc {
+  hiprtcResult (*create)(hiprtcProgram*, const char*, const char*, int, const char**, const char**);
+  hiprtcResult (*compile)(hiprtcProgram, int, const char**);
+  hiprtcResult (*log_size)(hiprtcProgram, size_t*);
+  hiprtcResult (*log)(hiprtcProgram, char*);
+  hiprtcResult (*code_size)(hiprtcProgram, size_t*);
+  hiprtcResult (*code)(hiprtcProgram, char*);
+  hiprtcResult (*destroy)(hiprtcProgram*);
+  const char* (*error_string)(hiprtcResult);
+  bool ok = false;
+  std::string why;
+};
+
+const Rtc& rtc() {
+  static Rtc r = [] {
+    Rtc x;
+    void* h = dlopen("libhiprtc.so.7", RTLD_NOW | RTLD_GLOBAL);
+    if (!h) h = dlopen("/opt/rocm/lib/libhiprtc.so.7", RTLD_NOW | RTLD_GLOBAL);
+    if (!h) {
+      x.why = std::string("hipRTC is not available: ") + dlerror();
+      return x;
+    }
+    bool all = true;
+    auto get = [&](auto& fn, const char* name) {
+      fn = reinterpret_cast<std::remove_reference_t<decltype(fn)>>(dlsym(h, name));
+      all = all && fn != nullptr;
+    };
+    get(x.create, "hiprtcCreateProgram");
+    get(x.compile, "hiprtcCompileProgram");
+    get(x.log_size, "hiprtcGetProgramLogSize");
+    get(x.log, "hiprtcGetProgramLog");
+    get(x.code_size, "hiprtcGetCodeSize");
+    get(x.code, "hiprtcGetCode");
+    get(x.destroy, "hiprtcDestroyProgram");
+    get(x.error_string, "hiprtcGetErrorString");
+    x.ok = all;
+    if (!all) x.why = "hipRTC library lacks an expected entry point";
+    return x;
+  }();
+  return r;
+}
+
+// Storage and arithmetic types of each storage format inside the generated
+// source.  The 16-bit formats widen exactly to float and narrow by
+// round-to-nearest-even, as the built-in kernels do.
+struct TypeText {
+  const char* storage;
+  const char* arith;
+  const char* widen;   // expression of `v` (storage) giving the arithmetic value
+  const char* narrow;  // expression of `r` (arithmetic) giving the storage value
+};
+
+TypeText type_text(int dtype) {
+  switch (dtype) {
+    case TS_F64: return {"double", "double", "v", "r"};
+    case TS_F32: return {"float", "float", "v", "r"};
+    case TS_BF16:
+      return {"unsigned short", "float", "__builtin_bit_cast(float, (unsigned int)v << 16)",
+              "__builtin_bit_cast(unsigned short, (__bf16)ts_keep(r))"};
+    case TS_F16:
+      return {"unsigned short", "float", "(float)__builtin_bit_cast(_Float16, v)",
+              "__builtin_bit_cast(unsigned short, (_Float16)ts_keep(r))"};
+    default: return {"unsigned char", "int", "(int)v", "(unsigned char)(r)"};
+  }
+}
+
+std::string kernel_source(const std::string& expr, int n_inputs, int dtype) {
+  const TypeText t = type_text(dtype);
+  std::string s;
+  s += "typedef " + std::string(t.storage) + " ts_store_t;\n";
+  s += "typedef " + std::string(t.arith) + " ts_arith_t;\n";
+  s += "__device__ inline float ts_keep(float v) { asm(\"\" : \"+v\"(v)); return v; }\n";
+  s += "__device__ inline ts_arith_t ts_widen(ts_store_t v) { return " + std::string(t.widen) + "; }\n";
+  s += "__device__ inline ts_store_t ts_narrow(ts_arith_t r) { return " + std::string(t.narrow) + "; }\n";
+  s += "extern \"C\" __global__ void ts_transform_kernel(const ts_store_t* __restrict__ xs,\n"
+       "    const ts_store_t* __restrict__ ys, ts_store_t* ds, double qd, unsigned long long n) {\n"
+       "  const ts_arith_t q = (ts_arith_t)qd;\n"
+       "  (void)q;\n"
+       "  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;\n"
+       "  for (unsigned long long j = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; j < n;\n"
+       "       j += stride) {\n"
+       "    const ts_arith_t x = ts_widen(xs[j]);\n";
+  if (n_inputs == 2) s += "    const ts_arith_t y = ts_widen(ys[j]);\n";
+  s += "    ds[j] = ts_narrow((ts_arith_t)(" + expr + "));\n  }\n}\n";
+  return s;
+}
+
+// Code objects already compiled, by (expression, inputs, type, architecture).
+std::mutex g_cache_mu;
+std::map<std::tuple<std::string, int, int, std::string>, std::shared_ptr<std::vector<char>>> g_code_cache;
+
+}  // namespace
+
+struct ts_transform_s {
+  uint32_t magic;
+  int device;
+  int dtype;
+  int n_inputs;
+  hipModule_t module;
+  hipFunction_t fn;
+  std::string log;
+};
+
+extern "C" {
+
+int ts_transform_create(ts_target t, const char* expr, int n_inputs, ts_dtype dtype, ts_transform* out) {
+  try {
+    if (!ts_ok_target_handle(t) || !expr || !out) return api_fail(TS_E_INVALID, "invalid target, expression or out");
+    if (t->host) return api_fail(TS_E_UNSUPPORTED, "transforms are compiled for GPU targets");
+    if (n_inputs != 1 && n_inputs != 2) return api_fail(TS_E_INVALID, "n_inputs must be 1 or 2");
+    if (dtype < TS_F64 || dtype > TS_U8) return api_fail(TS_E_INVALID, "unknown dtype");
+    const Rtc& r = rtc();
+    if (!r.ok) return api_fail(TS_E_UNSUPPORTED, "%s", r.why.c_str());
+    hipError_t he = hipSetDevice(t->device);
+    if (he != hipSuccess) return api_hip_fail(he, "hipSetDevice");
+    std::string arch = t->info.arch;
+    const std::string arch_name = arch.substr(0, arch.find(':'));
+    const auto key = std::make_tuple(std::string(expr), n_inputs, static_cast<int>(dtype), arch);
+    std::shared_ptr<std::vector<char>> code;
+    std::string log;
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      auto it = g_code_cache.find(key);
+      if (it != g_code_cache.end()) code = it->second;
+    }
+    if (!code) {
+      const std::string src = kernel_source(expr, n_inputs, dtype);
+      hiprtcProgram prog = nullptr;
+      hiprtcResult rr = r.create(&prog, src.c_str(), "ts_transform.hip", 0, nullptr, nullptr);
+      if (rr != HIPRTC_SUCCESS) return api_fail(TS_E_DEVICE, "hiprtcCreateProgram: %s", r.error_string(rr));
+      const std::string arch_opt = "--offload-arch=" + arch_name;
+      const char* opts[] = {arch_opt.c_str(), "-O3", "-ffp-contract=off", "-std=c++17",
+                            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+      rr = r.compile(prog, 8, opts);
+      size_t ls = 0;
+      if (r.log_size(prog, &ls) == HIPRTC_SUCCESS && ls > 1) {
+        log.resize(ls);
+        r.log(prog, &log[0]);
+        log.resize(std::strlen(log.c_str()));
+      }
+      if (rr != HIPRTC_SUCCESS) {
+        r.destroy(&prog);
+        return api_fail(TS_E_INVALID, "expression does not compile: %s", log.empty() ? r.error_string(rr) : log.c_str());
+      }
+      size_t cs = 0;
+      rr = r.code_size(prog, &cs);
+      auto buf = std::make_shared<std::vector<char>>(cs);
+      if (rr == HIPRTC_SUCCESS) rr = r.code(prog, buf->data());
+      r.destroy(&prog);
+      if (rr != HIPRTC_SUCCESS) return api_fail(TS_E_DEVICE, "hiprtcGetCode: %s", r.error_string(rr));
+      code = buf;
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      g_code_cache[key] = code;
+    }
+    hipModule_t mod = nullptr;
+    he = hipModuleLoadData(&mod, code->data());
+    if (he != hipSuccess) return api_hip_fail(he, "hipModuleLoadData");
+    hipFunction_t fn = nullptr;
+    he = hipModuleGetFunction(&fn, mod, "ts_transform_kernel");
+    if (he != hipSuccess) {
+      (void)hipModuleUnload(mod);
+      return api_hip_fail(he, "hipModuleGetFunction");
+    }
+    ts_transform_s* x = new ts_transform_s();
+    x->device = t->device;
+    x->dtype = dtype;
+    x->n_inputs = n_inputs;
+    x->module = mod;
+    x->fn = fn;
+    x->log = log;
+    x->magic = kTransformMagic;
+    *out = x;
+    return TS_OK;
+  } catch (...) {
+    return api_fail(TS_E_OOM, "host allocation failed");
+  }
+}
+
+int ts_transform_apply(ts_target t, ts_transform x, ts_array a, ts_array b, ts_array d, double q) {
+  try {
+    if (!ts_ok_target_handle(t) || !x || x->magic != kTransformMagic)
+      return api_fail(TS_E_INVALID, "invalid target or transform handle");
+    if (t->host) return api_fail(TS_E_UNSUPPORTED, "transforms run on GPU targets");
+    const bool two = x->n_inputs == 2;
+    if (!ts_ok_array_handle(a) || !ts_ok_array_handle(d) || (two && !ts_ok_array_handle(b)))
+      return api_fail(TS_E_INVALID, "invalid array handle");
+    if (a->dtype != x->dtype) return api_fail(TS_E_DTYPE, "arrays have another storage type than the transform");
+    if (x->device != t->device) return api_fail(TS_E_PLACEMENT, "transform was compiled for another device");
+    const Operand ox{reinterpret_cast<uintptr_t>(a->ptr), a->n, a->dtype, a->device};
+    const Operand od{reinterpret_cast<uintptr_t>(d->ptr), d->n, d->dtype, d->device};
+    Operand oy{};
+    if (two) oy = Operand{reinterpret_cast<uintptr_t>(b->ptr), b->n, b->dtype, b->device};
+    const MapCheck c = check_map(two, t->device, ox, two ? &oy : nullptr, od);
+    if (c.status != ST_OK) return api_fail(c.status, "%s", c.msg.c_str());
+    if (c.count == 0) return TS_OK;
+    hipError_t he = hipSetDevice(t->device);
+    if (he != hipSuccess) return api_hip_fail(he, "hipSetDevice");
+    const void* xp = a->ptr;
+    const void* yp = two ? b->ptr : a->ptr;
+    void* dp = d->ptr;
+    unsigned long long n = c.count;
+    void* args[] = {&xp, &yp, &dp, &q, &n};
+    const unsigned block = 256;
+    unsigned long long grid = (n + block - 1) / block;
+    const unsigned long long cap = 32ull * static_cast<unsigned long long>(t->info.compute_units);
+    if (grid > cap) grid = cap;  // grid-stride over the rest
+    he = hipModuleLaunchKernel(x->fn, static_cast<unsigned>(grid), 1, 1, block, 1, 1, 0, t->stream, args, nullptr);
+    if (he != hipSuccess) return api_hip_fail(he, "hipModuleLaunchKernel");
+    return TS_OK;
+  } catch (...) {
+    return api_fail(TS_E_INVALID, "internal error");
+  }
+}
+
+int ts_transform_log(ts_transform x, const char** log) {
+  if (!x || x->magic != kTransformMagic || !log) return api_fail(TS_E_INVALID, "invalid transform handle");
+  *log = x->log.c_str();
+  return TS_OK;
+}
+
+int ts_transform_destroy(ts_transform x) {
+  if (!x) return TS_OK;
+  if (x->magic != kTransformMagic) return api_fail(TS_E_INVALID, "invalid transform handle");
+  (void)hipSetDevice(x->device);
+  (void)hipModuleUnload(x->module);
+  x->magic = 0xdeadbeefu;
+  delete x;
+  return TS_OK;
+}
+
+}  // extern "C"

@@ -31,6 +31,7 @@ inline size_t dtype_size(int dt) {
     case 1: return 4;
     case 2:
     case 3: return 2;
+    case 4: return 1;
     default: return 0;
   }
 }

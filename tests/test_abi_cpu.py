@@ -74,6 +74,9 @@ def test_version_and_errors(ts):
     assert L.ts_future_ready(None) == TS_E_INVALID
     assert L.ts_future_destroy(None) == TS_OK
     assert L.ts_target_async(None, None) == TS_E_INVALID
+    assert L.ts_transform_create(None, b"x", 1, 0, None) == TS_E_INVALID
+    assert L.ts_transform_apply(None, None, None, None, None, ctypes.c_double(0.0)) == TS_E_INVALID
+    assert L.ts_transform_destroy(None) == TS_OK
 
 
 def test_target_create_without_gpu_reports_device_error(ts):

@@ -115,6 +115,12 @@ def test_host_target_limits(ts):
         tgt.stream_handle()
     with pytest.raises(ts.TSError):
         ts.Target.host([100000])
+    with pytest.raises(ts.TSError) as e:
+        ts.Transform(tgt, "x + 1")
+    assert e.value.status == E_UNSUPPORTED
+    with pytest.raises(ts.TSError) as e:
+        ts.copy(tgt, ts.Array.alloc(tgt, "u8", 10), ts.Array.alloc(tgt, "u8", 10))
+    assert e.value.status == E_UNSUPPORTED
     done = []
     tgt.then(lambda: done.append(1))
     assert done == [1]
