@@ -11,8 +11,11 @@ synchronisation.  Every launch is bracketed by events on the target's stream,
 giving per-kernel best/average times; bytes follow the STREAM convention
 (copy and scale move 2 arrays, add and triad 3; GB = 1e9 B).
 
-After timing, the arrays are validated on the GPU against the oracle's
-scalar recurrence (every element of a, b, c must match bit for bit).
+After timing, the arrays are validated on the GPU: every element of a, b
+and c must equal element 0 of its array bit for bit (all elements follow the
+same chain), and a separate 10-iteration run from (1, 2, 0) must reproduce
+STREAM's closed form a = 15^10, b = 3*15^9, c = 4*15^9 exactly.  Only the
+CPU-baseline leg runs the oracle.
 
 Extra legs (skipped with --quick): the batched ragged form (4096 instances,
 log-uniform lengths in [1e3, 1e7), one persistent launch per map, the
@@ -69,6 +72,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def first_value(arr) -> float:
+    return float(arr.to_host(1)[0])
+
+
+def uniform_arrays(ts, tgt, arrays) -> bool:
+    """Every element equals element 0 of its array, bit for bit."""
+    return all(ts.checksum(tgt, arr, first_value(arr))["mismatches"] == 0 for arr in arrays)
+
+
+def closed_form_check(ts, tgt, A, B, C, iters=10) -> bool:
+    """STREAM's closed form from (1, 2, 0) with q = 3: after k iterations
+    a = 15^k, b = 3*15^(k-1), c = 4*15^(k-1), exact in binary64 for k <= 13."""
+    A.fill(1.0), B.fill(2.0), C.fill(0.0)
+    for _ in range(iters):
+        ts.stream_iteration(tgt, A, B, C, 3.0)
+    exp = (15.0 ** iters, 3.0 * 15 ** (iters - 1), 4.0 * 15 ** (iters - 1))
+    return all(ts.checksum(tgt, arr, e)["mismatches"] == 0 for arr, e in zip((A, B, C), exp))
+
+
 def main_leg(ts, torch, tgt, n, steps, warmup):
     """Headline: FP64 STREAM at n elements; returns the result dict."""
     A, B, C = (ts.Array.alloc(tgt, "f64", n) for _ in range(3))
@@ -93,10 +115,8 @@ def main_leg(ts, torch, tgt, n, steps, warmup):
     wall = time.perf_counter() - t0
     per = {op: [ev[s][k].elapsed_ms(ev[s][k + 1]) for s in range(steps)] for k, op in enumerate(OPS)}
     step_ms = [ev[s][0].elapsed_ms(ev[s][4]) for s in range(steps)]
-    # validation against the oracle's scalar recurrence (all elements equal)
-    import oracle
-    exp = oracle.stream_scalar_f64(1.0, 2.0, 0.0, 3.0, warmup + steps)
-    valid = all(ts.checksum(tgt, arr, e)["mismatches"] == 0 for arr, e in zip((A, B, C), exp))
+    # every element followed the same chain; then STREAM's closed form
+    valid = uniform_arrays(ts, tgt, (A, B, C)) and closed_form_check(ts, tgt, A, B, C)
     kernels = {}
     for op in OPS:
         b = ts.stream_bytes(op, n)
@@ -113,6 +133,8 @@ def main_leg(ts, torch, tgt, n, steps, warmup):
 
 def batched_leg(ts, torch, tgt, count=4096, seed=5, replays=50, triad_reps=20):
     """Batched ragged triad and the graph-captured iteration vs plain launches."""
+    import numpy as np
+
     import tsgen
     lens = tsgen.batched_lengths(seed, count)
     qs = tsgen.batched_scalars(seed, count)
@@ -138,10 +160,12 @@ def batched_leg(ts, torch, tgt, count=4096, seed=5, replays=50, triad_reps=20):
     e1.record(tgt)
     e1.synchronize()
     graph_ms = e0.elapsed_ms(e1) / (replays - 1)
-    # per-instance closed recurrence after `replays` iterations
-    import oracle
-    exp = [oracle.stream_scalar_f64(1.0, 2.0, 0.0, float(q), replays) for q in qs]
-    valid = all(int(batch.mismatch_count(tgt, k, [e[k] for e in exp]).sum()) == 0 for k in range(3))
+    # every element of instance i equals its first element, and that value
+    # follows a = (q(2+q))^K up to the rounding of 4K operations
+    firsts = [pools[k][torch.tensor(offs, device="cuda")].cpu().numpy() for k in range(3)]
+    valid = all(int(batch.mismatch_count(tgt, k, firsts[k]).sum()) == 0 for k in range(3))
+    growth = (qs * (2.0 + qs)) ** replays
+    valid = valid and bool(np.all(np.abs(firsts[0] - growth) <= 4 * replays * 2.0 ** -52 * growth))
     # triad alone: one persistent launch over all instances
     t_ms = []
     for _ in range(triad_reps):
@@ -176,26 +200,57 @@ def batched_leg(ts, torch, tgt, count=4096, seed=5, replays=50, triad_reps=20):
     return out
 
 
-def reduced_leg(ts, torch, tgt, n=1 << 28, reps=10):
+def reduced_leg(ts, torch, tgt, n=1 << 28, reps=10, samples=1 << 14):
+    """Storage as f64/f32/bf16/f16 (arithmetic in binary32 for the narrow
+    types), N = 2^28 per array: GB/s and elements/s per map, and the maximum
+    relative error of each map against binary64 arithmetic on the same
+    stored inputs (numpy, on sampled elements; normal results only)."""
+    import numpy as np
+
+    import tsgen
     out = {}
+    rng = np.random.default_rng(4)
+    idx = np.unique(rng.integers(0, n, samples))
+    tidx = torch.from_numpy(idx).cuda()
     for dtype in ("f64", "f32", "bf16", "f16"):
-        A, B, C = (ts.Array.alloc(tgt, dtype, n) for _ in range(3))
+        tt = [torch.empty(n, dtype=ts.TORCH_DTYPES[dtype], device="cuda") for _ in range(3)]
+        torch.cuda.synchronize()
+        A, B, C = (ts.Array.wrap(tgt, t) for t in tt)
         A.fill_uniform(4, 0), B.fill_uniform(4, 1), C.fill_uniform(4, 2)
-        roles = {"copy": (A, None, C), "scale": (C, None, B), "add": (A, B, C), "triad": (B, C, A)}
+        tgt.synchronize()
+        xs = {k: tt[k][tidx].double().cpu().numpy() for k in range(3)}  # exact widening
+        roles = {"copy": (A, None, C, 0, None, 2), "scale": (C, None, B, 2, None, 1),
+                 "add": (A, B, C, 0, 1, 2), "triad": (B, C, A, 1, 2, 0)}
         res = {}
         for op in OPS:
-            x, y, d = roles[op]
+            x, y, d, ix, iy, idst = roles[op]
             ts.time_op(tgt, op, x, y, d, 3.0, reps=2)
             ms = ts.time_op(tgt, op, x, y, d, 3.0, reps=reps) / reps
             b = ts.stream_bytes(op, n, dtype)
             res[op] = {"GBps": round(b / ms / 1e6, 1), "Gelem_per_s": round(n / ms / 1e6, 2)}
+            # one more standalone application from known inputs for the error figure
+            for k in range(3):
+                tt[k][tidx] = torch.from_numpy(xs[k]).to(tt[k].dtype).cuda()
+            torch.cuda.synchronize()
+            ts.run_op(tgt, op, x, y, d, 3.0)
+            tgt.synchronize()
+            got = tt[idst][tidx].double().cpu().numpy()
+            xv, yv = xs[ix], (xs[iy] if iy is not None else None)
+            ref = {"copy": xv, "scale": 3.0 * xv, "add": xv + (yv if yv is not None else 0),
+                   "triad": xv + 3.0 * (yv if yv is not None else 0)}[op]
+            tiny = {"f64": 2.0 ** -1022, "f32": 2.0 ** -126, "bf16": 2.0 ** -126, "f16": 2.0 ** -14}[dtype]
+            m = np.abs(ref) >= tiny
+            res[op]["max_rel_err_vs_f64"] = float(np.max(np.abs(got[m] - ref[m]) / np.abs(ref[m]))) if m.any() else 0.0
+            xs = {k: tt[k][tidx].double().cpu().numpy() for k in range(3)}
         out[dtype] = res
-        for arr in (A, B, C):
-            arr.free()
+        del A, B, C, tt
+        torch.cuda.empty_cache()
     for dtype in ("f32", "bf16", "f16"):
         for op in OPS:
             out[dtype][op]["elem_rate_vs_f64"] = round(out[dtype][op]["Gelem_per_s"] / out["f64"][op]["Gelem_per_s"], 2)
     out["n"] = n
+    out["error_note"] = ("max relative error of one standalone map vs binary64 arithmetic (numpy) on the "
+                         "same stored inputs, over sampled elements with normal results")
     return out
 
 
@@ -275,8 +330,8 @@ def host_target_leg(ts, n, threads, iters=10):
             ms = ts.time_op(tgt, op, x, y, d, 3.0, reps=1)
             best[op] = min(best[op], ms)
             total += ms
-    import oracle
-    exp = oracle.stream_scalar_f64(1.0, 2.0, 0.0, 3.0, iters + 1)
+    k = iters + 1  # closed form of STREAM from (1, 2, 0): exact integers up to k = 13
+    exp = (15.0 ** k, 3.0 * 15 ** (k - 1), 4.0 * 15 ** (k - 1))
     valid = all(ts.checksum(tgt, arr, e)["mismatches"] == 0 for arr, e in zip((A, B, C), exp))
     for arr in (A, B, C):
         arr.free()
@@ -319,7 +374,7 @@ def main():
     log(f"main leg: f64 N={a.n}, warmup={a.warmup}, steps={a.steps}")
     m = main_leg(ts, torch, tgt, a.n, a.steps, a.warmup)
     if not m["valid"]:
-        print("validation failed: results differ from the oracle's recurrence", file=sys.stderr)
+        print("validation failed: arrays not uniform, or the closed-form run differs", file=sys.stderr)
         sys.exit(1)
     k = m["kernels"]
     step_bytes = sum(k[op]["bytes"] for op in OPS)
@@ -350,7 +405,8 @@ def main():
         "copy_pct_peak_best": k["copy"]["pct_peak_best"],
         "per_kernel": k,
         "host_wall_ms_per_step": round(1e3 * m["wall_s"] / a.steps, 5),
-        "validated": "all elements of a, b, c equal the oracle's recurrence bit for bit",
+        "validated": "all elements of a, b, c equal element 0 bit for bit; a 10-iteration run matches "
+                     "STREAM's closed form exactly",
         "roofline": {"bound": "hbm", "kernel": "triad f64", "achieved": round(achieved, 1), "peak": PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_GBPS, 4),
                      "traffic": traffic,
