@@ -286,6 +286,40 @@ def sweep_leg(ts, tgt, lo=16, hi=29):
     return out
 
 
+def overhead_leg(ts, torch, tgt, lo=12, hi=22, iters=200):
+    """Launch overhead at small sizes (the paper's Fig. 5 point: abstraction
+    cost shows for small arrays, vanishes for large ones): microseconds per
+    four-map iteration issued eagerly through the C ABI from Python, against
+    the same iteration captured once as a HIP graph and replayed."""
+    out = {}
+    e0, e1 = ts.Event(), ts.Event()
+    for p in range(lo, hi + 1, 2):
+        n = 1 << p
+        A, B, C = (ts.Array.alloc(tgt, "f64", n) for _ in range(3))
+        A.fill(1.0), B.fill(2.0), C.fill(0.0)
+        for _ in range(3):
+            ts.stream_iteration(tgt, A, B, C, 1.0)
+        e0.record(tgt)
+        for _ in range(iters):
+            ts.stream_iteration(tgt, A, B, C, 1.0)
+        e1.record(tgt)
+        e1.synchronize()
+        eager = 1e3 * e0.elapsed_ms(e1) / iters
+        g = ts.Graph.capture_arrays_iteration(tgt, A, B, C, 1.0)
+        g.launch(tgt, 3)
+        e0.record(tgt)
+        g.launch(tgt, iters)
+        e1.record(tgt)
+        e1.synchronize()
+        graph = 1e3 * e0.elapsed_ms(e1) / iters
+        g.close()
+        out[f"2^{p}"] = {"eager_us_per_iteration": round(eager, 2), "graph_us_per_iteration": round(graph, 2),
+                         "eager_GBps": round(80 * n / eager / 1e3, 1), "graph_GBps": round(80 * n / graph / 1e3, 1)}
+        for arr in (A, B, C):
+            arr.free()
+    return out
+
+
 def cpu_baseline_leg(n, target_seconds=12.0):
     """The oracle's timed mode on the host (pinned threads, first touch)."""
     import oracle
@@ -417,7 +451,8 @@ def main():
     if not a.quick:
         for name, fn in (("batched", lambda: batched_leg(ts, torch, tgt)),
                          ("reduced_precision", lambda: reduced_leg(ts, torch, tgt)),
-                         ("sweep", lambda: sweep_leg(ts, tgt))):
+                         ("sweep", lambda: sweep_leg(ts, tgt)),
+                         ("launch_overhead", lambda: overhead_leg(ts, torch, tgt))):
             log(f"{name} leg")
             try:
                 result[name] = fn()
