@@ -73,12 +73,12 @@ std::vector<ts_kernel_cfg> candidates(int batched) {
                 out.push_back(ts_kernel_cfg{block, u, vb, ntl, nts, g, 0});
               }
   } else {
-    for (int block : {256, 512, 1024})
-      for (int u : {1, 2, 4, 8})
+    for (int block : {512, 1024})
+      for (int u : {2, 4, 8})
         for (int ntl : {0, 1})
           for (int nts : {0, 1})
-            for (int g : {2, 4, 8, 16})
-              for (int64_t tile : {16384, 65536}) {
+            for (int g : {4, 8, 16})
+              for (int64_t tile : {4096, 8192, 16384, 65536}) {
                 if (block * g > 8192) continue;  // beyond what the CUs hold resident
                 out.push_back(ts_kernel_cfg{block, u, 16, ntl, nts, g, tile});
               }
