@@ -46,12 +46,17 @@ PROFILE_PMC = os.path.join(ROOT, "profiles", "triad_f64_n2p27_pmc.md")
 
 
 def kernel_source_digest() -> str:
+    """Digest of what determines the f64 kernels the headline launches: their
+    source and the tuned launch configurations (measured rates excluded)."""
     h = hashlib.sha256()
-    for rel in ("paper_2206_06302_amd/csrc/ts_device.hpp", "paper_2206_06302_amd/csrc/kern_f64.hip",
-                "paper_2206_06302_amd/tune/gfx950.json"):
-        p = os.path.join(ROOT, rel)
-        if os.path.exists(p):
-            h.update(open(p, "rb").read())
+    for rel in ("paper_2206_06302_amd/csrc/ts_device.hpp", "paper_2206_06302_amd/csrc/kern_f64.hip"):
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    tune = os.path.join(ROOT, "paper_2206_06302_amd", "tune", "gfx950.json")
+    if os.path.exists(tune):
+        entries = json.load(open(tune)).get("entries", [])
+        cfgs = sorted(json.dumps({k: v for k, v in e.items() if k != "bytes_per_s"}, sort_keys=True)
+                      for e in entries if e.get("dtype") == "f64" and not e.get("batched"))
+        h.update("\n".join(cfgs).encode())
     return h.hexdigest()[:16]
 
 
