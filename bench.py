@@ -290,35 +290,45 @@ def sweep_leg(ts, tgt, lo=16, hi=29):
     return out
 
 
-def overhead_leg(ts, torch, tgt, lo=12, hi=22, iters=200):
+def overhead_leg(ts, torch, tgt, lo=12, hi=22, iters=192, per_graph=16):
     """Launch overhead at small sizes (the paper's Fig. 5 point: abstraction
     cost shows for small arrays, vanishes for large ones): microseconds per
     four-map iteration issued eagerly through the C ABI from Python, against
-    the same iteration captured once as a HIP graph and replayed."""
+    HIP graphs replayed back to back, holding one iteration (4 nodes) or
+    `per_graph` iterations each.  A graph launch has a fixed cost that only a
+    graph of many nodes amortises."""
     out = {}
     e0, e1 = ts.Event(), ts.Event()
+
+    def per_iteration(run, count):
+        run(2)
+        e0.record(tgt)
+        run(count)
+        e1.record(tgt)
+        e1.synchronize()
+        return 1e3 * e0.elapsed_ms(e1) / iters
+
     for p in range(lo, hi + 1, 2):
         n = 1 << p
         A, B, C = (ts.Array.alloc(tgt, "f64", n) for _ in range(3))
         A.fill(1.0), B.fill(2.0), C.fill(0.0)
-        for _ in range(3):
-            ts.stream_iteration(tgt, A, B, C, 1.0)
-        e0.record(tgt)
-        for _ in range(iters):
-            ts.stream_iteration(tgt, A, B, C, 1.0)
-        e1.record(tgt)
-        e1.synchronize()
-        eager = 1e3 * e0.elapsed_ms(e1) / iters
-        g = ts.Graph.capture_arrays_iteration(tgt, A, B, C, 1.0)
-        g.launch(tgt, 3)
-        e0.record(tgt)
-        g.launch(tgt, iters)
-        e1.record(tgt)
-        e1.synchronize()
-        graph = 1e3 * e0.elapsed_ms(e1) / iters
-        g.close()
-        out[f"2^{p}"] = {"eager_us_per_iteration": round(eager, 2), "graph_us_per_iteration": round(graph, 2),
-                         "eager_GBps": round(80 * n / eager / 1e3, 1), "graph_GBps": round(80 * n / graph / 1e3, 1)}
+
+        def eager(k):
+            for _ in range(k):
+                ts.stream_iteration(tgt, A, B, C, 1.0)
+
+        t_eager = per_iteration(eager, iters)
+        g1 = ts.Graph.capture_arrays_iteration(tgt, A, B, C, 1.0)
+        t_g1 = per_iteration(lambda k: g1.launch(tgt, k), iters)
+        g1.close()
+        gk = ts.Graph.capture_arrays_iteration(tgt, A, B, C, 1.0, iterations=per_graph)
+        t_gk = per_iteration(lambda k: gk.launch(tgt, k), iters // per_graph)
+        gk.close()
+        row = {"eager_us_per_iteration": round(t_eager, 2), "graph_us_per_iteration": round(t_g1, 2),
+               f"graph{per_graph}_us_per_iteration": round(t_gk, 2)}
+        for key, t in (("eager", t_eager), ("graph", t_g1), (f"graph{per_graph}", t_gk)):
+            row[f"{key}_GBps"] = round(80 * n / t / 1e3, 1)
+        out[f"2^{p}"] = row
         for arr in (A, B, C):
             arr.free()
     return out

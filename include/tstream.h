@@ -380,6 +380,18 @@ TS_API int ts_graph_capture_batch_op(ts_target target, ts_batch batch,
 TS_API int ts_graph_capture_arrays_iteration(ts_target target, ts_array a,
                                              ts_array b, ts_array c, double q,
                                              ts_graph *out);
+/* Capture `iterations` consecutive benchmark iterations into one graph
+ * (4 x iterations nodes, in the order eager calls would run them).  A graph
+ * launch has a fixed cost of several microseconds regardless of its size,
+ * so small arrays gain from graphs only when one launch holds many
+ * kernels.  1 <= iterations <= TS_GRAPH_MAX_ITERATIONS (TS_E_INVALID
+ * otherwise); the other rules are those of the one-iteration calls. */
+#define TS_GRAPH_MAX_ITERATIONS 4096
+TS_API int ts_graph_capture_arrays_iterations(ts_target target, ts_array a,
+                                              ts_array b, ts_array c, double q,
+                                              int iterations, ts_graph *out);
+TS_API int ts_graph_capture_stream_iterations(ts_target target, ts_batch batch,
+                                              int iterations, ts_graph *out);
 /* Enqueue the graph `repeats` times on the target's stream. */
 TS_API int ts_graph_launch(ts_target target, ts_graph graph, int repeats);
 TS_API int ts_graph_destroy(ts_graph graph);

@@ -470,9 +470,14 @@ class Graph:
         self._keep = keep
 
     @classmethod
-    def capture_stream_iteration(cls, target: Target, batch: Batch) -> "Graph":
+    def capture_stream_iteration(cls, target: Target, batch: Batch, iterations: int = 1) -> "Graph":
+        """`iterations` consecutive batched iterations (4 nodes each)."""
         h = ctypes.c_void_p()
-        _check(lib.ts_graph_capture_stream_iteration(target.handle, batch.handle, ctypes.byref(h)))
+        if iterations == 1:
+            _check(lib.ts_graph_capture_stream_iteration(target.handle, batch.handle, ctypes.byref(h)))
+        else:
+            _check(lib.ts_graph_capture_stream_iterations(target.handle, batch.handle, int(iterations),
+                                                          ctypes.byref(h)))
         return cls(h, keep=batch)
 
     @classmethod
@@ -482,10 +487,16 @@ class Graph:
         return cls(h, keep=batch)
 
     @classmethod
-    def capture_arrays_iteration(cls, target: Target, a: Array, b: Array, c: Array, q: float = 3.0) -> "Graph":
+    def capture_arrays_iteration(cls, target: Target, a: Array, b: Array, c: Array, q: float = 3.0,
+                                 iterations: int = 1) -> "Graph":
+        """`iterations` consecutive plain iterations over a, b, c (4 nodes each)."""
         h = ctypes.c_void_p()
-        _check(lib.ts_graph_capture_arrays_iteration(target.handle, a.handle, b.handle, c.handle, float(q),
-                                                     ctypes.byref(h)))
+        if iterations == 1:
+            _check(lib.ts_graph_capture_arrays_iteration(target.handle, a.handle, b.handle, c.handle, float(q),
+                                                         ctypes.byref(h)))
+        else:
+            _check(lib.ts_graph_capture_arrays_iterations(target.handle, a.handle, b.handle, c.handle, float(q),
+                                                          int(iterations), ctypes.byref(h)))
         return cls(h, keep=(a, b, c))
 
     def launch(self, target: Target, repeats: int = 1) -> None:

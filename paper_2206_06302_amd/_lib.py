@@ -137,6 +137,8 @@ PROTOTYPES = {
     "ts_graph_capture_stream_iteration": [H, H, ctypes.POINTER(H)],
     "ts_graph_capture_batch_op": [H, H, I, ctypes.POINTER(H)],
     "ts_graph_capture_arrays_iteration": [H, H, H, H, D, ctypes.POINTER(H)],
+    "ts_graph_capture_arrays_iterations": [H, H, H, H, D, I, ctypes.POINTER(H)],
+    "ts_graph_capture_stream_iterations": [H, H, I, ctypes.POINTER(H)],
     "ts_graph_launch": [H, H, I],
     "ts_graph_destroy": [H],
     "ts_event_create": [ctypes.POINTER(H)],

@@ -1371,21 +1371,28 @@ int capture(ts_target_s* t, Body&& body, ts_graph* out) {
 
 extern "C" {
 
-int ts_graph_capture_stream_iteration(ts_target t, ts_batch b, ts_graph* out) {
+int ts_graph_capture_stream_iterations(ts_target t, ts_batch b, int iterations, ts_graph* out) {
   TS_GUARD_BEGIN
   int st = check_batch_exec(t, b);
   if (st != TS_OK) return st;
+  if (iterations < 1 || iterations > TS_GRAPH_MAX_ITERATIONS)
+    return fail(TS_E_INVALID, "iterations must be in [1, TS_GRAPH_MAX_ITERATIONS]");
   return capture(
       t,
       [&]() {
-        for (int op = TS_COPY; op <= TS_TRIAD; ++op) {
-          const int s = launch_batch(t, b, op, batch_cfg(b, op));
-          if (s != TS_OK) return s;
-        }
+        for (int k = 0; k < iterations; ++k)
+          for (int op = TS_COPY; op <= TS_TRIAD; ++op) {
+            const int s = launch_batch(t, b, op, batch_cfg(b, op));
+            if (s != TS_OK) return s;
+          }
         return static_cast<int>(TS_OK);
       },
       out);
   TS_GUARD_END
+}
+
+int ts_graph_capture_stream_iteration(ts_target t, ts_batch b, ts_graph* out) {
+  return ts_graph_capture_stream_iterations(t, b, 1, out);
 }
 
 int ts_graph_capture_batch_op(ts_target t, ts_batch b, ts_op op, ts_graph* out) {
@@ -1397,13 +1404,29 @@ int ts_graph_capture_batch_op(ts_target t, ts_batch b, ts_op op, ts_graph* out) 
   TS_GUARD_END
 }
 
-int ts_graph_capture_arrays_iteration(ts_target t, ts_array a, ts_array b, ts_array c, double q,
-                                      ts_graph* out) {
+int ts_graph_capture_arrays_iterations(ts_target t, ts_array a, ts_array b, ts_array c, double q,
+                                       int iterations, ts_graph* out) {
   TS_GUARD_BEGIN
   if (!ok_target(t)) return fail(TS_E_INVALID, "invalid target handle");
   if (t->host) return host_only_gpu("graph capture");
-  return capture(t, [&]() { return ts_stream_iteration(t, a, b, c, q); }, out);
+  if (iterations < 1 || iterations > TS_GRAPH_MAX_ITERATIONS)
+    return fail(TS_E_INVALID, "iterations must be in [1, TS_GRAPH_MAX_ITERATIONS]");
+  return capture(
+      t,
+      [&]() {
+        for (int k = 0; k < iterations; ++k) {
+          const int s = ts_stream_iteration(t, a, b, c, q);
+          if (s != TS_OK) return s;
+        }
+        return static_cast<int>(TS_OK);
+      },
+      out);
   TS_GUARD_END
+}
+
+int ts_graph_capture_arrays_iteration(ts_target t, ts_array a, ts_array b, ts_array c, double q,
+                                      ts_graph* out) {
+  return ts_graph_capture_arrays_iterations(t, a, b, c, q, 1, out);
 }
 
 int ts_graph_launch(ts_target t, ts_graph g, int repeats) {

@@ -215,6 +215,31 @@ def test_graph_iteration_matches_eager_and_closed_form(env):
     g1.close(), bg.close(), be.close()
 
 
+def test_multi_iteration_batched_graph(env):
+    """Five batched iterations captured as one 20-node graph, replayed twice:
+    every instance follows the scalar chain with its own q for 10 iterations."""
+    ts, torch, tgt = env
+    rng = np.random.default_rng(17)
+    count = 24
+    lens = _lens(rng, count)
+    pool = Pool(ts, torch, lens, "f64", _mis(rng, count, 8))
+    qs = tsgen.batched_scalars(6, count)
+    batch = ts.Batch(tgt, "f64", pool.descs(qs))
+    batch.fill(tgt, 0, 1.0), batch.fill(tgt, 1, 2.0), batch.fill(tgt, 2, 0.0)
+    say("[multi-iteration batched graph]")
+    g = ts.Graph.capture_stream_iteration(tgt, batch, iterations=5)
+    g.launch(tgt, 1)
+    tgt.synchronize()
+    g.launch(tgt, 1)
+    tgt.synchronize()
+    g.close()
+    exp = [oracle.stream_scalar_f64(1.0, 2.0, 0.0, float(q), 10) for q in qs]
+    for k in range(3):
+        counts = batch.mismatch_count(tgt, k, np.array([e[k] for e in exp]))
+        assert counts.sum() == 0, (k, np.nonzero(counts)[0][:5])
+    batch.close()
+
+
 def test_batch_mismatch_count_counts(env):
     ts, torch, tgt = env
     lens = [10, 0, 5000, 3]

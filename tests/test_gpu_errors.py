@@ -94,6 +94,8 @@ def test_graph_capture_needs_a_stream(env):
     dflt.synchronize()
     own = ts.Target(0, "own")
     assert own.stream_handle() != 0
+    for bad in (0, -1, 4097):
+        assert status(ts, lambda: ts.Graph.capture_arrays_iteration(own, a, b, c, iterations=bad)) == E_INVALID
     g = ts.Graph.capture_arrays_iteration(own, a, b, c)
     g.launch(own, 1)
     own.synchronize()

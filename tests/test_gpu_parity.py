@@ -265,6 +265,28 @@ def test_plain_graph_matches_eager(env):
     assert_same_bits(A1.to_host(), a, "f64", "a after graph")
 
 
+@pytest.mark.parametrize("n,offset", [(4099, 1), ((1 << 18) + 5, 3)])
+def test_multi_iteration_graph_matches_oracle(env, n, offset):
+    """One graph holding 16 iterations (64 nodes), replayed twice with eager
+    iterations between the replays, equals the oracle's 34-iteration chain
+    from random values, bit for bit."""
+    ts, torch, tgt = env
+    a, b, c = _inputs(n, "f64", seed=23)
+    A, B, C = (device_array(ts, torch, tgt, v, "f64", offset) for v in (a, b, c))
+    say(f"[multi-iteration graph] n={n} offset={offset}")
+    g = ts.Graph.capture_arrays_iteration(tgt, A, B, C, 3.0, iterations=16)
+    g.launch(tgt, 1)
+    tgt.synchronize()
+    ts.stream_iteration(tgt, A, B, C, 3.0)
+    ts.stream_iteration(tgt, A, B, C, 3.0)
+    g.launch(tgt, 1)
+    tgt.synchronize()
+    g.close()
+    oracle.stream_run(oracle.F64, a, b, c, 3.0, 34)
+    for X, ref, nm in ((A, a, "a"), (B, b, "b"), (C, c, "c")):
+        assert_same_bits(X.to_host(), ref, "f64", nm)
+
+
 def test_futures_become_ready_after_the_work(env):
     """A future of the work enqueued so far is made ready by a stream callback
     once that work has finished; its results are then visible to the host."""

@@ -104,6 +104,9 @@ def test_host_target_limits(ts):
         ts.Graph.capture_arrays_iteration(tgt, a, a, a)
     assert e.value.status == E_UNSUPPORTED
     with pytest.raises(ts.TSError) as e:
+        ts.Graph.capture_arrays_iteration(tgt, a, a, a, iterations=8)
+    assert e.value.status == E_UNSUPPORTED
+    with pytest.raises(ts.TSError) as e:
         ts.Batch(tgt, "f64", [])
     assert e.value.status == E_UNSUPPORTED
     with pytest.raises(ts.TSError) as e:
