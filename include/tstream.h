@@ -263,7 +263,7 @@ typedef struct {
     int32_t nt_store;    /* 1: nontemporal stores                           */
     int32_t grid_per_cu; /* workgroups per CU with a grid-stride loop; 0: one
                             pass, i.e. enough workgroups to cover the array
-                            once (plain kernels only)                       */
+                            once (batched: one workgroup per tile)          */
     int64_t tile_elems;  /* batched: elements per tile, a multiple of 8;
                             0 = default.  Ignored by plain kernels          */
 } ts_kernel_cfg;
@@ -317,7 +317,7 @@ TS_API int ts_time_op(ts_target exec, ts_op op, ts_array x, ts_array y,
                       ts_array dst, double q, int reps, float *ms_total);
 
 /* ------------------------------------------------------------------------ */
-/* Batched ragged instances: one persistent launch per map                   */
+/* Batched ragged instances: one launch per map over all instances          */
 /* ------------------------------------------------------------------------ */
 
 /* One instance: device pointers of its three arrays (len elements each) and
@@ -331,10 +331,12 @@ typedef struct {
     double q;
 } ts_batch_desc;
 
-/* Copy `count` descriptors (host memory), split every instance into tiles
- * (tile_elems from the tuning table unless forced), and upload the
- * descriptor and tile tables to the target's device.  The instances' arrays
- * must not overlap one another.  Zero-length instances are allowed.
+/* Copy `count` descriptors (host memory), split every instance into tiles,
+ * and upload the tile tables to the target's device.  The primary plan uses
+ * the triad's tile size from the tuning table (or the forced configuration);
+ * a map whose configuration asks for another tile size gets a plan of its
+ * own, so each map runs on its tuned tiles.  The instances' arrays must not
+ * overlap one another.  Zero-length instances are allowed.
  * Errors: TS_E_INVALID (NULL pointer with len > 0, misaligned element),
  * TS_E_PLACEMENT, TS_E_OOM, TS_E_DEVICE.  Blocking (uploads complete). */
 TS_API int ts_batch_create(ts_target target, ts_dtype dtype,
@@ -343,7 +345,10 @@ TS_API int ts_batch_create(ts_target target, ts_dtype dtype,
 TS_API int ts_batch_destroy(ts_batch batch);
 TS_API int ts_batch_info(ts_batch batch, size_t *count, uint64_t *total_elems,
                          uint64_t *tiles, int64_t *tile_elems);
-/* Re-plan the tiles with tile_elems (multiple of 8, > 0).  Blocking. */
+/* Re-plan with tile_elems (multiple of 8, > 0) and pin it: every map then
+ * runs on this one plan, whatever its configuration's tile size.  Blocking.
+ * Re-planning (this call, ts_autotune_batch) frees the old tile tables, so
+ * graphs captured from the batch before it must not be launched again. */
 TS_API int ts_batch_set_tile(ts_batch batch, int64_t tile_elems);
 /* Apply map `op` to every instance in one persistent launch (bulk
  * execution over all instances, Sections 3.3 and 4.2). */
@@ -370,7 +375,8 @@ TS_API int ts_batch_mismatch_count(ts_target exec, ts_batch batch, int which,
 /* Capture the four batched maps of one benchmark iteration (copy, scale,
  * add, triad) on the target's stream into an instantiated graph.  The
  * target's stream must not be the legacy default stream
- * (TS_E_UNSUPPORTED).  The batch must outlive the graph. */
+ * (TS_E_UNSUPPORTED).  The batch must outlive the graph and must not be
+ * re-planned while the graph is in use. */
 TS_API int ts_graph_capture_stream_iteration(ts_target target, ts_batch batch,
                                              ts_graph *out);
 /* Capture a single batched map (one graph node). */

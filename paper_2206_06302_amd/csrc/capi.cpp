@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -28,6 +29,9 @@
 #include "tune.hpp"
 
 namespace {
+
+// Largest grid.x of a launch; kernels stride over whatever lies beyond it.
+constexpr uint64_t kMaxGridX = 0x7fffffffull;
 
 using namespace ts;
 
@@ -73,6 +77,7 @@ constexpr uint32_t kGraphMagic = 0x47524631u;
 constexpr uint32_t kEventMagic = 0x45564e31u;
 constexpr uint32_t kFutureMagic = 0x46555431u;
 constexpr uint32_t kDead = 0xdeadbeefu;
+constexpr uint64_t kDeadEpoch = ~0ull;
 constexpr double kPeakBytesPerS = 8.0e12;  // MI355X HBM3E, the % of peak denominator
 
 }  // namespace
@@ -97,12 +102,25 @@ struct ts_batch_s {
   int dtype;
   std::vector<HostDesc> host;
   std::vector<BatchDesc> descs;  // host-side metadata (alignment per instance)
-  std::vector<BatchTile> tiles;
+  std::vector<BatchTile> tiles;  // primary plan: fills, mismatch counts, info
   BatchTile* d_tiles;
   double* d_expected;
   unsigned long long* d_counts;
   uint64_t total;
   int64_t tile_elems;
+  // Device plans for the other tile sizes that the maps' tuned configurations
+  // ask for, so that each map runs on its own tiles.
+  struct OpPlan {
+    int64_t tile_elems;
+    uint64_t ntiles;
+    BatchTile* d_tiles;
+  };
+  std::vector<OpPlan> op_plans;
+  bool tile_pinned;  // set by ts_batch_set_tile: every map uses the primary plan
+  // Bumped whenever a tile table is freed (re-plan) and set to kDeadEpoch on
+  // destruction; graphs captured from the batch share it and refuse to launch
+  // once it has moved, instead of reading freed tile tables.
+  std::shared_ptr<uint64_t> plan_epoch;
 };
 
 struct ts_graph_s {
@@ -110,6 +128,8 @@ struct ts_graph_s {
   int device;
   hipGraph_t graph;
   hipGraphExec_t exec;
+  std::shared_ptr<uint64_t> batch_epoch;  // null for graphs of plain arrays
+  uint64_t epoch_at_capture;
 };
 
 struct ts_event_s {
@@ -235,7 +255,7 @@ int launch_map(ts_target_s* t, int op, int dtype, const void* x, const void* y, 
     const uint64_t cap = static_cast<uint64_t>(cfg.grid_per_cu) * static_cast<uint64_t>(t->info.compute_units);
     if (grid > cap) grid = cap;
   }
-  if (grid > 0x7fffffffull) grid = 0x7fffffffull;  // the loop strides over the rest
+  if (grid > kMaxGridX) grid = kMaxGridX;  // the loop strides over the rest
   PlainLaunch L{};
   L.x = x;
   L.y = has_y ? y : x;
@@ -305,10 +325,15 @@ int run_map(ts_target_s* t, int op, ts_array_s* x, ts_array_s* y, ts_array_s* d,
   return launch_map(t, op, x->dtype, x->ptr, has_y ? y->ptr : nullptr, d->ptr, count, q, cfg);
 }
 
+void bump_epoch(ts_batch_s* b) {
+  if (b->plan_epoch) ++*b->plan_epoch;
+}
+
 // Upload a batch's tile table (blocking).
 int batch_upload(ts_batch_s* b) {
   ts_target_s* t = b->target;
   if (b->d_tiles) {
+    bump_epoch(b);
     (void)hipFree(b->d_tiles);
     b->d_tiles = nullptr;
   }
@@ -340,13 +365,64 @@ int batch_replan(ts_batch_s* b, int64_t tile_elems) {
   return batch_upload(b);
 }
 
+void free_op_plans(ts_batch_s* b) {
+  if (!b->op_plans.empty()) bump_epoch(b);
+  for (const ts_batch_s::OpPlan& p : b->op_plans)
+    if (p.d_tiles) (void)hipFree(p.d_tiles);
+  b->op_plans.clear();
+}
+
+ts_kernel_cfg batch_cfg(const ts_batch_s* b, int op) {
+  return tune_table().lookup(op, b->dtype, b->total, TS_ALIGN_16, 1);
+}
+
+// Plans for the tile sizes of the four maps' configurations that differ from
+// the primary plan's (blocking).  Nothing is planned when the tile is pinned.
+int build_op_plans(ts_batch_s* b) {
+  free_op_plans(b);
+  if (b->tile_pinned || b->tiles.empty()) return TS_OK;
+  for (int op = TS_COPY; op <= TS_TRIAD; ++op) {
+    const int64_t tile = batch_cfg(b, op).tile_elems;
+    if (tile <= 0 || tile == b->tile_elems) continue;
+    bool have = false;
+    for (const ts_batch_s::OpPlan& p : b->op_plans) have = have || p.tile_elems == tile;
+    if (have) continue;
+    std::string err;
+    std::vector<BatchDesc> descs;
+    std::vector<BatchTile> tiles;
+    uint64_t total = 0;
+    const int st = plan_batch(b->host.data(), b->host.size(), dtype_size(b->dtype), tile, descs, tiles,
+                              total, err);
+    if (st != ST_OK) return fail(st, "%s", err.c_str());
+    ts_batch_s::OpPlan p{tile, tiles.size(), nullptr};
+    TS_HIP(hipMalloc(&p.d_tiles, tiles.size() * sizeof(BatchTile)));
+    b->op_plans.push_back(p);
+    TS_HIP(hipMemcpyAsync(p.d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
+                          b->target->stream));
+    TS_HIP(hipStreamSynchronize(b->target->stream));
+  }
+  return TS_OK;
+}
+
 int launch_batch(ts_target_s* t, ts_batch_s* b, int op, const ts_kernel_cfg& cfg) {
   if (b->tiles.empty()) return TS_OK;
   BatchLaunch L{};
   L.tiles = b->d_tiles;
   L.ntiles = b->tiles.size();
-  uint64_t grid = static_cast<uint64_t>(cfg.grid_per_cu) * static_cast<uint64_t>(t->info.compute_units);
+  if (!b->tile_pinned && cfg.tile_elems > 0 && cfg.tile_elems != b->tile_elems) {
+    for (const ts_batch_s::OpPlan& p : b->op_plans)
+      if (p.tile_elems == cfg.tile_elems) {
+        L.tiles = p.d_tiles;
+        L.ntiles = p.ntiles;
+      }
+  }
+  // grid_per_cu 0: one workgroup per tile; otherwise a persistent grid that
+  // strides over the tiles.
+  uint64_t grid = cfg.grid_per_cu > 0
+                      ? static_cast<uint64_t>(cfg.grid_per_cu) * static_cast<uint64_t>(t->info.compute_units)
+                      : L.ntiles;
   if (grid > L.ntiles) grid = L.ntiles;
+  if (grid > kMaxGridX) grid = kMaxGridX;
   if (grid < 1) grid = 1;
   L.grid = static_cast<uint32_t>(grid);
   L.block = static_cast<uint32_t>(cfg.block);
@@ -358,10 +434,6 @@ int launch_batch(ts_target_s* t, ts_batch_s* b, int op, const ts_kernel_cfg& cfg
   const hipError_t e = batch_launch(b->dtype, L);
   if (e != hipSuccess) return hip_fail(e, "batched STREAM kernel launch");
   return TS_OK;
-}
-
-ts_kernel_cfg batch_cfg(const ts_batch_s* b, int op) {
-  return tune_table().lookup(op, b->dtype, b->total, TS_ALIGN_16, 1);
 }
 
 int check_batch_exec(ts_target_s* t, ts_batch_s* b) {
@@ -1028,7 +1100,7 @@ int ts_autotune(ts_target t, ts_op op, ts_dtype dtype, size_t n, size_t offset_e
   const uintptr_t ya = reinterpret_cast<uintptr_t>(p[1]);
   const int cls = align_class(reinterpret_cast<uintptr_t>(p[0]), has_y ? &ya : nullptr,
                               reinterpret_cast<uintptr_t>(p[2]));
-  ts_kernel_cfg best_cfg = default_cfg(0);
+  ts_kernel_cfg best_cfg = default_cfg(0, dtype);
   double best_s = 0;
   const uint64_t bytes = stream_bytes(op, n, es);
   for (const ts_kernel_cfg& c : candidates(0)) {
@@ -1060,7 +1132,10 @@ int ts_autotune_batch(ts_target t, ts_batch b, ts_op op, int reps, ts_kernel_cfg
   if (!valid_op(op)) return fail(TS_E_INVALID, "bad op");
   if (b->total == 0) return fail(TS_E_INVALID, "empty batch");
   const int64_t original_tile = b->tile_elems;
-  ts_kernel_cfg best_cfg = default_cfg(1);
+  const bool pinned = b->tile_pinned;
+  free_op_plans(b);
+  b->tile_pinned = true;  // candidates run on the primary plan, re-planned to their tile
+  ts_kernel_cfg best_cfg = default_cfg(1, b->dtype);
   double best_s = 0;
   for (const ts_kernel_cfg& c : candidates(1)) {
     if (c.tile_elems != b->tile_elems && (st = batch_replan(b, c.tile_elems)) != TS_OK) break;
@@ -1072,13 +1147,16 @@ int ts_autotune_batch(ts_target t, ts_batch b, ts_op op, int reps, ts_kernel_cfg
       best_cfg = c;
     }
   }
-  if (st != TS_OK) {
-    (void)batch_replan(b, original_tile);
-    return st;
-  }
-  if ((st = batch_replan(b, best_cfg.tile_elems)) != TS_OK) return st;
-  const double bps = static_cast<double>(stream_bytes(op, b->total, dtype_size(b->dtype))) / best_s;
-  tune_table().put(TuneKey{op, b->dtype, size_bucket(b->total), TS_ALIGN_16, 1}, TuneEntry{best_cfg, bps});
+  const double bps =
+      best_s > 0 ? static_cast<double>(stream_bytes(op, b->total, dtype_size(b->dtype))) / best_s : 0.0;
+  if (st == TS_OK)
+    tune_table().put(TuneKey{op, b->dtype, size_bucket(b->total), TS_ALIGN_16, 1}, TuneEntry{best_cfg, bps});
+  // Back to the batch's own tile; the maps' plans now follow the updated table.
+  b->tile_pinned = pinned;
+  const int rst = batch_replan(b, original_tile);
+  if (st != TS_OK) return st;
+  if (rst != TS_OK) return rst;
+  if ((st = build_op_plans(b)) != TS_OK) return st;
   if (best) *best = best_cfg;
   if (best_bytes_per_s) *best_bytes_per_s = bps;
   return TS_OK;
@@ -1161,6 +1239,7 @@ int ts_batch_create(ts_target t, ts_dtype dtype, const ts_batch_desc* descs, siz
   int st = use_device(t->device);
   if (st != TS_OK) return st;
   ts_batch_s* b = new ts_batch_s();
+  b->plan_epoch = std::make_shared<uint64_t>(0);
   b->target = t;
   b->device = t->device;
   b->dtype = dtype;
@@ -1175,6 +1254,7 @@ int ts_batch_create(ts_target t, ts_dtype dtype, const ts_batch_desc* descs, siz
                           reinterpret_cast<uintptr_t>(d.c), d.len, d.q};
   }
   auto cleanup = [&](int status) {
+    free_op_plans(b);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     if (b->d_expected) (void)hipFree(b->d_expected);
     if (b->d_counts) (void)hipFree(b->d_counts);
@@ -1205,6 +1285,7 @@ int ts_batch_create(ts_target t, ts_dtype dtype, const ts_batch_desc* descs, siz
   const ts_kernel_cfg sized = tune_table().lookup(TS_TRIAD, dtype, total, TS_ALIGN_16, 1);
   int64_t tile = sized.tile_elems > 0 ? sized.tile_elems : (cfg.tile_elems > 0 ? cfg.tile_elems : 16384);
   st = batch_replan(b, tile);
+  if (st == TS_OK) st = build_op_plans(b);
   if (st != TS_OK) return cleanup(st);
   b->magic = kBatchMagic;
   *out = b;
@@ -1217,9 +1298,11 @@ int ts_batch_destroy(ts_batch b) {
   if (!ok_batch(b)) return fail(TS_E_INVALID, "invalid batch handle");
   (void)use_device(b->device);
   if (ok_target(b->target)) (void)hipStreamSynchronize(b->target->stream);
+  free_op_plans(b);
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   if (b->d_expected) (void)hipFree(b->d_expected);
   if (b->d_counts) (void)hipFree(b->d_counts);
+  *b->plan_epoch = kDeadEpoch;
   b->magic = kDead;
   delete b;
   return TS_OK;
@@ -1239,7 +1322,10 @@ int ts_batch_set_tile(ts_batch b, int64_t tile_elems) {
   if (!ok_batch(b) || !ok_target(b->target)) return fail(TS_E_INVALID, "invalid batch handle");
   int st = use_device(b->device);
   if (st != TS_OK) return st;
-  return batch_replan(b, tile_elems);
+  if ((st = batch_replan(b, tile_elems)) != TS_OK) return st;
+  b->tile_pinned = true;
+  free_op_plans(b);
+  return TS_OK;
   TS_GUARD_END
 }
 
@@ -1336,7 +1422,7 @@ int ts_batch_mismatch_count(ts_target exec, ts_batch b, int which, const double*
 namespace {
 
 template <class Body>
-int capture(ts_target_s* t, Body&& body, ts_graph* out) {
+int capture(ts_target_s* t, Body&& body, ts_graph* out, const ts_batch_s* batch = nullptr) {
   if (!out) return fail(TS_E_INVALID, "NULL out");
   if (t->host) return host_only_gpu("graph capture");
   if (t->stream == nullptr)
@@ -1362,6 +1448,10 @@ int capture(ts_target_s* t, Body&& body, ts_graph* out) {
   g->device = t->device;
   g->graph = graph;
   g->exec = exec;
+  if (batch) {
+    g->batch_epoch = batch->plan_epoch;
+    g->epoch_at_capture = *batch->plan_epoch;
+  }
   g->magic = kGraphMagic;
   *out = g;
   return TS_OK;
@@ -1387,7 +1477,7 @@ int ts_graph_capture_stream_iterations(ts_target t, ts_batch b, int iterations, 
           }
         return static_cast<int>(TS_OK);
       },
-      out);
+      out, b);
   TS_GUARD_END
 }
 
@@ -1400,7 +1490,7 @@ int ts_graph_capture_batch_op(ts_target t, ts_batch b, ts_op op, ts_graph* out) 
   int st = check_batch_exec(t, b);
   if (st != TS_OK) return st;
   if (!valid_op(op)) return fail(TS_E_INVALID, "bad op");
-  return capture(t, [&]() { return launch_batch(t, b, op, batch_cfg(b, op)); }, out);
+  return capture(t, [&]() { return launch_batch(t, b, op, batch_cfg(b, op)); }, out, b);
   TS_GUARD_END
 }
 
@@ -1435,6 +1525,8 @@ int ts_graph_launch(ts_target t, ts_graph g, int repeats) {
   if (t->host) return host_only_gpu("graph launch");
   if (repeats < 0) return fail(TS_E_INVALID, "negative repeat count");
   if (g->device != t->device) return fail(TS_E_PLACEMENT, "graph belongs to another device");
+  if (g->batch_epoch && *g->batch_epoch != g->epoch_at_capture)
+    return fail(TS_E_INVALID, "the graph's batch was re-planned or destroyed after capture");
   int st = use_device(t->device);
   if (st != TS_OK) return st;
   for (int r = 0; r < repeats; ++r) TS_HIP(hipGraphLaunch(g->exec, t->stream));

@@ -31,15 +31,26 @@ int size_bucket(uint64_t n) {
   return b;
 }
 
-ts_kernel_cfg default_cfg(int batched) {
+ts_kernel_cfg default_cfg(int batched, int dtype) {
   ts_kernel_cfg c{};
-  c.block = 256;
-  c.unroll = 4;
   c.vec_bytes = 16;
-  c.nt_load = 0;
   c.nt_store = 1;
-  c.grid_per_cu = batched ? 4 : 0;
-  c.tile_elems = batched ? 16384 : 0;
+  if (batched) {
+    // One workgroup per tile, one 16-byte vector per lane: tiles of 16 KiB
+    // per array, the shape that measured best on the ragged batch.
+    const int64_t es = dtype == TS_F64 ? 8 : dtype == TS_F32 ? 4 : 2;
+    c.block = 1024;
+    c.unroll = 1;
+    c.nt_load = 1;
+    c.grid_per_cu = 0;
+    c.tile_elems = 16384 / es;
+  } else {
+    c.block = 256;
+    c.unroll = 4;
+    c.nt_load = 0;
+    c.grid_per_cu = 0;
+    c.tile_elems = 0;
+  }
   return c;
 }
 
@@ -48,7 +59,7 @@ std::string cfg_problem(const ts_kernel_cfg& c, int batched) {
   if (c.unroll != 1 && c.unroll != 2 && c.unroll != 4 && c.unroll != 8) return "unroll must be 1, 2, 4 or 8";
   if (batched) {
     if (c.vec_bytes != 16) return "batched kernels use 16-byte vectors";
-    if (c.grid_per_cu < 1 || c.grid_per_cu > 64) return "batched grid_per_cu must be 1..64";
+    if (c.grid_per_cu < 0 || c.grid_per_cu > 64) return "batched grid_per_cu must be 0..64";
     if (c.tile_elems < 0 || c.tile_elems % 8) return "tile_elems must be a multiple of 8";
   } else {
     if (c.vec_bytes != 16 && c.vec_bytes != 8 && c.vec_bytes != 4 && c.vec_bytes != 2)
@@ -73,15 +84,19 @@ std::vector<ts_kernel_cfg> candidates(int batched) {
                 out.push_back(ts_kernel_cfg{block, u, vb, ntl, nts, g, 0});
               }
   } else {
-    for (int block : {512, 1024})
-      for (int u : {2, 4, 8})
+    // One workgroup per tile (grid_per_cu 0) with small tiles ...
+    for (int block : {256, 512, 1024})
+      for (int u : {1, 2})
         for (int ntl : {0, 1})
-          for (int nts : {0, 1})
-            for (int g : {4, 8, 16})
-              for (int64_t tile : {4096, 8192, 16384, 65536}) {
-                if (block * g > 8192) continue;  // beyond what the CUs hold resident
-                out.push_back(ts_kernel_cfg{block, u, 16, ntl, nts, g, tile});
-              }
+          for (int64_t tile : {1024, 2048, 4096, 8192})
+            out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, 0, tile});
+    // ... and persistent grids that stride over larger tiles.
+    for (int block : {512, 1024})
+      for (int u : {4, 8})
+        for (int ntl : {0, 1})
+          for (int g : {4, 8})
+            for (int64_t tile : {16384, 65536})
+              out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, g, tile});
   }
   return out;
 }
@@ -106,7 +121,7 @@ ts_kernel_cfg TuneTable::lookup(int op, int dtype, uint64_t n, int align, int ba
     }
   }
   if (best) return best->cfg;
-  ts_kernel_cfg c = default_cfg(b);
+  ts_kernel_cfg c = default_cfg(b, dtype);
   if (align == TS_ALIGN_MIXED && !b) c.vec_bytes = 0;  // caller substitutes the element size
   return c;
 }

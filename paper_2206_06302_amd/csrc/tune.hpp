@@ -33,7 +33,7 @@ struct TuneEntry {
 };
 
 int size_bucket(uint64_t n);
-ts_kernel_cfg default_cfg(int batched);
+ts_kernel_cfg default_cfg(int batched, int dtype);
 // Empty string if cfg is a valid configuration (plain or batched), else why not.
 std::string cfg_problem(const ts_kernel_cfg& cfg, int batched);
 std::vector<ts_kernel_cfg> candidates(int batched);

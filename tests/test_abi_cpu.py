@@ -165,8 +165,19 @@ def test_forced_configuration(ts):
         cfg.update(bad)
         with pytest.raises(ts.TSError):
             ts.set_kernel_cfg("copy", "f64", cfg)
-    with pytest.raises(ts.TSError):  # batched kernels require 16-byte vectors and a persistent grid
+    with pytest.raises(ts.TSError):  # batched kernels require 16-byte vectors
         ts.set_kernel_cfg("copy", "f64", {"vec_bytes": 8, "grid_per_cu": 4, "tile_elems": 8192}, batched=True)
+    for bad in ({"grid_per_cu": -1}, {"grid_per_cu": 65}, {"tile_elems": 12}):
+        cfg = {"block": 1024, "unroll": 4, "vec_bytes": 16, "nt_load": 1, "nt_store": 1, "grid_per_cu": 0,
+               "tile_elems": 4096}
+        cfg.update(bad)
+        with pytest.raises(ts.TSError):
+            ts.set_kernel_cfg("copy", "f64", cfg, batched=True)
+    # grid_per_cu 0 on the batched path: one workgroup per tile
+    ts.set_kernel_cfg("copy", "f64", {"block": 1024, "unroll": 4, "vec_bytes": 16, "nt_load": 1, "nt_store": 1,
+                                      "grid_per_cu": 0, "tile_elems": 4096}, batched=True)
+    assert ts.get_kernel_cfg("copy", "f64", 1 << 30, batched=True)["grid_per_cu"] == 0
+    ts.set_kernel_cfg("copy", "f64", None, batched=True)
 
 
 def test_candidate_sets_are_valid(ts):

@@ -281,3 +281,114 @@ def test_batch_tile_sizes_do_not_change_results(env):
             assert torch.equal(pool.t[k].view(torch.int64), ref_pool.t[k].view(torch.int64)), (tile, k)
         b.close()
     ref.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "bf16"])
+def test_batch_launch_shapes_do_not_change_results(env, dtype):
+    """One workgroup per tile (grid_per_cu 0) and persistent grids of several
+    sizes give the per-instance plain launches' results bit for bit."""
+    ts, torch, tgt = env
+    rng = np.random.default_rng(12)
+    lens = _lens(rng, 24)
+    mis = _mis(rng, 24, ts.ELEM_SIZE[dtype])
+    qs = tsgen.batched_scalars(9, 24)
+    ref_pool = Pool(ts, torch, lens, dtype, mis)
+    ref = ts.Batch(tgt, dtype, ref_pool.descs(qs))
+    for k in range(3):
+        ref.fill_uniform(tgt, k, 6)
+    for op in OPS:
+        ref.op_plain(tgt, op)
+    shapes = [(0, 256, 1, 24), (0, 1024, 4, 4096), (0, 512, 2, 2048), (1, 1024, 8, 16384), (64, 64, 1, 8)]
+    try:
+        for grid, block, unroll, tile in shapes:
+            cfg = {"block": block, "unroll": unroll, "vec_bytes": 16, "nt_load": 1, "nt_store": 1,
+                   "grid_per_cu": grid, "tile_elems": tile}
+            for op in OPS:
+                ts.set_kernel_cfg(op, dtype, cfg, batched=True)
+            pool = Pool(ts, torch, lens, dtype, mis)
+            b = ts.Batch(tgt, dtype, pool.descs(qs))
+            b.set_tile(tile)
+            for k in range(3):
+                b.fill_uniform(tgt, k, 6)
+            say(f"[launch shape grid_per_cu={grid} block={block} U{unroll} tile={tile} {dtype}]")
+            for op in OPS:
+                b.op(tgt, op)
+            tgt.synchronize()
+            for k in range(3):
+                assert torch.equal(pool.t[k].view(torch.int16), ref_pool.t[k].view(torch.int16)), (grid, tile, k)
+            b.close()
+    finally:
+        for op in OPS:
+            ts.set_kernel_cfg(op, dtype, None, batched=True)
+    ref.close()
+
+
+def test_each_map_runs_on_its_own_tiles(env):
+    """Configurations with a different tile size per map give one batch
+    several tile plans; eager maps and a captured iteration both equal the
+    per-instance plain launches bit for bit."""
+    ts, torch, tgt = env
+    rng = np.random.default_rng(13)
+    lens = _lens(rng, 24)
+    mis = _mis(rng, 24, 8)
+    qs = tsgen.batched_scalars(10, 24)
+    cfgs = {"copy": (0, 512, 1, 1024), "scale": (8, 1024, 4, 16384), "add": (0, 1024, 2, 4096),
+            "triad": (0, 256, 1, 24)}
+    ref_pool = Pool(ts, torch, lens, "f64", mis)
+    ref = ts.Batch(tgt, "f64", ref_pool.descs(qs))
+    for k in range(3):
+        ref.fill_uniform(tgt, k, 7)
+    try:
+        for op, (grid, block, unroll, tile) in cfgs.items():
+            ts.set_kernel_cfg(op, "f64", {"block": block, "unroll": unroll, "vec_bytes": 16, "nt_load": 1,
+                                          "nt_store": 1, "grid_per_cu": grid, "tile_elems": tile}, batched=True)
+        pool = Pool(ts, torch, lens, "f64", mis)
+        b = ts.Batch(tgt, "f64", pool.descs(qs))
+        assert b.info()["tile_elems"] == 24  # the primary plan follows the triad
+        for k in range(3):
+            b.fill_uniform(tgt, k, 7)
+        say("[per-map tile plans]")
+        for op in OPS:
+            b.op(tgt, op)
+            ref.op_plain(tgt, op)
+        g = ts.Graph.capture_stream_iteration(tgt, b, iterations=2)
+        g.launch(tgt, 1)
+        for _ in range(2):
+            for op in OPS:
+                ref.op_plain(tgt, op)
+        tgt.synchronize()
+        for k in range(3):
+            assert torch.equal(pool.t[k].view(torch.int64), ref_pool.t[k].view(torch.int64)), k
+        g.close()
+        b.close()
+    finally:
+        for op in OPS:
+            ts.set_kernel_cfg(op, "f64", None, batched=True)
+    ref.close()
+
+
+def test_graph_refuses_a_replanned_or_destroyed_batch(env):
+    """A re-plan frees the tile tables a captured graph points to: launching
+    that graph afterwards is refused on the host."""
+    ts, torch, tgt = env
+    lens = [1000, 5000, 17]
+    pool = Pool(ts, torch, lens, "f64")
+    b = ts.Batch(tgt, "f64", pool.descs([2.0] * 3))
+    for k, v in enumerate((1.0, 2.0, 0.0)):
+        b.fill(tgt, k, v)
+    g = ts.Graph.capture_stream_iteration(tgt, b)
+    g.launch(tgt, 1)
+    tgt.synchronize()
+    b.set_tile(4096)
+    with pytest.raises(ts.TSError) as e:
+        g.launch(tgt, 1)
+    assert e.value.status == -1 and "re-planned" in e.value.message
+    g.close()
+    g2 = ts.Graph.capture_batch_op(tgt, b, "triad")
+    g2.launch(tgt, 1)
+    tgt.synchronize()
+    b.close()
+    with pytest.raises(ts.TSError) as e:
+        g2.launch(tgt, 1)
+    assert e.value.status == -1
+    g2.close()
