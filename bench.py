@@ -86,25 +86,44 @@ def uniform_arrays(ts, tgt, arrays) -> bool:
     return all(ts.checksum(tgt, arr, first_value(arr))["mismatches"] == 0 for arr in arrays)
 
 
-def closed_form_check(ts, tgt, A, B, C, iters=10) -> bool:
-    """STREAM's closed form from (1, 2, 0) with q = 3: after k iterations
-    a = 15^k, b = 3*15^(k-1), c = 4*15^(k-1), exact in binary64 for k <= 13."""
+def expected_integers(order, iters):
+    """(a, b, c) after `iters` iterations from (1, 2, 0) with q = 3, in exact
+    integer arithmetic (every intermediate is an integer below 2^53 here, so
+    binary64 reproduces it exactly).  Listing order: a = 15^k, b = 3*15^(k-1),
+    c = 4*15^(k-1); the copy_b variant follows its own recurrence."""
+    a, b, c = 1, 2, 0
+    for _ in range(iters):
+        if order == "listing":
+            c = a
+        else:
+            a = b
+        b = 3 * c
+        c = a + b
+        a = b + 3 * c
+    assert max(a, b, c) < 2 ** 53
+    return float(a), float(b), float(c)
+
+
+def closed_form_check(ts, tgt, A, B, C, iters=10, order="listing") -> bool:
+    """The 10-iteration run from (1, 2, 0) with q = 3 must give the exact
+    integers of STREAM's closed form, at every element."""
     A.fill(1.0), B.fill(2.0), C.fill(0.0)
     for _ in range(iters):
-        ts.stream_iteration(tgt, A, B, C, 3.0)
-    exp = (15.0 ** iters, 3.0 * 15 ** (iters - 1), 4.0 * 15 ** (iters - 1))
+        ts.stream_iteration(tgt, A, B, C, 3.0, order=order)
+    exp = expected_integers(order, iters)
     return all(ts.checksum(tgt, arr, e)["mismatches"] == 0 for arr, e in zip((A, B, C), exp))
 
 
-def main_leg(ts, torch, tgt, n, steps, warmup):
+def main_leg(ts, torch, tgt, n, steps, warmup, order="listing"):
     """Headline: FP64 STREAM at n elements; returns the result dict."""
     A, B, C = (ts.Array.alloc(tgt, "f64", n) for _ in range(3))
     A.fill(1.0), B.fill(2.0), C.fill(0.0)
     tgt.synchronize()
-    roles = {"copy": (A, None, C), "scale": (C, None, B), "add": (A, B, C), "triad": (B, C, A)}
+    roles = {"copy": (A, None, C) if order == "listing" else (B, None, A),
+             "scale": (C, None, B), "add": (A, B, C), "triad": (B, C, A)}
     ev = [[ts.Event() for _ in range(5)] for _ in range(steps)]
     for _ in range(warmup):
-        ts.stream_iteration(tgt, A, B, C, 3.0)
+        ts.stream_iteration(tgt, A, B, C, 3.0, order=order)
     tgt.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -121,7 +140,7 @@ def main_leg(ts, torch, tgt, n, steps, warmup):
     per = {op: [ev[s][k].elapsed_ms(ev[s][k + 1]) for s in range(steps)] for k, op in enumerate(OPS)}
     step_ms = [ev[s][0].elapsed_ms(ev[s][4]) for s in range(steps)]
     # every element followed the same chain; then STREAM's closed form
-    valid = uniform_arrays(ts, tgt, (A, B, C)) and closed_form_check(ts, tgt, A, B, C)
+    valid = uniform_arrays(ts, tgt, (A, B, C)) and closed_form_check(ts, tgt, A, B, C, order=order)
     kernels = {}
     for op in OPS:
         b = ts.stream_bytes(op, n)
@@ -398,6 +417,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline leg only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--autotune", action="store_true", help="re-tune the four maps before timing")
+    ap.add_argument("--order", choices=("listing", "copy_b"), default="listing",
+                    help="listing: copy c = a (Listing 4); copy_b: the variant with copy a = b")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -420,7 +441,7 @@ def main():
             log(f"autotune {op}: {bps/1e9:.1f} GB/s {cfg}")
 
     log(f"main leg: f64 N={a.n}, warmup={a.warmup}, steps={a.steps}")
-    m = main_leg(ts, torch, tgt, a.n, a.steps, a.warmup)
+    m = main_leg(ts, torch, tgt, a.n, a.steps, a.warmup, a.order)
     if not m["valid"]:
         print("validation failed: arrays not uniform, or the closed-form run differs", file=sys.stderr)
         sys.exit(1)
@@ -445,7 +466,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "stream_f64_n2^27", "n": a.n, "arrays": 3, "q": 3.0,
-                   "init": "a=1,b=2,c=0 (device fill)", "order": "copy,scale,add,triad",
+                   "init": "a=1,b=2,c=0 (device fill)",
+                   "order": "copy c=a,scale,add,triad" if a.order == "listing" else "copy a=b,scale,add,triad",
                    "bytes_per_step": step_bytes},
         "triad_best_GBps": tri["best_GBps"],
         "triad_pct_peak_best": tri["pct_peak_best"],

@@ -72,6 +72,7 @@ def lib() -> ctypes.CDLL:
             "oracle_triad_f64": [P, P, P, S, D],
             "oracle_stream_iteration_f64": [P, P, P, S, D],
             "oracle_stream_run_f64": [P, P, P, S, D, I],
+            "oracle_stream_run_copyb_f64": [P, P, P, S, D, I],
             "oracle_f32_to_bf16_array": [P, P, S],
             "oracle_f32_to_f16_array": [P, P, S],
             "oracle_bf16_to_f32_array": [P, P, S],
@@ -132,6 +133,15 @@ def stream_run(dtype: int, a: np.ndarray, b: np.ndarray, c: np.ndarray, q: float
         lib().oracle_stream_run_f64(_ptr(a), _ptr(b), _ptr(c), n, q, iterations)
     else:
         lib().oracle_stream_run(dtype, _ptr(a), _ptr(b), _ptr(c), n, q, iterations)
+
+
+def stream_run_copyb_f64(a: np.ndarray, b: np.ndarray, c: np.ndarray, q: float = 3.0,
+                         iterations: int = 1) -> None:
+    """The variant with copy a <- b (scale, add, triad as listed), in place."""
+    n = a.shape[0]
+    for arr, nm in ((a, "a"), (b, "b"), (c, "c")):
+        _check(arr, F64, n, nm)
+    lib().oracle_stream_run_copyb_f64(_ptr(a), _ptr(b), _ptr(c), n, q, iterations)
 
 
 def stream_scalar_f64(a0: float, b0: float, c0: float, q: float, iterations: int):

@@ -69,6 +69,22 @@ void oracle_stream_run_f64(double *a, double *b, double *c, size_t n, double q,
         oracle_stream_iteration_f64(a, b, c, n, q);
 }
 
+void oracle_stream_iteration_copyb_f64(double *a, double *b, double *c,
+                                       size_t n, double q)
+{
+    oracle_copy_f64(b, a, n);        /* a = b         */
+    oracle_scale_f64(c, b, n, q);    /* b = q * c     */
+    oracle_add_f64(a, b, c, n);      /* c = a + b     */
+    oracle_triad_f64(b, c, a, n, q); /* a = b + q * c */
+}
+
+void oracle_stream_run_copyb_f64(double *a, double *b, double *c, size_t n,
+                                 double q, int iterations)
+{
+    for (int it = 0; it < iterations; ++it)
+        oracle_stream_iteration_copyb_f64(a, b, c, n, q);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Storage-format converters, written from the IEEE-754 format definitions. */
 /* ------------------------------------------------------------------------ */

@@ -61,6 +61,13 @@ void oracle_stream_iteration_f64(double *a, double *b, double *c, size_t n,
                                  double q);
 void oracle_stream_run_f64(double *a, double *b, double *c, size_t n, double q,
                            int iterations);
+/* The variant whose copy runs a <- b (the direction some one-line summaries
+ * of STREAM write); scale, add and triad as in the listing:
+ * copy (b -> a), scale (c -> b), add (a, b -> c), triad (b, c -> a). */
+void oracle_stream_iteration_copyb_f64(double *a, double *b, double *c,
+                                       size_t n, double q);
+void oracle_stream_run_copyb_f64(double *a, double *b, double *c, size_t n,
+                                 double q, int iterations);
 
 /* --- Reduced-precision storage ------------------------------------------ */
 /* Round-to-nearest-even narrowing of a binary32 value; NaN stays NaN (quiet,

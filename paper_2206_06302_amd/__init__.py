@@ -299,9 +299,23 @@ def triad(target: Target, x: Array, y: Array, dst: Array, q: float) -> None:
     _check(lib.ts_triad(target.handle, x.handle, y.handle, dst.handle, float(q)))
 
 
-def stream_iteration(target: Target, a: Array, b: Array, c: Array, q: float = 3.0) -> None:
-    """One iteration of Listing 4: c = a; b = q*c; c = a + b; a = b + q*c."""
-    _check(lib.ts_stream_iteration(target.handle, a.handle, b.handle, c.handle, float(q)))
+ORDERS = ("listing", "copy_b")
+
+
+def stream_iteration(target: Target, a: Array, b: Array, c: Array, q: float = 3.0,
+                     order: str = "listing") -> None:
+    """One iteration of Listing 4: c = a; b = q*c; c = a + b; a = b + q*c.
+    order="copy_b" runs the variant whose copy is a = b (the direction some
+    summaries of STREAM write), the other maps unchanged, as four calls."""
+    if order == "listing":
+        _check(lib.ts_stream_iteration(target.handle, a.handle, b.handle, c.handle, float(q)))
+    elif order == "copy_b":
+        copy(target, b, a)
+        scale(target, c, b, q)
+        add(target, a, b, c)
+        triad(target, b, c, a, q)
+    else:
+        raise ValueError(f"order must be one of {ORDERS}")
 
 
 def run_op(target: Target, op, x: Array, y: Array | None, dst: Array, q: float = 3.0) -> None:

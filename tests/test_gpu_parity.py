@@ -287,6 +287,28 @@ def test_multi_iteration_graph_matches_oracle(env, n, offset):
         assert_same_bits(X.to_host(), ref, "f64", nm)
 
 
+@pytest.mark.parametrize("n,offset", [(100003, 1), ((1 << 16) + 8, 0)])
+def test_copy_b_variant_matches_oracle(env, n, offset):
+    """The variant with copy a = b, from random values, 12 iterations, and
+    from (1, 2, 0) against the oracle's pinned integer closed form."""
+    ts, torch, tgt = env
+    a, b, c = _inputs(n, "f64", seed=29)
+    A, B, C = (device_array(ts, torch, tgt, v, "f64", offset) for v in (a, b, c))
+    say(f"[copy_b variant] n={n} offset={offset}")
+    for _ in range(12):
+        ts.stream_iteration(tgt, A, B, C, 3.0, order="copy_b")
+    oracle.stream_run_copyb_f64(a, b, c, 3.0, 12)
+    for X, ref, nm in ((A, a, "a"), (B, b, "b"), (C, c, "c")):
+        assert_same_bits(X.to_host(), ref, "f64", nm)
+    A.fill(1.0), B.fill(2.0), C.fill(0.0)
+    for _ in range(21):
+        ts.stream_iteration(tgt, A, B, C, 3.0, order="copy_b")
+    s = [np.array([v]) for v in (1.0, 2.0, 0.0)]
+    oracle.stream_run_copyb_f64(*s, 3.0, 21)
+    for X, ref in zip((A, B, C), s):
+        assert ts.checksum(tgt, X, float(ref[0]))["mismatches"] == 0
+
+
 def test_futures_become_ready_after_the_work(env):
     """A future of the work enqueued so far is made ready by a stream callback
     once that work has finished; its results are then visible to the host."""

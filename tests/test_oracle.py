@@ -66,6 +66,59 @@ def test_fused_triad_is_detectable_at_50(oracle_lib):
     assert abs(got[0] - 15.0 ** 50) / 15.0 ** 50 < 1e-15
 
 
+# ------------------------------------------- variant with copy a <- b
+def _binet_copyb(k):
+    """Closed form of the variant from (1, 2, 0) with q = 3.  One iteration
+    maps (a, b, c) to (3b + 12c, 3c, b + 3c), so c follows
+    c[k+1] = 3c[k] + 3c[k-1] with c[0] = 0, c[1] = 2, whose solution is
+    c[k] = 2 (l1^k - l2^k) / sqrt(21), l1,2 = (3 +- sqrt(21)) / 2; then
+    b[k] = 3c[k-1] and a[k] = b[k] + 3c[k].  Evaluated in 60-digit decimal
+    arithmetic and rounded to the nearest integer."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    r = Decimal(21).sqrt()
+    l1, l2 = (3 + r) / 2, (3 - r) / 2
+
+    def cc(j):
+        return int((2 * (l1 ** j - l2 ** j) / r).to_integral_value())
+    c = cc(k)
+    b = 3 * cc(k - 1)
+    return b + 3 * c, b, c
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 10, 21, 25])
+def test_copyb_variant_closed_form(oracle_lib, k):
+    exp = _binet_copyb(k)
+    assert max(exp) < 2 ** 53  # exact in binary64
+    n = 19
+    a, b, c = np.full(n, 1.0), np.full(n, 2.0), np.full(n, 0.0)
+    oracle_lib.stream_run_copyb_f64(a, b, c, 3.0, k)
+    assert np.all(a == exp[0]) and np.all(b == exp[1]) and np.all(c == exp[2])
+
+
+def test_copyb_variant_ten_iterations_values():
+    assert _binet_copyb(10) == (1015254, 211896, 267786)
+
+
+def test_copyb_variant_random_matches_exact_ops(oracle_lib):
+    """Random operands, 3 iterations, every step an exactly rounded IEEE
+    operation (exact rational arithmetic, rounded once)."""
+    rng = np.random.default_rng(31)
+    n = 9
+    a, b, c = (_random_f64(rng, n) for _ in range(3))
+    q = -1.3
+    ra, rb, rc = a.copy(), b.copy(), c.copy()
+    oracle_lib.stream_run_copyb_f64(a, b, c, q, 3)
+    for j in range(n):
+        x, y, z = float(ra[j]), float(rb[j]), float(rc[j])
+        for _ in range(3):
+            x = y
+            y = exact.mul(q, z, "f64")
+            z = exact.add(x, y, "f64")
+            x = exact.fma(q, z, y, "f64")
+        assert _same(a[j], x) and _same(b[j], y) and _same(c[j], z), j
+
+
 # -------------------------------------------------------- brute force (f64)
 def _special_f64():
     return np.array([0.0, -0.0, 1.0, -1.0, 5e-324, -5e-324, 2.2250738585072014e-308,
