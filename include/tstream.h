@@ -184,8 +184,17 @@ TS_API int ts_array_info(ts_array array, void **dev_ptr, size_t *n,
  *   u = (h >> 11) * 2^-52 - 1,  h = SplitMix64 output number
  *   (first_index + j + 1) from the state seed ^ (stream_id << 48),
  * an exact binary64 value in [-1, 1), narrowed to binary32 by RNE and then,
- * for bfloat16/binary16, to the storage type by RNE.  Asynchronous. */
+ * for bfloat16/binary16, to the storage type by RNE.  Asynchronous.
+ * ts_fill_uniform_range stores lo + w * ((h >> 11) * 2^-53), w = hi - lo,
+ * each operation rounded in binary64 (so values lie in [lo, hi], hi only
+ * through rounding), then narrowed the same way; with
+ * lo = -1, hi = 1 it equals ts_fill_uniform bit for bit.  lo < hi, both
+ * finite with a finite difference, else TS_E_INVALID.  stream_id < 2^16.
+ * Floating-point storage only (TS_E_UNSUPPORTED for TS_U8). */
 TS_API int ts_fill(ts_array array, double value);
+TS_API int ts_fill_uniform_range(ts_array array, uint64_t seed,
+                                 uint64_t stream_id, uint64_t first_index,
+                                 double lo, double hi);
 TS_API int ts_fill_uniform(ts_array array, uint64_t seed, uint64_t stream_id,
                            uint64_t first_index);
 

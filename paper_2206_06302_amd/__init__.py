@@ -244,8 +244,13 @@ class Array:
         _check(lib.ts_fill(self.handle, float(value)))
         return self
 
-    def fill_uniform(self, seed: int, stream_id: int, first_index: int = 0) -> "Array":
-        _check(lib.ts_fill_uniform(self.handle, int(seed), int(stream_id), int(first_index)))
+    def fill_uniform(self, seed: int, stream_id: int, first_index: int = 0, lo: float = -1.0,
+                     hi: float = 1.0) -> "Array":
+        if (lo, hi) == (-1.0, 1.0):
+            _check(lib.ts_fill_uniform(self.handle, int(seed), int(stream_id), int(first_index)))
+        else:
+            _check(lib.ts_fill_uniform_range(self.handle, int(seed), int(stream_id), int(first_index),
+                                             float(lo), float(hi)))
         return self
 
     def copy_from_host(self, host: np.ndarray) -> None:

@@ -107,6 +107,7 @@ PROTOTYPES = {
     "ts_array_info": [H, ctypes.POINTER(P), ctypes.POINTER(SZ), ctypes.POINTER(I)],
     "ts_fill": [H, D],
     "ts_fill_uniform": [H, U64, U64, U64],
+    "ts_fill_uniform_range": [H, U64, U64, U64, D, D],
     "ts_copy_from_host": [H, P, SZ],
     "ts_copy_to_host": [P, H, SZ],
     "ts_copy": [H, H, H],

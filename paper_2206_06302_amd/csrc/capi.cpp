@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
@@ -844,20 +845,24 @@ int ts_fill(ts_array a, double value) {
   return TS_OK;
 }
 
-int ts_fill_uniform(ts_array a, uint64_t seed, uint64_t stream_id, uint64_t first_index) {
+int ts_fill_uniform_range(ts_array a, uint64_t seed, uint64_t stream_id, uint64_t first_index, double vlo,
+                          double vhi) {
   if (!ok_array(a) || !ok_target(a->target)) return fail(TS_E_INVALID, "invalid array handle");
   if (!map_dtype(a->dtype)) return fail(TS_E_UNSUPPORTED, "fills take floating-point storage");
   if (stream_id >= (1ull << 16)) return fail(TS_E_INVALID, "stream_id must be below 2^16");
+  const double w = vhi - vlo;
+  if (!(vlo < vhi) || !std::isfinite(vlo) || !std::isfinite(vhi) || !std::isfinite(w))
+    return fail(TS_E_INVALID, "the range needs finite lo < hi with a finite difference");
   if (a->n == 0) return TS_OK;
   if (a->target->host) {
     const uint64_t state0 = seed ^ (stream_id << 48);
     if (a->dtype == TS_F64)
       host_blocks(a->target, a->n, [&](uint64_t lo, uint64_t hi, int) {
-        host_fill_uniform_f64(static_cast<double*>(a->ptr), lo, hi, state0, first_index);
+        host_fill_uniform_f64(static_cast<double*>(a->ptr), lo, hi, state0, first_index, vlo, w);
       });
     else if (a->dtype == TS_F32)
       host_blocks(a->target, a->n, [&](uint64_t lo, uint64_t hi, int) {
-        host_fill_uniform_f32(static_cast<float*>(a->ptr), lo, hi, state0, first_index);
+        host_fill_uniform_f32(static_cast<float*>(a->ptr), lo, hi, state0, first_index, vlo, w);
       });
     else
       return fail(TS_E_UNSUPPORTED, "host targets support binary64 and binary32 storage");
@@ -866,9 +871,13 @@ int ts_fill_uniform(ts_array a, uint64_t seed, uint64_t stream_id, uint64_t firs
   int st = use_device(a->device);
   if (st != TS_OK) return st;
   const hipError_t e =
-      launch_fill_uniform(a->dtype, a->ptr, a->n, seed, stream_id, first_index, a->target->stream);
+      launch_fill_uniform(a->dtype, a->ptr, a->n, seed, stream_id, first_index, vlo, w, a->target->stream);
   if (e != hipSuccess) return hip_fail(e, "uniform fill kernel launch");
   return TS_OK;
+}
+
+int ts_fill_uniform(ts_array a, uint64_t seed, uint64_t stream_id, uint64_t first_index) {
+  return ts_fill_uniform_range(a, seed, stream_id, first_index, -1.0, 1.0);
 }
 
 int ts_copy_from_host(ts_array dst, const void* src, size_t n) {
@@ -1092,7 +1101,8 @@ int ts_autotune(ts_target t, ts_op op, ts_dtype dtype, size_t n, size_t offset_e
   for (int i = 0; i < 3; ++i) {
     p[i] = static_cast<char*>(base[i]) + offset_elems * es;
     if (st == TS_OK) {
-      const hipError_t e = launch_fill_uniform(dtype, p[i], n, 1, static_cast<uint64_t>(i), 0, t->stream);
+      const hipError_t e =
+          launch_fill_uniform(dtype, p[i], n, 1, static_cast<uint64_t>(i), 0, -1.0, 2.0, t->stream);
       if (e != hipSuccess) st = hip_fail(e, "fill kernel launch");
     }
   }

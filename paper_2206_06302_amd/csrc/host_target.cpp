@@ -205,10 +205,6 @@ uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-double uniform_at(uint64_t state0, uint64_t counter) {
-  return static_cast<double>(mix64(state0 + counter * kGamma) >> 11) * 0x1p-52 - 1.0;
-}
-
 template <class T>
 HostPart checksum_block(const T* x, uint64_t lo, uint64_t hi, double e) {
   HostPart p{0.0, 0.0, std::nan(""), 0};
@@ -247,12 +243,21 @@ void host_fill_f32(float* d, uint64_t lo, uint64_t hi, float v) {
   for (uint64_t j = lo; j < hi; ++j) d[j] = v;
 }
 
-void host_fill_uniform_f64(double* d, uint64_t lo, uint64_t hi, uint64_t state0, uint64_t first) {
-  for (uint64_t j = lo; j < hi; ++j) d[j] = uniform_at(state0, first + j + 1);
+// vlo + w * u01, u01 = (h >> 11) * 2^-53, with separate roundings.
+static double uniform_range_at(uint64_t state0, uint64_t counter, double vlo, double w) {
+  const double u01 = static_cast<double>(mix64(state0 + counter * kGamma) >> 11) * 0x1p-53;
+  const double scaled = w * u01;
+  return vlo + scaled;
 }
 
-void host_fill_uniform_f32(float* d, uint64_t lo, uint64_t hi, uint64_t state0, uint64_t first) {
-  for (uint64_t j = lo; j < hi; ++j) d[j] = static_cast<float>(uniform_at(state0, first + j + 1));
+void host_fill_uniform_f64(double* d, uint64_t lo, uint64_t hi, uint64_t state0, uint64_t first, double vlo,
+                           double w) {
+  for (uint64_t j = lo; j < hi; ++j) d[j] = uniform_range_at(state0, first + j + 1, vlo, w);
+}
+
+void host_fill_uniform_f32(float* d, uint64_t lo, uint64_t hi, uint64_t state0, uint64_t first, double vlo,
+                           double w) {
+  for (uint64_t j = lo; j < hi; ++j) d[j] = static_cast<float>(uniform_range_at(state0, first + j + 1, vlo, w));
 }
 
 HostPart host_checksum_f64(const double* x, uint64_t lo, uint64_t hi, double expected) {

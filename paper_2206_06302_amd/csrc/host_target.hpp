@@ -57,8 +57,11 @@ void host_map_f64(int op, const double* x, const double* y, double* d, uint64_t 
 void host_map_f32(int op, const float* x, const float* y, float* d, uint64_t lo, uint64_t hi, float q);
 void host_fill_f64(double* d, uint64_t lo, uint64_t hi, double v);
 void host_fill_f32(float* d, uint64_t lo, uint64_t hi, float v);
-void host_fill_uniform_f64(double* d, uint64_t lo, uint64_t hi, uint64_t state0, uint64_t first);
-void host_fill_uniform_f32(float* d, uint64_t lo, uint64_t hi, uint64_t state0, uint64_t first);
+// Elements [lo, hi) of the uniform fill over [vlo, vlo + w).
+void host_fill_uniform_f64(double* d, uint64_t lo, uint64_t hi, uint64_t state0, uint64_t first, double vlo,
+                           double w);
+void host_fill_uniform_f32(float* d, uint64_t lo, uint64_t hi, uint64_t state0, uint64_t first, double vlo,
+                           double w);
 
 struct HostPart {
   double sum, absdev, maxdev;

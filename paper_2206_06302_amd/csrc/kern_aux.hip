@@ -54,14 +54,22 @@ __global__ __launch_bounds__(256) void fill_const_kernel(void* p, uint64_t n, do
     d[j] = v;
 }
 
+// lo + w * u01 with u01 = (h >> 11) * 2^-53 in [0, 1): a product and a sum,
+// each rounded (nothing is contracted).  For lo = -1, w = 2 every step is
+// exact and the value equals uniform_pm1's.
+__device__ __forceinline__ double uniform_range(uint64_t state0, uint64_t counter, double lo, double w) {
+  const uint64_t h = splitmix64_mix(state0 + counter * kGamma);
+  return lo + w * (static_cast<double>(h >> 11) * 0x1p-53);
+}
+
 template <int DT>
 __global__ __launch_bounds__(256) void fill_uniform_kernel(void* p, uint64_t n, uint64_t state0,
-                                                           uint64_t first) {
+                                                           uint64_t first, double lo, double w) {
   using T = typename Fmt<DT>::T;
   T* d = static_cast<T*>(p);
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n; j += stride)
-    d[j] = from_f64<DT>(uniform_pm1(state0, first + j + 1));
+    d[j] = from_f64<DT>(uniform_range(state0, first + j + 1, lo, w));
 }
 
 __device__ __forceinline__ void combine(CsPart& a, const CsPart& b) {
@@ -212,9 +220,10 @@ hipError_t launch_fill_const(int dt, void* p, uint64_t n, double value, hipStrea
 }
 
 hipError_t launch_fill_uniform(int dt, void* p, uint64_t n, uint64_t seed, uint64_t stream_id,
-                               uint64_t first_index, hipStream_t s) {
+                               uint64_t first_index, double lo, double w, hipStream_t s) {
   const uint64_t state0 = seed ^ (stream_id << 48);
-  TS_BY_FORMAT(dt, fill_uniform_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, n, state0, first_index)
+  TS_BY_FORMAT(dt, fill_uniform_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, n, state0, first_index,
+               lo, w)
 }
 
 hipError_t launch_checksum(int dt, const void* x, uint64_t n, double expected, void* scratch,

@@ -58,8 +58,9 @@ uint32_t reduce_parts(uint64_t n);
 constexpr size_t kReduceScratchBytes = (kReduceMaxParts + 1) * sizeof(CsPart);
 
 hipError_t launch_fill_const(int dt, void* p, uint64_t n, double value, hipStream_t s);
+// Element j: lo + w * u01(first_index + j + 1), narrowed to the storage type.
 hipError_t launch_fill_uniform(int dt, void* p, uint64_t n, uint64_t seed, uint64_t stream_id,
-                               uint64_t first_index, hipStream_t s);
+                               uint64_t first_index, double lo, double w, hipStream_t s);
 // Leaves the reduced CsPart at scratch + kReduceMaxParts parts.
 hipError_t launch_checksum(int dt, const void* x, uint64_t n, double expected, void* scratch,
                            hipStream_t s);

@@ -88,7 +88,7 @@ std::vector<ts_kernel_cfg> candidates(int batched) {
     for (int block : {256, 512, 1024})
       for (int u : {1, 2})
         for (int ntl : {0, 1})
-          for (int64_t tile : {1024, 2048, 4096, 8192})
+          for (int64_t tile : {512, 1024, 2048, 4096, 8192})
             out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, 0, tile});
     // ... and persistent grids that stride over larger tiles.
     for (int block : {512, 1024})

@@ -186,6 +186,22 @@ def test_fill_uniform_matches_generator(env, dtype, first):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+@pytest.mark.parametrize("lo,hi", [(0.5, 4.0), (-3.0, 1e-3), (-1.0, 1.0)])
+def test_fill_uniform_range_matches_generator(env, dtype, lo, hi):
+    """The range form draws the host generator's values; on [-1, 1) it is the
+    default fill bit for bit."""
+    ts, torch, tgt = env
+    n = (1 << 15) + 3
+    A = empty_array(ts, torch, tgt, n, dtype)
+    say(f"[fill_uniform_range {dtype} [{lo}, {hi})]")
+    rc = ts.lib.ts_fill_uniform_range(A.handle, 6, 3, 77, lo, hi)
+    assert rc == 0, ts.last_error()
+    assert_same_bits(A.to_host(), tsgen.uniform_array(6, 3, n, dtype, start=77, lo=lo, hi=hi), dtype, "range")
+    for bad in ((1.0, 1.0), (2.0, 1.0), (float("nan"), 1.0), (0.0, float("inf")), (-1e308, 1e308)):
+        assert ts.lib.ts_fill_uniform_range(A.handle, 6, 3, 0, bad[0], bad[1]) == -1
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
 def test_checksum_against_oracle(env, dtype):
     ts, torch, tgt = env
     n = (1 << 20) + 11

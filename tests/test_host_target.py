@@ -91,6 +91,21 @@ def test_host_fill_uniform_matches_generator(ts, dtype):
     tgt.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("lo,hi", [(0.5, 4.0), (-3.0, 1e-3)])
+def test_host_fill_uniform_range_matches_generator(ts, dtype, lo, hi):
+    tgt = ts.Target.host(_cpus(ts, 4))
+    A = ts.Array.alloc(tgt, dtype, 70001)
+    A.fill_uniform(8, 1, 5, lo=lo, hi=hi)
+    ref = tsgen.uniform_array(8, 1, 70001, dtype, start=5, lo=lo, hi=hi)
+    assert np.array_equal(A.to_host().view(np.uint8), ref.view(np.uint8))
+    for bad in ((1.0, 1.0), (2.0, 1.0), (float("nan"), 1.0), (-float("inf"), 0.0), (-1e308, 1e308)):
+        with pytest.raises(ts.TSError) as e:
+            A.fill_uniform(8, 1, lo=bad[0], hi=bad[1])
+        assert e.value.status == E_INVALID
+    tgt.close()
+
+
 def test_host_target_limits(ts):
     tgt = ts.Target.host(_cpus(ts, 2))
     with pytest.raises(ts.TSError) as e:

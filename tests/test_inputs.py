@@ -1,5 +1,6 @@
 """Pins of the seeded input generator (tsgen)."""
 import numpy as np
+import pytest
 
 import tsgen
 
@@ -46,3 +47,20 @@ def test_batched_lengths_and_scalars():
     assert 4.1e9 < total < 4.8e9
     q = tsgen.batched_scalars(5, 4096)
     assert q.min() >= 0.5 and q.max() < 4.0
+
+
+def test_range_generator_reduces_to_the_default_exactly():
+    """On [-1, 1) the range form lo + 2*u01 is exact at every step, so it must
+    equal the default generator bit for bit."""
+    idx = np.arange(0, 1 << 20, dtype=np.uint64)
+    a = tsgen.uniform_pm1(11, 3, idx)
+    b = tsgen.uniform_range(11, 3, idx, -1.0, 1.0)
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
+@pytest.mark.parametrize("lo,hi", [(0.5, 4.0), (-3.0, 1e-3), (1e300, 1.5e300), (-2.0 ** -1070, 2.0 ** -1070)])
+def test_range_generator_bounds(lo, hi):
+    v = tsgen.uniform_range(4, 1, np.arange(200000, dtype=np.uint64), lo, hi)
+    assert v.min() >= lo and v.max() <= hi
+    # the draws spread over the whole range
+    assert v.min() <= lo + 0.01 * (hi - lo) and v.max() >= hi - 0.01 * (hi - lo)

@@ -89,9 +89,21 @@ def narrow(x64: np.ndarray, dtype: str) -> np.ndarray:
     raise ValueError(dtype)
 
 
-def uniform_array(seed: int, stream: int, n: int, dtype: str = "f64", start: int = 0) -> np.ndarray:
-    """Elements start..start+n-1 of a seeded uniform[-1,1) array."""
-    return narrow(uniform_pm1(seed, stream, np.arange(start, start + n, dtype=np.uint64)), dtype)
+def uniform_range(seed: int, stream: int, idx, lo: float, hi: float) -> np.ndarray:
+    """lo + (hi - lo) * u01, the difference, the product and the sum each
+    rounded once in binary64 (numpy does not contract)."""
+    w = np.float64(hi) - np.float64(lo)
+    return np.float64(lo) + w * uniform01(seed, stream, idx)
+
+
+def uniform_array(seed: int, stream: int, n: int, dtype: str = "f64", start: int = 0,
+                  lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """Elements start..start+n-1 of a seeded uniform array over [lo, hi)
+    (the default [-1, 1) draws exact multiples of 2^-52)."""
+    idx = np.arange(start, start + n, dtype=np.uint64)
+    if (lo, hi) == (-1.0, 1.0):
+        return narrow(uniform_pm1(seed, stream, idx), dtype)
+    return narrow(uniform_range(seed, stream, idx, lo, hi), dtype)
 
 
 def batched_lengths(seed: int, count: int, lo_exp: float = 3.0, span_exp: float = 4.0) -> np.ndarray:
