@@ -18,11 +18,12 @@ STREAM's closed form a = 15^10, b = 3*15^9, c = 4*15^9 exactly.  Only the
 CPU-baseline leg runs the oracle.
 
 Extra legs (skipped with --quick): the batched ragged form (4096 instances,
-log-uniform lengths in [1e3, 1e7), one persistent launch per map, the
-iteration captured as a HIP graph and replayed) against per-instance plain
-launches; reduced-precision storage (binary32, bfloat16, binary16) at
-N = 2^28 per array; and a size/alignment sweep from 2^16 to 2^29 elements
-(L2, Infinity Cache and HBM regimes).  The CPU-baseline leg times the oracle
+log-uniform lengths in [1e3, 1e7), one launch per map over all instances,
+the iteration captured as a HIP graph and replayed) against per-instance
+plain launches; reduced-precision storage (binary32, bfloat16, binary16) at
+N = 2^28 per array; a size/alignment sweep from 2^16 to 2^29 elements (L2,
+Infinity Cache and HBM regimes); and launch overhead at small sizes (eager
+calls against HIP graphs).  --legs picks a subset.  The CPU-baseline leg times the oracle
 on host cores.
 """
 from __future__ import annotations
@@ -417,15 +418,20 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline leg only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--autotune", action="store_true", help="re-tune the four maps before timing")
+    ap.add_argument("--legs", type=lambda v: [x for x in v.split(",") if x], default=None,
+                    help="comma-separated extra legs to run after the headline (default: all): "
+                         "batched, reduced_precision, sweep, launch_overhead")
     ap.add_argument("--order", choices=("listing", "copy_b"), default="listing",
                     help="listing: copy c = a (Listing 4); copy_b: the variant with copy a = b")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(STREAM shards with no exchange; see the design notes).", file=sys.stderr)
+              "(STREAM shards with no exchange: each GPU would run the same kernels on its own block).", file=sys.stderr)
         sys.exit(2)
     if a.steps < 1 or a.warmup < 0:
         sys.exit("--steps must be >= 1 and --warmup >= 0")
+    if a.legs and set(a.legs) - {"batched", "reduced_precision", "sweep", "launch_overhead"}:
+        sys.exit(f"unknown legs: {sorted(set(a.legs) - {'batched', 'reduced_precision', 'sweep', 'launch_overhead'})}")
 
     import torch
 
@@ -489,6 +495,8 @@ def main():
                          ("reduced_precision", lambda: reduced_leg(ts, torch, tgt)),
                          ("sweep", lambda: sweep_leg(ts, tgt)),
                          ("launch_overhead", lambda: overhead_leg(ts, torch, tgt))):
+            if a.legs and name not in a.legs:
+                continue
             log(f"{name} leg")
             try:
                 result[name] = fn()
