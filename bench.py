@@ -22,8 +22,9 @@ log-uniform lengths in [1e3, 1e7), one launch per map over all instances,
 the iteration captured as a HIP graph and replayed) against per-instance
 plain launches; reduced-precision storage (binary32, bfloat16, binary16) at
 N = 2^28 per array; a size/alignment sweep from 2^16 to 2^29 elements (L2,
-Infinity Cache and HBM regimes); and launch overhead at small sizes (eager
-calls against HIP graphs).  --legs picks a subset.  The CPU-baseline leg times the oracle
+Infinity Cache and HBM regimes); launch overhead at small sizes (eager
+calls against HIP graphs); and library comparators on the same traffic (the
+runtime's device copy, torch's elementwise b + q*c).  --legs picks a subset.  The CPU-baseline leg times the oracle
 on host cores.
 """
 from __future__ import annotations
@@ -43,6 +44,7 @@ if ROOT not in sys.path:
 METRIC = "STREAM Triad/Copy GB/s and % of HBM peak, FP64 N=2^27; batched vs plain"
 PEAK_GBPS = 8000.0
 OPS = ("copy", "scale", "add", "triad")
+EXTRA_LEGS = ("batched", "reduced_precision", "sweep", "launch_overhead", "comparators")
 PROFILE_PMC = os.path.join(ROOT, "profiles", "triad_f64_n2p27_pmc.md")
 
 
@@ -354,6 +356,33 @@ def overhead_leg(ts, torch, tgt, lo=12, hi=22, iters=192, per_graph=16):
     return out
 
 
+def comparator_leg(torch, n, reps=20):
+    """The same traffic through library kernels, for context: the runtime's
+    device-to-device copy (hipMemcpyAsync behind torch's copy_) and torch's
+    elementwise b + q*c, on N binary64 elements per array, timed with events
+    on torch's current stream (where these kernels run)."""
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    cases = {"runtime_memcpy_d2d": (lambda: z.copy_(x), 16 * n),
+             "torch_add_alpha_triad": (lambda: torch.add(x, y, alpha=3.0, out=z), 24 * n)}
+    out = {}
+    for name, (fn, nbytes) in cases.items():
+        fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record()
+        for i in range(reps):
+            fn()
+            ev[i + 1].record()
+        ev[-1].synchronize()
+        ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+        out[name] = {"best_GBps": round(nbytes / min(ms) / 1e6, 1),
+                     "avg_GBps": round(nbytes / (sum(ms) / len(ms)) / 1e6, 1)}
+    del x, y, z
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline_leg(n, target_seconds=12.0):
     """The oracle's timed mode on the host (pinned threads, first touch)."""
     import oracle
@@ -420,7 +449,7 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="re-tune the four maps before timing")
     ap.add_argument("--legs", type=lambda v: [x for x in v.split(",") if x], default=None,
                     help="comma-separated extra legs to run after the headline (default: all): "
-                         "batched, reduced_precision, sweep, launch_overhead")
+                         + ", ".join(EXTRA_LEGS))
     ap.add_argument("--order", choices=("listing", "copy_b"), default="listing",
                     help="listing: copy c = a (Listing 4); copy_b: the variant with copy a = b")
     a = ap.parse_args()
@@ -430,8 +459,8 @@ def main():
         sys.exit(2)
     if a.steps < 1 or a.warmup < 0:
         sys.exit("--steps must be >= 1 and --warmup >= 0")
-    if a.legs and set(a.legs) - {"batched", "reduced_precision", "sweep", "launch_overhead"}:
-        sys.exit(f"unknown legs: {sorted(set(a.legs) - {'batched', 'reduced_precision', 'sweep', 'launch_overhead'})}")
+    if a.legs and set(a.legs) - set(EXTRA_LEGS):
+        sys.exit(f"unknown legs: {sorted(set(a.legs) - set(EXTRA_LEGS))}; choose from {', '.join(EXTRA_LEGS)}")
 
     import torch
 
@@ -494,7 +523,8 @@ def main():
         for name, fn in (("batched", lambda: batched_leg(ts, torch, tgt)),
                          ("reduced_precision", lambda: reduced_leg(ts, torch, tgt)),
                          ("sweep", lambda: sweep_leg(ts, tgt)),
-                         ("launch_overhead", lambda: overhead_leg(ts, torch, tgt))):
+                         ("launch_overhead", lambda: overhead_leg(ts, torch, tgt)),
+                         ("comparators", lambda: comparator_leg(torch, a.n))):
             if a.legs and name not in a.legs:
                 continue
             log(f"{name} leg")
