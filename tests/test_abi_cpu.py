@@ -336,3 +336,23 @@ def test_plan_batch_rejects_bad_input(shim):
     assert plan_batch(shim, [[1 << 20, 1 << 21, (1 << 22) + 4, 5]], 8, 64)[0] == TS_E_INVALID  # misaligned
     assert plan_batch(shim, [[1 << 20, 1 << 21, 1 << 22, 5]], 8, 60)[0] == TS_E_INVALID        # tile % 8
     assert plan_batch(shim, [[0, 0, 0, 0]], 8, 64)[0] == 0                      # empty instance is fine
+
+
+@pytest.mark.parametrize("cmd", [
+    ["gcc", "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror", "-x", "c"],
+    ["g++", "-std=c++11", "-pedantic", "-Wall", "-Wextra", "-Werror", "-x", "c++"],
+])
+def test_header_is_plain_c_and_cxx(cmd, tmp_path):
+    """include/tstream.h compiles on its own as strict C99 and C++11."""
+    src = tmp_path / "inc.c"
+    src.write_text('#include "tstream.h"\nint main(void) { return ts_version(0, 0) == 0 ? 0 : 1; }\n')
+    subprocess.run(cmd + ["-fsyntax-only", "-I" + os.path.join(ROOT, "include"), str(src)], check=True)
+
+
+def test_c_client_compiles_against_the_header_and_library(tmp_path):
+    out = tmp_path / "stream_client"
+    subprocess.run(["gcc", "-std=c99", "-O2", "-Wall", "-Wextra", "-Werror", "-ffp-contract=off",
+                    "-I" + os.path.join(ROOT, "include"), "-o", str(out),
+                    os.path.join(ROOT, "tests", "cpp", "stream_client.c"),
+                    "-L" + os.path.join(ROOT, "paper_2206_06302_amd"), "-ltstream"], check=True)
+    assert out.exists()
