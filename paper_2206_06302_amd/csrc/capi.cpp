@@ -330,44 +330,60 @@ void bump_epoch(ts_batch_s* b) {
   if (b->plan_epoch) ++*b->plan_epoch;
 }
 
-// Upload a batch's tile table (blocking).
-int batch_upload(ts_batch_s* b) {
-  ts_target_s* t = b->target;
-  if (b->d_tiles) {
-    bump_epoch(b);
-    (void)hipFree(b->d_tiles);
-    b->d_tiles = nullptr;
+// Copy a tile table to a new device allocation (blocking).  On failure
+// nothing is left allocated.
+int upload_tiles(ts_target_s* t, const std::vector<BatchTile>& tiles, BatchTile** out) {
+  *out = nullptr;
+  if (tiles.empty()) return TS_OK;
+  BatchTile* d = nullptr;
+  TS_HIP(hipMalloc(&d, tiles.size() * sizeof(BatchTile)));
+  hipError_t e =
+      hipMemcpyAsync(d, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice, t->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(t->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(e, "tile table upload");
   }
-  if (!b->d_expected && !b->descs.empty()) {
-    TS_HIP(hipMalloc(&b->d_expected, b->descs.size() * sizeof(double)));
-    TS_HIP(hipMalloc(&b->d_counts, b->descs.size() * sizeof(unsigned long long)));
-  }
-  if (!b->tiles.empty()) {
-    TS_HIP(hipMalloc(&b->d_tiles, b->tiles.size() * sizeof(BatchTile)));
-    TS_HIP(hipMemcpyAsync(b->d_tiles, b->tiles.data(), b->tiles.size() * sizeof(BatchTile),
-                          hipMemcpyHostToDevice, t->stream));
-  }
-  TS_HIP(hipStreamSynchronize(t->stream));
+  *out = d;
   return TS_OK;
 }
 
+// Plan the batch's primary tiles with tile_elems and upload them (blocking).
+// The old plan stays in place, whole, until the new one is on the device;
+// on failure the batch is unchanged.
 int batch_replan(ts_batch_s* b, int64_t tile_elems) {
   std::string err;
   std::vector<BatchDesc> descs;
   std::vector<BatchTile> tiles;
   uint64_t total = 0;
-  const int st = plan_batch(b->host.data(), b->host.size(), dtype_size(b->dtype), tile_elems, descs,
-                            tiles, total, err);
+  int st = plan_batch(b->host.data(), b->host.size(), dtype_size(b->dtype), tile_elems, descs, tiles, total,
+                      err);
   if (st != ST_OK) return fail(st, "%s", err.c_str());
+  if (!b->d_expected && !descs.empty()) {
+    TS_HIP(hipMalloc(&b->d_expected, descs.size() * sizeof(double)));
+    TS_HIP(hipMalloc(&b->d_counts, descs.size() * sizeof(unsigned long long)));
+  }
+  BatchTile* d_new = nullptr;
+  if ((st = upload_tiles(b->target, tiles, &d_new)) != TS_OK) return st;
+  if (b->d_tiles) {
+    bump_epoch(b);
+    // Maps of this batch may run on any stream of the device (every target
+    // of it may execute the batch): none may still read the old table.
+    (void)hipDeviceSynchronize();
+    (void)hipFree(b->d_tiles);
+  }
+  b->d_tiles = d_new;
   b->descs.swap(descs);
   b->tiles.swap(tiles);
   b->total = total;
   b->tile_elems = tile_elems;
-  return batch_upload(b);
+  return TS_OK;
 }
 
 void free_op_plans(ts_batch_s* b) {
-  if (!b->op_plans.empty()) bump_epoch(b);
+  if (b->op_plans.empty()) return;
+  bump_epoch(b);
+  (void)hipDeviceSynchronize();  // as in batch_replan: no launch may still read these tables
   for (const ts_batch_s::OpPlan& p : b->op_plans)
     if (p.d_tiles) (void)hipFree(p.d_tiles);
   b->op_plans.clear();
@@ -396,11 +412,9 @@ int build_op_plans(ts_batch_s* b) {
                               total, err);
     if (st != ST_OK) return fail(st, "%s", err.c_str());
     ts_batch_s::OpPlan p{tile, tiles.size(), nullptr};
-    TS_HIP(hipMalloc(&p.d_tiles, tiles.size() * sizeof(BatchTile)));
+    const int ust = upload_tiles(b->target, tiles, &p.d_tiles);
+    if (ust != TS_OK) return ust;
     b->op_plans.push_back(p);
-    TS_HIP(hipMemcpyAsync(p.d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
-                          b->target->stream));
-    TS_HIP(hipStreamSynchronize(b->target->stream));
   }
   return TS_OK;
 }
@@ -1307,7 +1321,7 @@ int ts_batch_destroy(ts_batch b) {
   if (!b) return TS_OK;
   if (!ok_batch(b)) return fail(TS_E_INVALID, "invalid batch handle");
   (void)use_device(b->device);
-  if (ok_target(b->target)) (void)hipStreamSynchronize(b->target->stream);
+  (void)hipDeviceSynchronize();  // the batch's maps may run on any stream of its device
   free_op_plans(b);
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   if (b->d_expected) (void)hipFree(b->d_expected);
