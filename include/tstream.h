@@ -23,7 +23,9 @@
  *   - Handles are opaque; objects made by *_create / *_alloc are owned by the
  *     caller and released by the matching *_destroy / *_free, which never
  *     fail on a valid handle (the allocator's bulk_destroy is noexcept,
- *     Listing 1) and accept NULL as a no-op.
+ *     Listing 1) and accept NULL as a no-op.  Arrays, batches, transforms
+ *     and graphs refer to the target they were made on: destroy them before
+ *     that target.
  *   - "Device pointer" means memory of the target's device (from hipMalloc,
  *     or a torch CUDA/HIP tensor); "host pointer" means ordinary CPU memory.
  *   - Algorithm, fill and copy calls are asynchronous and ordered on the

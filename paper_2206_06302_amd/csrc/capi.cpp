@@ -736,7 +736,8 @@ int ts_array_alloc(ts_target t, ts_dtype dtype, size_t n, size_t offset_elems, t
   if (!ok_target(t) || !out) return fail(TS_E_INVALID, "invalid target handle or NULL out");
   if (!valid_dtype(dtype)) return fail(TS_E_INVALID, "unknown dtype %d", static_cast<int>(dtype));
   const size_t es = dtype_size(dtype);
-  if (n > (SIZE_MAX / es) - offset_elems - 1) return fail(TS_E_INVALID, "size overflow");
+  const size_t max_elems = SIZE_MAX / es - 1;
+  if (offset_elems > max_elems || n > max_elems - offset_elems) return fail(TS_E_INVALID, "size overflow");
   void* base = nullptr;
   const size_t bytes = (n + offset_elems) * es;
   if (t->host) {
@@ -965,7 +966,16 @@ int ts_stream_iteration(ts_target exec, ts_array a, ts_array b, ts_array c, doub
   if (ranges_overlap(pa, pb, a->n, es) || ranges_overlap(pa, pc, a->n, es) ||
       ranges_overlap(pb, pc, a->n, es))
     return fail(TS_E_ALIAS, "the benchmark arrays a, b, c must not overlap");
+  // All four maps are checked before any is enqueued, so an error leaves the
+  // arrays untouched.
+  uint64_t count = 0;
   int st;
+  if ((st = check_exec_arrays(exec, TS_COPY, a, nullptr, c, &count)) != TS_OK ||
+      (st = check_exec_arrays(exec, TS_SCALE, c, nullptr, b, &count)) != TS_OK ||
+      (st = check_exec_arrays(exec, TS_ADD, a, b, c, &count)) != TS_OK ||
+      (st = check_exec_arrays(exec, TS_TRIAD, b, c, a, &count)) != TS_OK)
+    return st;
+  if (!map_dtype(a->dtype)) return fail(TS_E_UNSUPPORTED, "the STREAM maps take floating-point storage");
   if ((st = run_map(exec, TS_COPY, a, nullptr, c, q)) != TS_OK) return st;   // c = a
   if ((st = run_map(exec, TS_SCALE, c, nullptr, b, q)) != TS_OK) return st;  // b = q*c
   if ((st = run_map(exec, TS_ADD, a, b, c, q)) != TS_OK) return st;          // c = a + b

@@ -60,6 +60,10 @@ def test_algorithm_rules(env):
     assert status(ts, lambda: ts.copy(tgt, a, f32)) == E_DTYPE
     assert status(ts, lambda: ts.triad(tgt, a, b, overlap, 3.0)) == E_ALIAS
     assert status(ts, lambda: ts.stream_iteration(tgt, a, overlap, c)) == E_ALIAS
+    # an iteration whose third map would fail enqueues nothing: c keeps its values
+    a.fill(5.0), c.fill(7.0)
+    assert status(ts, lambda: ts.stream_iteration(tgt, a, short, c)) == E_SHAPE
+    assert ts.checksum(tgt, c, 7.0)["mismatches"] == 0
     ts.copy(tgt, short, a)          # count = n of the first input: fewer elements is fine
     ts.triad(tgt, a, b, a, 3.0)     # exact in place
     ts.copy(tgt, ts.Array.wrap(tgt, t[0:0]), c)  # empty range: no launch
