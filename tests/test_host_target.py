@@ -115,6 +115,11 @@ def test_host_target_limits(ts):
     with pytest.raises(ts.TSError) as e:
         ts.copy(tgt, a, b)
     assert e.value.status == E_SHAPE
+    c = ts.Array.alloc(tgt, "f64", 100)
+    a.fill(5.0), c.fill(7.0)
+    with pytest.raises(ts.TSError) as e:  # scale would not fit b: nothing runs
+        ts.stream_iteration(tgt, a, b, c)
+    assert e.value.status == E_SHAPE and np.all(c.to_host() == 7.0)
     with pytest.raises(ts.TSError) as e:
         ts.Graph.capture_arrays_iteration(tgt, a, a, a)
     assert e.value.status == E_UNSUPPORTED
