@@ -383,7 +383,7 @@ def comparator_leg(torch, n, reps=20):
     return out
 
 
-def cpu_baseline_leg(n, target_seconds=12.0):
+def cpu_baseline_leg(n, target_seconds=10.0):
     """The oracle's timed mode on the host (pinned threads, first touch)."""
     import oracle
     try:
@@ -394,7 +394,7 @@ def cpu_baseline_leg(n, target_seconds=12.0):
     t0 = time.perf_counter()
     secs, _ = oracle.stream_timed_f64(n, 1, threads)
     one = float(secs.sum())
-    iters = int(max(2, min(40, target_seconds / max(one, 1e-3))))
+    iters = int(max(2, min(300, target_seconds / max(one, 1e-3))))
     secs, fin = oracle.stream_timed_f64(n, iters, threads)
     spent = time.perf_counter() - t0
     exp = oracle.stream_scalar_f64(1.0, 2.0, 0.0, 3.0, iters)
