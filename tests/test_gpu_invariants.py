@@ -81,6 +81,7 @@ def test_every_batched_candidate_matches_plain(env):
     for cfg in cands:
         for op in OPS:
             ts.set_kernel_cfg(op, "f64", cfg, batched=True)
+        bw.set_tile(cfg["tile_elems"])  # the candidate's own tiles
         for k in range(3):
             work[k].copy_(init[k])
         torch.cuda.synchronize()
