@@ -29,7 +29,8 @@ LIB = os.path.join(PKG, "libtstream.so")
 ARCH = os.environ.get("TS_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["kern_f64.hip", "kern_f32.hip", "kern_bf16.hip", "kern_f16.hip", "kern_aux.hip",
-           "capi.cpp", "tune.cpp", "host_target.cpp", "transform.cpp"]
+           "capi.cpp", "capi_tune.cpp", "capi_batch.cpp", "capi_async.cpp", "tune.cpp", "host_target.cpp",
+           "transform.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
@@ -48,7 +49,7 @@ def hipcc() -> str:
 
 def _inputs():
     return [os.path.join(CSRC, s) for s in SOURCES] + glob.glob(os.path.join(CSRC, "*.hpp")) + \
-        [os.path.join(INCLUDE, "tstream.h")]
+        [os.path.join(INCLUDE, "tstream.h"), os.path.join(CSRC, "libtstream.map")]
 
 
 def stale() -> bool:
@@ -82,7 +83,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
                 f.result()
         tmp_lib = LIB + ".tmp%d" % os.getpid()
         cmd = [cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp_lib, *objs,
-               "-Wl,-rpath,/opt/rocm/lib", "-Wl,--no-undefined", "-ldl"]
+               "-Wl,-rpath,/opt/rocm/lib", "-Wl,--no-undefined",
+               "-Wl,--version-script=" + os.path.join(CSRC, "libtstream.map"), "-ldl"]
         r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}")

@@ -1,40 +1,26 @@
-// capi.cpp -- the C ABI of libtstream (declared in include/tstream.h).
+// capi.cpp -- the C ABI of libtstream (declared in include/tstream.h):
+// errors, targets, arrays, algorithms and validation.
 //
 // Targets pair a device with a stream (Sections 3.1 and 4.2); arrays are
 // placed on a target's device and bulk-constructed there (Section 3.2);
 // each algorithm call is one bulk launch on the executing target's stream
 // (Sections 3.3 and 3.4).  Every entry point catches everything, returns a
 // status and leaves a thread-local message on failure.
-#include <hip/hip_runtime_api.h>
-
 #include <unistd.h>
 
 #include <algorithm>
-#include <chrono>
 #include <cmath>
-#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <memory>
-#include <mutex>
 #include <new>
-#include <string>
-#include <vector>
 
-#include "../../include/tstream.h"
-#include "host_target.hpp"
-#include "ts_handles.hpp"
-#include "ts_internal.hpp"
-#include "tune.hpp"
-
-namespace {
-
-// Largest grid.x of a launch; kernels stride over whatever lies beyond it.
-constexpr uint64_t kMaxGridX = 0x7fffffffull;
+#include "capi_internal.hpp"
 
 using namespace ts;
+
+namespace tsapi {
 
 thread_local std::string g_error;
 
@@ -54,133 +40,8 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(st, "%s failed: %s (%d)", what, hipGetErrorString(e), static_cast<int>(e));
 }
 
-#define TS_HIP(call)                                  \
-  do {                                                \
-    hipError_t e_ = (call);                           \
-    if (e_ != hipSuccess) return hip_fail(e_, #call); \
-  } while (0)
-
-#define TS_GUARD_BEGIN try {
-#define TS_GUARD_END                                               \
-  }                                                                \
-  catch (const std::bad_alloc&) {                                  \
-    return fail(TS_E_OOM, "host allocation failed");               \
-  }                                                                \
-  catch (const std::exception& ex) {                               \
-    return fail(TS_E_INVALID, "internal error: %s", ex.what());    \
-  }                                                                \
-  catch (...) {                                                    \
-    return fail(TS_E_INVALID, "internal error");                   \
-  }
-
-constexpr uint32_t kBatchMagic = 0x42415431u;
-constexpr uint32_t kGraphMagic = 0x47524631u;
-constexpr uint32_t kEventMagic = 0x45564e31u;
-constexpr uint32_t kFutureMagic = 0x46555431u;
-constexpr uint32_t kDead = 0xdeadbeefu;
-constexpr uint64_t kDeadEpoch = ~0ull;
-constexpr double kPeakBytesPerS = 8.0e12;  // MI355X HBM3E, the % of peak denominator
-
-}  // namespace
-
-namespace ts {
-int api_fail(int status, const char* fmt, ...) {
-  char buf[1024];
-  va_list ap;
-  va_start(ap, fmt);
-  std::vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  g_error = buf;
-  return status;
-}
-int api_hip_fail(hipError_t e, const char* what) { return hip_fail(e, what); }
-}  // namespace ts
-
-struct ts_batch_s {
-  uint32_t magic;
-  ts_target_s* target;
-  int device;
-  int dtype;
-  std::vector<HostDesc> host;
-  std::vector<BatchDesc> descs;  // host-side metadata (alignment per instance)
-  std::vector<BatchTile> tiles;  // primary plan: fills, mismatch counts, info
-  BatchTile* d_tiles;
-  double* d_expected;
-  unsigned long long* d_counts;
-  uint64_t total;
-  int64_t tile_elems;
-  // Device plans for the other tile sizes that the maps' tuned configurations
-  // ask for, so that each map runs on its own tiles.
-  struct OpPlan {
-    int64_t tile_elems;
-    uint64_t ntiles;
-    BatchTile* d_tiles;
-  };
-  std::vector<OpPlan> op_plans;
-  bool tile_pinned;  // set by ts_batch_set_tile: every map uses the primary plan
-  // Bumped whenever a tile table is freed (re-plan) and set to kDeadEpoch on
-  // destruction; graphs captured from the batch share it and refuse to launch
-  // once it has moved, instead of reading freed tile tables.
-  std::shared_ptr<uint64_t> plan_epoch;
-};
-
-struct ts_graph_s {
-  uint32_t magic;
-  int device;
-  hipGraph_t graph;
-  hipGraphExec_t exec;
-  std::shared_ptr<uint64_t> batch_epoch;  // null for graphs of plain arrays
-  uint64_t epoch_at_capture;
-};
-
-struct ts_event_s {
-  uint32_t magic;
-  int device;
-  hipEvent_t ev;
-  bool recorded;
-};
-
-struct ts_future_s {
-  uint32_t magic;
-  std::mutex mu;
-  std::condition_variable cv;
-  bool ready;
-};
-
-namespace {
-
-bool ok_target(const ts_target_s* t) { return t && t->magic == kTargetMagic; }
-bool ok_array(const ts_array_s* a) { return a && a->magic == kArrayMagic; }
-bool ok_batch(const ts_batch_s* b) { return b && b->magic == kBatchMagic; }
-bool ok_graph(const ts_graph_s* g) { return g && g->magic == kGraphMagic; }
-bool ok_event(const ts_event_s* e) { return e && e->magic == kEventMagic; }
-bool ok_future(const ts_future_s* f) { return f && f->magic == kFutureMagic; }
-
-constexpr int kHostDevice = -1;
-
 int host_only_gpu(const char* what) {
   return fail(TS_E_UNSUPPORTED, "%s needs a GPU target (this is a host-CPU target)", what);
-}
-
-// Run fn(lo, hi, w) on every worker of a host target over its block of n.
-template <class F>
-void host_blocks(ts_target_s* t, uint64_t n, F&& fn) {
-  const int W = t->pool->size();
-  t->pool->run([&](int w) {
-    uint64_t lo, hi;
-    HostPool::block(n, W, w, &lo, &hi);
-    fn(lo, hi, w);
-  });
-}
-
-// Stream callback that makes a future ready (runs on a runtime thread).
-void future_ready_cb(void* p) {
-  ts_future_s* f = static_cast<ts_future_s*>(p);
-  {
-    std::lock_guard<std::mutex> lk(f->mu);
-    f->ready = true;
-  }
-  f->cv.notify_all();
 }
 
 // Make `device` current for the calling thread (cheap when it already is).
@@ -326,202 +187,22 @@ int run_map(ts_target_s* t, int op, ts_array_s* x, ts_array_s* y, ts_array_s* d,
   return launch_map(t, op, x->dtype, x->ptr, has_y ? y->ptr : nullptr, d->ptr, count, q, cfg);
 }
 
-void bump_epoch(ts_batch_s* b) {
-  if (b->plan_epoch) ++*b->plan_epoch;
-}
+}  // namespace tsapi
 
-// Copy a tile table to a new device allocation (blocking).  On failure
-// nothing is left allocated.
-int upload_tiles(ts_target_s* t, const std::vector<BatchTile>& tiles, BatchTile** out) {
-  *out = nullptr;
-  if (tiles.empty()) return TS_OK;
-  BatchTile* d = nullptr;
-  TS_HIP(hipMalloc(&d, tiles.size() * sizeof(BatchTile)));
-  hipError_t e =
-      hipMemcpyAsync(d, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice, t->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(t->stream);
-  if (e != hipSuccess) {
-    (void)hipFree(d);
-    return hip_fail(e, "tile table upload");
-  }
-  *out = d;
-  return TS_OK;
-}
+using namespace tsapi;
 
-// Plan the batch's primary tiles with tile_elems and upload them (blocking).
-// The old plan stays in place, whole, until the new one is on the device;
-// on failure the batch is unchanged.
-int batch_replan(ts_batch_s* b, int64_t tile_elems) {
-  std::string err;
-  std::vector<BatchDesc> descs;
-  std::vector<BatchTile> tiles;
-  uint64_t total = 0;
-  int st = plan_batch(b->host.data(), b->host.size(), dtype_size(b->dtype), tile_elems, descs, tiles, total,
-                      err);
-  if (st != ST_OK) return fail(st, "%s", err.c_str());
-  if (!b->d_expected && !descs.empty()) {
-    TS_HIP(hipMalloc(&b->d_expected, descs.size() * sizeof(double)));
-    TS_HIP(hipMalloc(&b->d_counts, descs.size() * sizeof(unsigned long long)));
-  }
-  BatchTile* d_new = nullptr;
-  if ((st = upload_tiles(b->target, tiles, &d_new)) != TS_OK) return st;
-  if (b->d_tiles) {
-    bump_epoch(b);
-    // Maps of this batch may run on any stream of the device (every target
-    // of it may execute the batch): none may still read the old table.
-    (void)hipDeviceSynchronize();
-    (void)hipFree(b->d_tiles);
-  }
-  b->d_tiles = d_new;
-  b->descs.swap(descs);
-  b->tiles.swap(tiles);
-  b->total = total;
-  b->tile_elems = tile_elems;
-  return TS_OK;
+namespace ts {
+int api_fail(int status, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return status;
 }
-
-void free_op_plans(ts_batch_s* b) {
-  if (b->op_plans.empty()) return;
-  bump_epoch(b);
-  (void)hipDeviceSynchronize();  // as in batch_replan: no launch may still read these tables
-  for (const ts_batch_s::OpPlan& p : b->op_plans)
-    if (p.d_tiles) (void)hipFree(p.d_tiles);
-  b->op_plans.clear();
-}
-
-ts_kernel_cfg batch_cfg(const ts_batch_s* b, int op) {
-  return tune_table().lookup(op, b->dtype, b->total, TS_ALIGN_16, 1);
-}
-
-// Plans for the tile sizes of the four maps' configurations that differ from
-// the primary plan's (blocking).  Nothing is planned when the tile is pinned.
-int build_op_plans(ts_batch_s* b) {
-  free_op_plans(b);
-  if (b->tile_pinned || b->tiles.empty()) return TS_OK;
-  for (int op = TS_COPY; op <= TS_TRIAD; ++op) {
-    const int64_t tile = batch_cfg(b, op).tile_elems;
-    if (tile <= 0 || tile == b->tile_elems) continue;
-    bool have = false;
-    for (const ts_batch_s::OpPlan& p : b->op_plans) have = have || p.tile_elems == tile;
-    if (have) continue;
-    std::string err;
-    std::vector<BatchDesc> descs;
-    std::vector<BatchTile> tiles;
-    uint64_t total = 0;
-    const int st = plan_batch(b->host.data(), b->host.size(), dtype_size(b->dtype), tile, descs, tiles,
-                              total, err);
-    if (st != ST_OK) return fail(st, "%s", err.c_str());
-    ts_batch_s::OpPlan p{tile, tiles.size(), nullptr};
-    const int ust = upload_tiles(b->target, tiles, &p.d_tiles);
-    if (ust != TS_OK) return ust;
-    b->op_plans.push_back(p);
-  }
-  return TS_OK;
-}
-
-int launch_batch(ts_target_s* t, ts_batch_s* b, int op, const ts_kernel_cfg& cfg) {
-  if (b->tiles.empty()) return TS_OK;
-  BatchLaunch L{};
-  L.tiles = b->d_tiles;
-  L.ntiles = b->tiles.size();
-  if (!b->tile_pinned && cfg.tile_elems > 0 && cfg.tile_elems != b->tile_elems) {
-    for (const ts_batch_s::OpPlan& p : b->op_plans)
-      if (p.tile_elems == cfg.tile_elems) {
-        L.tiles = p.d_tiles;
-        L.ntiles = p.ntiles;
-      }
-  }
-  // grid_per_cu 0: one workgroup per tile; otherwise a persistent grid that
-  // strides over the tiles.
-  uint64_t grid = cfg.grid_per_cu > 0
-                      ? static_cast<uint64_t>(cfg.grid_per_cu) * static_cast<uint64_t>(t->info.compute_units)
-                      : L.ntiles;
-  if (grid > L.ntiles) grid = L.ntiles;
-  if (grid > kMaxGridX) grid = kMaxGridX;
-  if (grid < 1) grid = 1;
-  L.grid = static_cast<uint32_t>(grid);
-  L.block = static_cast<uint32_t>(cfg.block);
-  L.op = op;
-  L.unroll = cfg.unroll;
-  L.ntl = cfg.nt_load;
-  L.nts = cfg.nt_store;
-  L.stream = t->stream;
-  const hipError_t e = batch_launch(b->dtype, L);
-  if (e != hipSuccess) return hip_fail(e, "batched STREAM kernel launch");
-  return TS_OK;
-}
-
-int check_batch_exec(ts_target_s* t, ts_batch_s* b) {
-  if (!ok_target(t)) return fail(TS_E_INVALID, "invalid target handle");
-  if (t->host) return host_only_gpu("batched execution");
-  if (!ok_batch(b)) return fail(TS_E_INVALID, "invalid batch handle");
-  if (b->device != t->device)
-    return fail(TS_E_PLACEMENT, "batch is placed on device %d, the executor runs on device %d",
-                b->device, t->device);
-  return use_device(t->device);
-}
-
-uint32_t aux_grid(const ts_target_s* t, uint64_t ntiles) {
-  uint64_t g = 4ull * static_cast<uint64_t>(t->info.compute_units);
-  if (g > ntiles) g = ntiles;
-  return static_cast<uint32_t>(g < 1 ? 1 : g);
-}
-
-// Seconds per launch of one candidate: `inner` back-to-back launches between
-// two events (so small, launch-bound sizes are timed as throughput), repeated
-// `reps` times after a warm-up; the median of the repetitions is returned.
-template <class Launch>
-int time_candidate(ts_target_s* t, int reps, int inner, Launch&& launch, double* seconds) {
-  if (reps < 1) reps = 1;
-  if (inner < 1) inner = 1;
-  std::vector<hipEvent_t> ev(2 * static_cast<size_t>(reps), nullptr);
-  int st = TS_OK;
-  for (auto& e : ev) {
-    const hipError_t he = hipEventCreate(&e);
-    if (he != hipSuccess) {
-      st = hip_fail(he, "hipEventCreate");
-      break;
-    }
-  }
-  if (st == TS_OK) st = launch();  // warm-up
-  for (int r = 0; r < reps && st == TS_OK; ++r) {
-    hipError_t he = hipEventRecord(ev[2 * r], t->stream);
-    if (he != hipSuccess) {
-      st = hip_fail(he, "hipEventRecord");
-      break;
-    }
-    for (int i = 0; i < inner && st == TS_OK; ++i) st = launch();
-    if (st != TS_OK) break;
-    he = hipEventRecord(ev[2 * r + 1], t->stream);
-    if (he != hipSuccess) st = hip_fail(he, "hipEventRecord");
-  }
-  std::vector<float> ms;
-  if (st == TS_OK) {
-    const hipError_t he = hipStreamSynchronize(t->stream);
-    if (he != hipSuccess) st = hip_fail(he, "hipStreamSynchronize");
-  }
-  for (int r = 0; r < reps && st == TS_OK; ++r) {
-    float v = 0;
-    const hipError_t he = hipEventElapsedTime(&v, ev[2 * r], ev[2 * r + 1]);
-    if (he != hipSuccess) st = hip_fail(he, "hipEventElapsedTime");
-    ms.push_back(v);
-  }
-  for (auto& e : ev)
-    if (e) (void)hipEventDestroy(e);
-  if (st != TS_OK) return st;
-  std::sort(ms.begin(), ms.end());
-  *seconds = 1e-3 * ms[ms.size() / 2] / inner;
-  return TS_OK;
-}
-
-// Launches per timed repetition: about a millisecond of work at ~6 TB/s.
-int inner_launches(uint64_t bytes) {
-  const double est = static_cast<double>(bytes) / 6.0e12 + 5e-6;
-  const double r = 1e-3 / est;
-  return r < 1 ? 1 : (r > 200 ? 200 : static_cast<int>(r));
-}
-
-}  // namespace
+int api_hip_fail(hipError_t e, const char* what) { return hip_fail(e, what); }
+}  // namespace ts
 
 extern "C" {
 
@@ -1063,642 +744,6 @@ int ts_mismatch_count(ts_target t, ts_array x, ts_array ref, uint64_t* out) {
   *out = static_cast<const CsPart*>(t->host_result)->mism;
   return TS_OK;
   TS_GUARD_END
-}
-
-// ---------------------------------------------------------------------------
-// Launch configuration and tuning
-// ---------------------------------------------------------------------------
-int ts_get_kernel_cfg(ts_op op, ts_dtype dtype, size_t n, int align_class, int batched,
-                      ts_kernel_cfg* out) {
-  TS_GUARD_BEGIN
-  if (!valid_op(op) || !map_dtype(dtype) || !out || align_class < 0 || align_class > 2)
-    return fail(TS_E_INVALID, "bad op, dtype, alignment class or NULL out");
-  ts_kernel_cfg c = tune_table().lookup(op, dtype, n, align_class, batched ? 1 : 0);
-  if (!batched && c.vec_bytes == 0) c.vec_bytes = static_cast<int32_t>(dtype_size(dtype));
-  *out = c;
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_set_kernel_cfg(ts_op op, ts_dtype dtype, int batched, const ts_kernel_cfg* cfg) {
-  TS_GUARD_BEGIN
-  if (!valid_op(op) || !map_dtype(dtype)) return fail(TS_E_INVALID, "bad op or dtype");
-  if (cfg) {
-    const std::string why = cfg_problem(*cfg, batched ? 1 : 0);
-    if (!why.empty()) return fail(TS_E_INVALID, "invalid configuration: %s", why.c_str());
-  }
-  tune_table().force(op, dtype, batched ? 1 : 0, cfg);
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_autotune_candidates(int batched, ts_kernel_cfg* out, size_t cap, size_t* count) {
-  TS_GUARD_BEGIN
-  if (!count) return fail(TS_E_INVALID, "NULL count");
-  const std::vector<ts_kernel_cfg> c = candidates(batched ? 1 : 0);
-  if (out)
-    for (size_t i = 0; i < c.size() && i < cap; ++i) out[i] = c[i];
-  *count = c.size();
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_autotune(ts_target t, ts_op op, ts_dtype dtype, size_t n, size_t offset_elems, int reps,
-                ts_kernel_cfg* best, double* best_bytes_per_s) {
-  TS_GUARD_BEGIN
-  if (!ok_target(t)) return fail(TS_E_INVALID, "invalid target handle");
-  if (t->host) return host_only_gpu("tuning");
-  if (!valid_op(op) || !map_dtype(dtype) || n == 0)
-    return fail(TS_E_INVALID, "bad op, dtype or zero size");
-  int st = use_device(t->device);
-  if (st != TS_OK) return st;
-  const size_t es = dtype_size(dtype);
-  void* base[3] = {nullptr, nullptr, nullptr};
-  for (int i = 0; i < 3; ++i) {
-    const hipError_t e = hipMalloc(&base[i], (n + offset_elems) * es);
-    if (e != hipSuccess) {
-      for (int j = 0; j < i; ++j) (void)hipFree(base[j]);
-      return hip_fail(e, "hipMalloc (autotune arrays)");
-    }
-  }
-  char* p[3];
-  for (int i = 0; i < 3; ++i) {
-    p[i] = static_cast<char*>(base[i]) + offset_elems * es;
-    if (st == TS_OK) {
-      const hipError_t e =
-          launch_fill_uniform(dtype, p[i], n, 1, static_cast<uint64_t>(i), 0, -1.0, 2.0, t->stream);
-      if (e != hipSuccess) st = hip_fail(e, "fill kernel launch");
-    }
-  }
-  const bool has_y = op == TS_ADD || op == TS_TRIAD;
-  const uintptr_t ya = reinterpret_cast<uintptr_t>(p[1]);
-  const int cls = align_class(reinterpret_cast<uintptr_t>(p[0]), has_y ? &ya : nullptr,
-                              reinterpret_cast<uintptr_t>(p[2]));
-  ts_kernel_cfg best_cfg = default_cfg(0, dtype);
-  double best_s = 0;
-  const uint64_t bytes = stream_bytes(op, n, es);
-  for (const ts_kernel_cfg& c : candidates(0)) {
-    if (st != TS_OK) break;
-    double s = 0;
-    st = time_candidate(t, reps, inner_launches(bytes),
-                        [&]() { return launch_map(t, op, dtype, p[0], p[1], p[2], n, 3.0, c); }, &s);
-    if (st == TS_OK && s > 0 && (best_s == 0 || s < best_s)) {
-      best_s = s;
-      best_cfg = c;
-    }
-  }
-  (void)hipStreamSynchronize(t->stream);
-  for (int i = 0; i < 3; ++i) (void)hipFree(base[i]);
-  if (st != TS_OK) return st;
-  const double bps = best_s > 0 ? static_cast<double>(bytes) / best_s : 0.0;
-  tune_table().put(TuneKey{op, dtype, size_bucket(n), cls, 0}, TuneEntry{best_cfg, bps});
-  if (best) *best = best_cfg;
-  if (best_bytes_per_s) *best_bytes_per_s = bps;
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_autotune_batch(ts_target t, ts_batch b, ts_op op, int reps, ts_kernel_cfg* best,
-                      double* best_bytes_per_s) {
-  TS_GUARD_BEGIN
-  int st = check_batch_exec(t, b);
-  if (st != TS_OK) return st;
-  if (!valid_op(op)) return fail(TS_E_INVALID, "bad op");
-  if (b->total == 0) return fail(TS_E_INVALID, "empty batch");
-  const int64_t original_tile = b->tile_elems;
-  const bool pinned = b->tile_pinned;
-  free_op_plans(b);
-  b->tile_pinned = true;  // candidates run on the primary plan, re-planned to their tile
-  ts_kernel_cfg best_cfg = default_cfg(1, b->dtype);
-  double best_s = 0;
-  for (const ts_kernel_cfg& c : candidates(1)) {
-    if (c.tile_elems != b->tile_elems && (st = batch_replan(b, c.tile_elems)) != TS_OK) break;
-    double s = 0;
-    st = time_candidate(t, reps, 1, [&]() { return launch_batch(t, b, op, c); }, &s);
-    if (st != TS_OK) break;
-    if (s > 0 && (best_s == 0 || s < best_s)) {
-      best_s = s;
-      best_cfg = c;
-    }
-  }
-  const double bps =
-      best_s > 0 ? static_cast<double>(stream_bytes(op, b->total, dtype_size(b->dtype))) / best_s : 0.0;
-  if (st == TS_OK)
-    tune_table().put(TuneKey{op, b->dtype, size_bucket(b->total), TS_ALIGN_16, 1}, TuneEntry{best_cfg, bps});
-  // Back to the batch's own tile; the maps' plans now follow the updated table.
-  b->tile_pinned = pinned;
-  const int rst = batch_replan(b, original_tile);
-  if (st != TS_OK) return st;
-  if (rst != TS_OK) return rst;
-  if ((st = build_op_plans(b)) != TS_OK) return st;
-  if (best) *best = best_cfg;
-  if (best_bytes_per_s) *best_bytes_per_s = bps;
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_tune_cache_load(const char* path) {
-  TS_GUARD_BEGIN
-  if (!path) return fail(TS_E_INVALID, "NULL path");
-  std::string err;
-  if (tune_table().load(path, &err) != 0) return fail(TS_E_INVALID, "%s", err.c_str());
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_tune_cache_save(const char* path) {
-  TS_GUARD_BEGIN
-  if (!path) return fail(TS_E_INVALID, "NULL path");
-  std::string err;
-  if (tune_table().save(path, &err) != 0) return fail(TS_E_INVALID, "%s", err.c_str());
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_tune_cache_clear(void) {
-  TS_GUARD_BEGIN
-  tune_table().clear();
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_time_op(ts_target exec, ts_op op, ts_array x, ts_array y, ts_array dst, double q, int reps,
-               float* ms_total) {
-  TS_GUARD_BEGIN
-  if (!valid_op(op) || !ms_total || reps < 1) return fail(TS_E_INVALID, "bad op, reps or NULL out");
-  uint64_t count = 0;
-  int st = check_exec_arrays(exec, op, x, y, dst, &count);
-  if (st != TS_OK) return st;
-  if (exec->host) {
-    const auto t0 = std::chrono::steady_clock::now();
-    for (int r = 0; r < reps && st == TS_OK; ++r) st = run_map(exec, op, x, y, dst, q);
-    if (st != TS_OK) return st;
-    *ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    return TS_OK;
-  }
-  if ((st = use_device(exec->device)) != TS_OK) return st;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  TS_HIP(hipEventCreate(&e0));
-  hipError_t he = hipEventCreate(&e1);
-  if (he != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return hip_fail(he, "hipEventCreate");
-  }
-  he = hipEventRecord(e0, exec->stream);
-  for (int r = 0; r < reps && he == hipSuccess && st == TS_OK; ++r) st = run_map(exec, op, x, y, dst, q);
-  if (he == hipSuccess && st == TS_OK) he = hipEventRecord(e1, exec->stream);
-  if (he == hipSuccess && st == TS_OK) he = hipEventSynchronize(e1);
-  float ms = 0;
-  if (he == hipSuccess && st == TS_OK) he = hipEventElapsedTime(&ms, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (st != TS_OK) return st;
-  if (he != hipSuccess) return hip_fail(he, "event timing");
-  *ms_total = ms;
-  return TS_OK;
-  TS_GUARD_END
-}
-
-// ---------------------------------------------------------------------------
-// Batched instances
-// ---------------------------------------------------------------------------
-int ts_batch_create(ts_target t, ts_dtype dtype, const ts_batch_desc* descs, size_t count,
-                    ts_batch* out) {
-  TS_GUARD_BEGIN
-  if (!ok_target(t) || !out) return fail(TS_E_INVALID, "invalid target handle or NULL out");
-  if (t->host) return host_only_gpu("batched execution");
-  if (!valid_dtype(dtype)) return fail(TS_E_INVALID, "unknown dtype");
-  if (!map_dtype(dtype)) return fail(TS_E_UNSUPPORTED, "batches take floating-point storage");
-  if (count > 0 && !descs) return fail(TS_E_INVALID, "NULL descriptors");
-  int st = use_device(t->device);
-  if (st != TS_OK) return st;
-  ts_batch_s* b = new ts_batch_s();
-  b->plan_epoch = std::make_shared<uint64_t>(0);
-  b->target = t;
-  b->device = t->device;
-  b->dtype = dtype;
-  b->host.resize(count);
-  const size_t es = dtype_size(dtype);
-  // Placement: every instance's first element must be device memory of this
-  // device (one query per array; instances are not required to be distinct
-  // allocations).
-  for (size_t i = 0; i < count; ++i) {
-    const ts_batch_desc& d = descs[i];
-    b->host[i] = HostDesc{reinterpret_cast<uintptr_t>(d.a), reinterpret_cast<uintptr_t>(d.b),
-                          reinterpret_cast<uintptr_t>(d.c), d.len, d.q};
-  }
-  auto cleanup = [&](int status) {
-    free_op_plans(b);
-    if (b->d_tiles) (void)hipFree(b->d_tiles);
-    if (b->d_expected) (void)hipFree(b->d_expected);
-    if (b->d_counts) (void)hipFree(b->d_counts);
-    delete b;
-    return status;
-  };
-  std::vector<uintptr_t> seen;
-  for (size_t i = 0; i < count; ++i) {
-    if (descs[i].len == 0) continue;
-    for (void* ptr : {descs[i].a, descs[i].b, descs[i].c}) {
-      if (!ptr) return cleanup(fail(TS_E_INVALID, "instance %zu: NULL array with len > 0", i));
-      hipPointerAttribute_t attr;
-      std::memset(&attr, 0, sizeof attr);
-      const hipError_t e = hipPointerGetAttributes(&attr, ptr);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return cleanup(fail(TS_E_PLACEMENT, "instance %zu: pointer is not device memory", i));
-      }
-      if ((attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged) ||
-          attr.device != t->device)
-        return cleanup(fail(TS_E_PLACEMENT, "instance %zu: array is not on the target's device", i));
-    }
-  }
-  (void)es;
-  const ts_kernel_cfg cfg = tune_table().lookup(TS_TRIAD, dtype, 0, TS_ALIGN_16, 1);
-  uint64_t total = 0;
-  for (size_t i = 0; i < count; ++i) total += descs[i].len;
-  const ts_kernel_cfg sized = tune_table().lookup(TS_TRIAD, dtype, total, TS_ALIGN_16, 1);
-  int64_t tile = sized.tile_elems > 0 ? sized.tile_elems : (cfg.tile_elems > 0 ? cfg.tile_elems : 16384);
-  st = batch_replan(b, tile);
-  if (st == TS_OK) st = build_op_plans(b);
-  if (st != TS_OK) return cleanup(st);
-  b->magic = kBatchMagic;
-  *out = b;
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_batch_destroy(ts_batch b) {
-  if (!b) return TS_OK;
-  if (!ok_batch(b)) return fail(TS_E_INVALID, "invalid batch handle");
-  (void)use_device(b->device);
-  (void)hipDeviceSynchronize();  // the batch's maps may run on any stream of its device
-  free_op_plans(b);
-  if (b->d_tiles) (void)hipFree(b->d_tiles);
-  if (b->d_expected) (void)hipFree(b->d_expected);
-  if (b->d_counts) (void)hipFree(b->d_counts);
-  *b->plan_epoch = kDeadEpoch;
-  b->magic = kDead;
-  delete b;
-  return TS_OK;
-}
-
-int ts_batch_info(ts_batch b, size_t* count, uint64_t* total, uint64_t* tiles, int64_t* tile_elems) {
-  if (!ok_batch(b)) return fail(TS_E_INVALID, "invalid batch handle");
-  if (count) *count = b->host.size();
-  if (total) *total = b->total;
-  if (tiles) *tiles = b->tiles.size();
-  if (tile_elems) *tile_elems = b->tile_elems;
-  return TS_OK;
-}
-
-int ts_batch_set_tile(ts_batch b, int64_t tile_elems) {
-  TS_GUARD_BEGIN
-  if (!ok_batch(b) || !ok_target(b->target)) return fail(TS_E_INVALID, "invalid batch handle");
-  int st = use_device(b->device);
-  if (st != TS_OK) return st;
-  if ((st = batch_replan(b, tile_elems)) != TS_OK) return st;
-  b->tile_pinned = true;
-  free_op_plans(b);
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_batch_op(ts_target exec, ts_batch b, ts_op op) {
-  TS_GUARD_BEGIN
-  int st = check_batch_exec(exec, b);
-  if (st != TS_OK) return st;
-  if (!valid_op(op)) return fail(TS_E_INVALID, "bad op");
-  return launch_batch(exec, b, op, batch_cfg(b, op));
-  TS_GUARD_END
-}
-
-int ts_batch_op_plain(ts_target exec, ts_batch b, ts_op op) {
-  TS_GUARD_BEGIN
-  int st = check_batch_exec(exec, b);
-  if (st != TS_OK) return st;
-  if (!valid_op(op)) return fail(TS_E_INVALID, "bad op");
-  for (const HostDesc& h : b->host) {
-    if (h.len == 0) continue;
-    const void* x;
-    const void* y = nullptr;
-    void* d;
-    switch (op) {  // Listing 4 roles inside every instance
-      case TS_COPY: x = reinterpret_cast<void*>(h.a); d = reinterpret_cast<void*>(h.c); break;
-      case TS_SCALE: x = reinterpret_cast<void*>(h.c); d = reinterpret_cast<void*>(h.b); break;
-      case TS_ADD: x = reinterpret_cast<void*>(h.a); y = reinterpret_cast<void*>(h.b); d = reinterpret_cast<void*>(h.c); break;
-      default: x = reinterpret_cast<void*>(h.b); y = reinterpret_cast<void*>(h.c); d = reinterpret_cast<void*>(h.a); break;
-    }
-    const uintptr_t ya = reinterpret_cast<uintptr_t>(y);
-    const int cls = align_class(reinterpret_cast<uintptr_t>(x), y ? &ya : nullptr, reinterpret_cast<uintptr_t>(d));
-    const ts_kernel_cfg cfg = tune_table().lookup(op, b->dtype, h.len, cls, 0);
-    if ((st = launch_map(exec, op, b->dtype, x, y, d, h.len, h.q, cfg)) != TS_OK) return st;
-  }
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_batch_fill(ts_target exec, ts_batch b, int which, double value) {
-  TS_GUARD_BEGIN
-  int st = check_batch_exec(exec, b);
-  if (st != TS_OK) return st;
-  if (which < 0 || which > 2) return fail(TS_E_INVALID, "which must be 0 (a), 1 (b) or 2 (c)");
-  if (b->tiles.empty()) return TS_OK;
-  const hipError_t e = launch_batch_fill(b->dtype, b->d_tiles, b->tiles.size(), which, 0,
-                                         value, 0, aux_grid(exec, b->tiles.size()), exec->stream);
-  if (e != hipSuccess) return hip_fail(e, "batched fill launch");
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_batch_fill_uniform(ts_target exec, ts_batch b, int which, uint64_t seed) {
-  TS_GUARD_BEGIN
-  int st = check_batch_exec(exec, b);
-  if (st != TS_OK) return st;
-  if (which < 0 || which > 2) return fail(TS_E_INVALID, "which must be 0 (a), 1 (b) or 2 (c)");
-  if (b->host.size() > (((1ull << 16) - 16) / 3))
-    return fail(TS_E_UNSUPPORTED, "too many instances for 16-bit stream ids");
-  if (b->tiles.empty()) return TS_OK;
-  const hipError_t e = launch_batch_fill(b->dtype, b->d_tiles, b->tiles.size(), which, 1,
-                                         0.0, seed, aux_grid(exec, b->tiles.size()), exec->stream);
-  if (e != hipSuccess) return hip_fail(e, "batched uniform fill launch");
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_batch_mismatch_count(ts_target exec, ts_batch b, int which, const double* expected,
-                            uint64_t* counts) {
-  TS_GUARD_BEGIN
-  int st = check_batch_exec(exec, b);
-  if (st != TS_OK) return st;
-  if (which < 0 || which > 2) return fail(TS_E_INVALID, "which must be 0 (a), 1 (b) or 2 (c)");
-  const size_t n = b->host.size();
-  if (n == 0) return TS_OK;
-  if (!expected || !counts) return fail(TS_E_INVALID, "NULL expected or counts");
-  TS_HIP(hipMemcpyAsync(b->d_expected, expected, n * sizeof(double), hipMemcpyHostToDevice, exec->stream));
-  hipError_t e = launch_zero_u64(b->d_counts, n, exec->stream);
-  if (e != hipSuccess) return hip_fail(e, "zero kernel launch");
-  if (!b->tiles.empty()) {
-    e = launch_batch_mismatch(b->dtype, b->d_tiles, b->tiles.size(), which, b->d_expected,
-                              b->d_counts, aux_grid(exec, b->tiles.size()), exec->stream);
-    if (e != hipSuccess) return hip_fail(e, "batched mismatch launch");
-  }
-  TS_HIP(hipMemcpyAsync(counts, b->d_counts, n * sizeof(uint64_t), hipMemcpyDeviceToHost, exec->stream));
-  TS_HIP(hipStreamSynchronize(exec->stream));
-  return TS_OK;
-  TS_GUARD_END
-}
-
-// ---------------------------------------------------------------------------
-// Graphs
-// ---------------------------------------------------------------------------
-}  // extern "C"
-
-namespace {
-
-template <class Body>
-int capture(ts_target_s* t, Body&& body, ts_graph* out, const ts_batch_s* batch = nullptr) {
-  if (!out) return fail(TS_E_INVALID, "NULL out");
-  if (t->host) return host_only_gpu("graph capture");
-  if (t->stream == nullptr)
-    return fail(TS_E_UNSUPPORTED, "graph capture needs a target with a non-default stream");
-  int st = use_device(t->device);
-  if (st != TS_OK) return st;
-  TS_HIP(hipStreamBeginCapture(t->stream, hipStreamCaptureModeThreadLocal));
-  st = body();
-  hipGraph_t graph = nullptr;
-  const hipError_t ee = hipStreamEndCapture(t->stream, &graph);
-  if (st != TS_OK) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return st;
-  }
-  if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
-  hipGraphExec_t exec = nullptr;
-  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  if (ie != hipSuccess) {
-    (void)hipGraphDestroy(graph);
-    return hip_fail(ie, "hipGraphInstantiate");
-  }
-  ts_graph_s* g = new ts_graph_s();
-  g->device = t->device;
-  g->graph = graph;
-  g->exec = exec;
-  if (batch) {
-    g->batch_epoch = batch->plan_epoch;
-    g->epoch_at_capture = *batch->plan_epoch;
-  }
-  g->magic = kGraphMagic;
-  *out = g;
-  return TS_OK;
-}
-
-}  // namespace
-
-extern "C" {
-
-int ts_graph_capture_stream_iterations(ts_target t, ts_batch b, int iterations, ts_graph* out) {
-  TS_GUARD_BEGIN
-  int st = check_batch_exec(t, b);
-  if (st != TS_OK) return st;
-  if (iterations < 1 || iterations > TS_GRAPH_MAX_ITERATIONS)
-    return fail(TS_E_INVALID, "iterations must be in [1, TS_GRAPH_MAX_ITERATIONS]");
-  return capture(
-      t,
-      [&]() {
-        for (int k = 0; k < iterations; ++k)
-          for (int op = TS_COPY; op <= TS_TRIAD; ++op) {
-            const int s = launch_batch(t, b, op, batch_cfg(b, op));
-            if (s != TS_OK) return s;
-          }
-        return static_cast<int>(TS_OK);
-      },
-      out, b);
-  TS_GUARD_END
-}
-
-int ts_graph_capture_stream_iteration(ts_target t, ts_batch b, ts_graph* out) {
-  return ts_graph_capture_stream_iterations(t, b, 1, out);
-}
-
-int ts_graph_capture_batch_op(ts_target t, ts_batch b, ts_op op, ts_graph* out) {
-  TS_GUARD_BEGIN
-  int st = check_batch_exec(t, b);
-  if (st != TS_OK) return st;
-  if (!valid_op(op)) return fail(TS_E_INVALID, "bad op");
-  return capture(t, [&]() { return launch_batch(t, b, op, batch_cfg(b, op)); }, out, b);
-  TS_GUARD_END
-}
-
-int ts_graph_capture_arrays_iterations(ts_target t, ts_array a, ts_array b, ts_array c, double q,
-                                       int iterations, ts_graph* out) {
-  TS_GUARD_BEGIN
-  if (!ok_target(t)) return fail(TS_E_INVALID, "invalid target handle");
-  if (t->host) return host_only_gpu("graph capture");
-  if (iterations < 1 || iterations > TS_GRAPH_MAX_ITERATIONS)
-    return fail(TS_E_INVALID, "iterations must be in [1, TS_GRAPH_MAX_ITERATIONS]");
-  return capture(
-      t,
-      [&]() {
-        for (int k = 0; k < iterations; ++k) {
-          const int s = ts_stream_iteration(t, a, b, c, q);
-          if (s != TS_OK) return s;
-        }
-        return static_cast<int>(TS_OK);
-      },
-      out);
-  TS_GUARD_END
-}
-
-int ts_graph_capture_arrays_iteration(ts_target t, ts_array a, ts_array b, ts_array c, double q,
-                                      ts_graph* out) {
-  return ts_graph_capture_arrays_iterations(t, a, b, c, q, 1, out);
-}
-
-int ts_graph_launch(ts_target t, ts_graph g, int repeats) {
-  TS_GUARD_BEGIN
-  if (!ok_target(t) || !ok_graph(g)) return fail(TS_E_INVALID, "invalid target or graph handle");
-  if (t->host) return host_only_gpu("graph launch");
-  if (repeats < 0) return fail(TS_E_INVALID, "negative repeat count");
-  if (g->device != t->device) return fail(TS_E_PLACEMENT, "graph belongs to another device");
-  if (g->batch_epoch && *g->batch_epoch != g->epoch_at_capture)
-    return fail(TS_E_INVALID, "the graph's batch was re-planned or destroyed after capture");
-  int st = use_device(t->device);
-  if (st != TS_OK) return st;
-  for (int r = 0; r < repeats; ++r) TS_HIP(hipGraphLaunch(g->exec, t->stream));
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_graph_destroy(ts_graph g) {
-  if (!g) return TS_OK;
-  if (!ok_graph(g)) return fail(TS_E_INVALID, "invalid graph handle");
-  (void)use_device(g->device);
-  (void)hipGraphExecDestroy(g->exec);
-  (void)hipGraphDestroy(g->graph);
-  g->magic = kDead;
-  delete g;
-  return TS_OK;
-}
-
-// ---------------------------------------------------------------------------
-// Events
-// ---------------------------------------------------------------------------
-int ts_event_create(ts_event* out) {
-  TS_GUARD_BEGIN
-  if (!out) return fail(TS_E_INVALID, "NULL out");
-  int dev = 0;
-  TS_HIP(hipGetDevice(&dev));
-  hipEvent_t ev = nullptr;
-  TS_HIP(hipEventCreate(&ev));
-  ts_event_s* e = new ts_event_s();
-  e->device = dev;
-  e->ev = ev;
-  e->recorded = false;
-  e->magic = kEventMagic;
-  *out = e;
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_event_destroy(ts_event e) {
-  if (!e) return TS_OK;
-  if (!ok_event(e)) return fail(TS_E_INVALID, "invalid event handle");
-  (void)hipEventDestroy(e->ev);
-  e->magic = kDead;
-  delete e;
-  return TS_OK;
-}
-
-int ts_event_record(ts_event e, ts_target t) {
-  if (!ok_event(e) || !ok_target(t)) return fail(TS_E_INVALID, "invalid event or target handle");
-  if (t->host) return host_only_gpu("events");
-  int st = use_device(t->device);
-  if (st != TS_OK) return st;
-  TS_HIP(hipEventRecord(e->ev, t->stream));
-  e->recorded = true;
-  return TS_OK;
-}
-
-int ts_event_synchronize(ts_event e) {
-  if (!ok_event(e)) return fail(TS_E_INVALID, "invalid event handle");
-  TS_HIP(hipEventSynchronize(e->ev));
-  return TS_OK;
-}
-
-int ts_event_query(ts_event e) {
-  if (!ok_event(e)) return fail(TS_E_INVALID, "invalid event handle");
-  const hipError_t r = hipEventQuery(e->ev);
-  if (r == hipSuccess) return TS_OK;
-  if (r == hipErrorNotReady) {
-    (void)hipGetLastError();
-    return 1;
-  }
-  return hip_fail(r, "hipEventQuery");
-}
-
-int ts_event_elapsed_ms(ts_event start, ts_event end, float* ms) {
-  if (!ok_event(start) || !ok_event(end) || !ms) return fail(TS_E_INVALID, "invalid event handle or NULL out");
-  TS_HIP(hipEventElapsedTime(ms, start->ev, end->ev));
-  return TS_OK;
-}
-
-// ---------------------------------------------------------------------------
-// Futures
-// ---------------------------------------------------------------------------
-int ts_target_async(ts_target t, ts_future* out) {
-  TS_GUARD_BEGIN
-  if (!ok_target(t) || !out) return fail(TS_E_INVALID, "invalid target handle or NULL out");
-  ts_future_s* f = new ts_future_s();
-  f->ready = false;
-  f->magic = kFutureMagic;
-  if (t->host) {  // host calls complete before they return
-    f->ready = true;
-    *out = f;
-    return TS_OK;
-  }
-  int st = use_device(t->device);
-  if (st != TS_OK) {
-    f->magic = kDead;
-    delete f;
-    return st;
-  }
-  const hipError_t e = hipLaunchHostFunc(t->stream, future_ready_cb, f);
-  if (e != hipSuccess) {
-    f->magic = kDead;
-    delete f;
-    return hip_fail(e, "hipLaunchHostFunc");
-  }
-  *out = f;
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_future_wait(ts_future f) {
-  TS_GUARD_BEGIN
-  if (!ok_future(f)) return fail(TS_E_INVALID, "invalid future handle");
-  std::unique_lock<std::mutex> lk(f->mu);
-  f->cv.wait(lk, [f] { return f->ready; });
-  return TS_OK;
-  TS_GUARD_END
-}
-
-int ts_future_ready(ts_future f) {
-  TS_GUARD_BEGIN
-  if (!ok_future(f)) return fail(TS_E_INVALID, "invalid future handle");
-  std::lock_guard<std::mutex> lk(f->mu);
-  return f->ready ? 1 : 0;
-  TS_GUARD_END
-}
-
-int ts_future_destroy(ts_future f) {
-  if (!f) return TS_OK;
-  if (!ok_future(f)) return fail(TS_E_INVALID, "invalid future handle");
-  {
-    std::unique_lock<std::mutex> lk(f->mu);
-    f->cv.wait(lk, [f] { return f->ready; });  // the callback still refers to it
-  }
-  f->magic = kDead;
-  delete f;
-  return TS_OK;
 }
 
 }  // extern "C"
