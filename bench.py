@@ -50,10 +50,14 @@ PROFILE_PMC = os.path.join(ROOT, "profiles", "triad_f64_n2p27_pmc.md")
 
 def kernel_source_digest() -> str:
     """Digest of what determines the f64 kernels the headline launches: their
-    source and the tuned launch configurations (measured rates excluded)."""
+    source (comments and whitespace aside) and the tuned launch configurations
+    (measured rates excluded)."""
     h = hashlib.sha256()
     for rel in ("paper_2206_06302_amd/csrc/ts_device.hpp", "paper_2206_06302_amd/csrc/kern_f64.hip"):
-        h.update(open(os.path.join(ROOT, rel), "rb").read())
+        text = open(os.path.join(ROOT, rel)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)  # comments and layout do not change code
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     tune = os.path.join(ROOT, "paper_2206_06302_amd", "tune", "gfx950.json")
     if os.path.exists(tune):
         entries = json.load(open(tune)).get("entries", [])

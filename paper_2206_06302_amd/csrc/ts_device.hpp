@@ -219,9 +219,11 @@ __device__ __forceinline__ void roles(const BatchTile& tl, const void*& x, const
   else { x = tl.b; y = tl.c; d = const_cast<void*>(tl.a); }
 }
 
-// Persistent kernel: workgroup w takes tiles w, w + G, w + 2G, ... (static
-// stride, G = grid size).  Each tile record is self-contained, and the next
-// one is fetched while the current tile streams; inside a tile the lanes
+// One launch over every instance: workgroup w takes tiles w, w + G, w + 2G,
+// ... (G = grid size).  With one workgroup per tile (G = number of tiles,
+// the tuned shape) each workgroup takes one tile; with a smaller grid the
+// workgroups persist and stride.  Each tile record is self-contained, and the
+// next one is fetched while the current tile streams; inside a tile the lanes
 // stream 16-byte vectors like the plain kernel.
 template <int DT, int OP, int U, bool NTL, bool NTS>
 __global__ __launch_bounds__(1024) void batch_kernel(const BatchTile* __restrict__ tiles,
