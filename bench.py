@@ -208,7 +208,7 @@ def batched_leg(ts, torch, tgt, count=4096, seed=5, replays=50, triad_reps=20):
             ev[i + 1].record(tgt)
         ev[-1].synchronize()
         return [ev[i].elapsed_ms(ev[i + 1]) for i in range(reps)]
-    # triad alone: one persistent launch over all instances
+    # triad alone: one launch over all instances
     t_ms = timed(lambda: batch.op(tgt, "triad"), triad_reps)
     # comparison: one plain launch per instance (4096 launches per map)
     p_ms = timed(lambda: batch.op_plain(tgt, "triad"), 5)

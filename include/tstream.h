@@ -361,7 +361,7 @@ TS_API int ts_batch_info(ts_batch batch, size_t *count, uint64_t *total_elems,
  * Re-planning (this call, ts_autotune_batch) frees the old tile tables, so
  * graphs captured from the batch before it must not be launched again. */
 TS_API int ts_batch_set_tile(ts_batch batch, int64_t tile_elems);
-/* Apply map `op` to every instance in one persistent launch (bulk
+/* Apply map `op` to every instance in one launch (bulk
  * execution over all instances, Sections 3.3 and 4.2). */
 TS_API int ts_batch_op(ts_target exec, ts_batch batch, ts_op op);
 /* The same map as one plain launch per instance (the comparison form). */
