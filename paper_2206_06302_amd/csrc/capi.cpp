@@ -440,6 +440,7 @@ int ts_array_alloc(ts_target t, ts_dtype dtype, size_t n, size_t offset_elems, t
     }
   }
   ts_array_s* a = new ts_array_s();
+  a->alive = std::make_shared<bool>(true);
   a->target = t;
   a->device = t->device;
   a->dtype = dtype;
@@ -485,6 +486,7 @@ int ts_array_wrap(ts_target t, ts_dtype dtype, void* dev_ptr, size_t n, ts_array
       return fail(TS_E_PLACEMENT, "pointer lives on device %d, the target is device %d", attr.device, t->device);
   }
   ts_array_s* a = new ts_array_s();
+  a->alive = std::make_shared<bool>(true);
   a->target = t;
   a->device = t->device;
   a->dtype = dtype;
@@ -506,6 +508,7 @@ int ts_array_free(ts_array a) {
     (void)use_device(a->device);
     (void)hipFree(a->owned_base);
   }
+  *a->alive = false;
   a->magic = kDead;
   delete a;
   return TS_OK;

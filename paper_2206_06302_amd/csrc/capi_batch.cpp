@@ -438,7 +438,7 @@ int ts_graph_capture_arrays_iterations(ts_target t, ts_array a, ts_array b, ts_a
   if (t->host) return host_only_gpu("graph capture");
   if (iterations < 1 || iterations > TS_GRAPH_MAX_ITERATIONS)
     return fail(TS_E_INVALID, "iterations must be in [1, TS_GRAPH_MAX_ITERATIONS]");
-  return capture(
+  const int st = capture(
       t,
       [&]() {
         for (int k = 0; k < iterations; ++k) {
@@ -448,6 +448,8 @@ int ts_graph_capture_arrays_iterations(ts_target t, ts_array a, ts_array b, ts_a
         return static_cast<int>(TS_OK);
       },
       out);
+  if (st == TS_OK) (*out)->arrays_alive = {a->alive, b->alive, c->alive};
+  return st;
   TS_GUARD_END
 }
 
@@ -464,6 +466,8 @@ int ts_graph_launch(ts_target t, ts_graph g, int repeats) {
   if (g->device != t->device) return fail(TS_E_PLACEMENT, "graph belongs to another device");
   if (g->batch_epoch && *g->batch_epoch != g->epoch_at_capture)
     return fail(TS_E_INVALID, "the graph's batch was re-planned or destroyed after capture");
+  for (const std::shared_ptr<bool>& alive : g->arrays_alive)
+    if (!*alive) return fail(TS_E_INVALID, "an array of the graph was freed after capture");
   int st = use_device(t->device);
   if (st != TS_OK) return st;
   for (int r = 0; r < repeats; ++r) TS_HIP(hipGraphLaunch(g->exec, t->stream));

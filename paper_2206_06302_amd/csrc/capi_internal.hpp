@@ -97,6 +97,7 @@ struct ts_graph_s {
   hipGraphExec_t exec;
   std::shared_ptr<uint64_t> batch_epoch;  // null for graphs of plain arrays
   uint64_t epoch_at_capture;
+  std::vector<std::shared_ptr<bool>> arrays_alive;  // graphs of plain arrays
 };
 
 struct ts_event_s {

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include <memory>
+
 #include "../../include/tstream.h"
 #include "host_target.hpp"
 
@@ -39,6 +41,9 @@ struct ts_array_s {
   void* ptr;
   uint64_t n;
   void* owned_base;
+  // Cleared by ts_array_free; graphs captured over the array share it and
+  // refuse to launch once it is cleared.
+  std::shared_ptr<bool> alive;
 };
 
 inline bool ts_ok_target_handle(const ts_target_s* t) { return t && t->magic == ts::kTargetMagic; }

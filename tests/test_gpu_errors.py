@@ -110,6 +110,26 @@ def test_graph_capture_needs_a_stream(env):
     dflt.close()
 
 
+def test_graph_refuses_freed_arrays(env):
+    """A graph over library-owned arrays refuses to launch once one of them
+    has been freed, instead of touching freed memory."""
+    ts, torch, tgt = env
+    own = ts.Target(0, "own")
+    a, b, c = (ts.Array.alloc(own, "f64", 4099) for _ in range(3))
+    for arr, v in zip((a, b, c), (1.0, 2.0, 0.0)):
+        arr.fill(v)
+    g = ts.Graph.capture_arrays_iteration(own, a, b, c, 3.0, iterations=2)
+    g.launch(own, 1)
+    own.synchronize()
+    assert ts.checksum(own, a, 225.0)["mismatches"] == 0
+    b.free()
+    assert status(ts, lambda: g.launch(own, 1)) == E_INVALID
+    assert "freed" in ts.last_error()
+    g.close()
+    a.free(), c.free()
+    own.close()
+
+
 def test_batch_errors(env):
     ts, torch, tgt = env
     host = np.zeros(64)
