@@ -24,7 +24,8 @@ plain launches; reduced-precision storage (binary32, bfloat16, binary16) at
 N = 2^28 per array; a size/alignment sweep from 2^16 to 2^29 elements (L2,
 Infinity Cache and HBM regimes); launch overhead at small sizes (eager
 calls against HIP graphs); and library comparators on the same traffic (the
-runtime's device copy, torch's elementwise b + q*c).  --legs picks a subset.  The CPU-baseline leg times the oracle
+runtime's device copy, torch's elementwise b + q*c); and the triad as a
+run-time-compiled generic transform.  --legs picks a subset.  The CPU-baseline leg times the oracle
 on host cores.
 """
 from __future__ import annotations
@@ -44,7 +45,7 @@ if ROOT not in sys.path:
 METRIC = "STREAM Triad/Copy GB/s and % of HBM peak, FP64 N=2^27; batched vs plain"
 PEAK_GBPS = 8000.0
 OPS = ("copy", "scale", "add", "triad")
-EXTRA_LEGS = ("batched", "reduced_precision", "sweep", "launch_overhead", "comparators")
+EXTRA_LEGS = ("batched", "reduced_precision", "sweep", "launch_overhead", "comparators", "transform")
 PROFILE_PMC = os.path.join(ROOT, "profiles", "triad_f64_n2p27_pmc.md")
 
 
@@ -360,6 +361,36 @@ def overhead_leg(ts, torch, tgt, lo=12, hi=22, iters=192, per_graph=16):
     return out
 
 
+def transform_leg(ts, tgt, n, reps=20):
+    """The triad as a generic transform: the expression fma(q, y, x) compiled
+    at run time (hipRTC) and applied by the generic grid-stride kernel, on
+    the headline arrays, against the tuned triad kernel in the same run.
+    Both results must agree bit for bit."""
+    A, B, C, D = (ts.Array.alloc(tgt, "f64", n) for _ in range(4))
+    for arr, k in zip((A, B, C), range(3)):
+        arr.fill_uniform(2, k)
+    tr = ts.Transform(tgt, "fma(q, y, x)", 2, "f64")
+    out = {}
+    for name, fn in (("transform_fma_expression", lambda: tr(tgt, B, D, C, 3.0)),
+                     ("tuned_triad_kernel", lambda: ts.triad(tgt, B, C, A, 3.0))):
+        ev = [ts.Event() for _ in range(reps + 1)]
+        fn()
+        ev[0].record(tgt)
+        for i in range(reps):
+            fn()
+            ev[i + 1].record(tgt)
+        ev[-1].synchronize()
+        ms = [ev[i].elapsed_ms(ev[i + 1]) for i in range(reps)]
+        b = ts.stream_bytes("triad", n)
+        out[name] = {"best_GBps": round(b / min(ms) / 1e6, 1), "avg_GBps": round(b / (sum(ms) / len(ms)) / 1e6, 1)}
+    out["same_bits"] = ts.mismatch_count(tgt, A, D) == 0
+    out["avg_ratio"] = round(out["transform_fma_expression"]["avg_GBps"] / out["tuned_triad_kernel"]["avg_GBps"], 3)
+    tr.close()
+    for arr in (A, B, C, D):
+        arr.free()
+    return out
+
+
 def comparator_leg(torch, n, reps=20):
     """The same traffic through library kernels, for context: the runtime's
     device-to-device copy (hipMemcpyAsync behind torch's copy_) and torch's
@@ -531,7 +562,8 @@ def main():
                          ("reduced_precision", lambda: reduced_leg(ts, torch, tgt)),
                          ("sweep", lambda: sweep_leg(ts, tgt)),
                          ("launch_overhead", lambda: overhead_leg(ts, torch, tgt)),
-                         ("comparators", lambda: comparator_leg(torch, a.n))):
+                         ("comparators", lambda: comparator_leg(torch, a.n)),
+                         ("transform", lambda: transform_leg(ts, tgt, a.n))):
             if a.legs and name not in a.legs:
                 continue
             log(f"{name} leg")
