@@ -4,9 +4,11 @@
 // The paper's GPU executor runs any device callable (Section 4.2), and its
 // hello-world example transforms a vector of chars with to_upper (Section
 // 3.4, Listing 3).  A C ABI cannot carry a callable, so the callable arrives
-// as the text of a C++ expression in x, y and q; the library wraps it in a
-// grid-stride kernel, compiles it once per (expression, inputs, storage
-// type, architecture) and launches it on the executing target's stream.
+// as the text of a C++ expression in x, y and q; the library wraps it in two
+// kernels (16-byte vectors for operands that share their alignment, and an
+// element-wise fallback), compiles them once per (expression, inputs,
+// storage type, architecture) and launches one on the executing target's
+// stream.
 // hipRTC is opened lazily (dlopen), so it is needed only when transforms
 // are used.
 #include <dlfcn.h>
@@ -99,24 +101,57 @@ TypeText type_text(int dtype) {
   }
 }
 
+// The generated source holds two kernels around the expression:
+//   ts_transform_vec     one pass, 16-byte nontemporal vectors (16 / element
+//                        size elements per lane) plus an element-wise head and
+//                        tail, for operands that share their misalignment
+//                        modulo 16 bytes;
+//   ts_transform_kernel  element-wise with a grid-stride loop, for any operands.
 std::string kernel_source(const std::string& expr, int n_inputs, int dtype) {
   const TypeText t = type_text(dtype);
+  const bool two = n_inputs == 2;
   std::string s;
   s += "typedef " + std::string(t.storage) + " ts_store_t;\n";
   s += "typedef " + std::string(t.arith) + " ts_arith_t;\n";
+  s += "typedef unsigned int ts_u4 __attribute__((ext_vector_type(4)));\n";
+  s += "#define TS_E (16 / sizeof(ts_store_t))\n";
+  s += "struct ts_vec_t { ts_store_t v[TS_E]; };\n";
   s += "__device__ inline float ts_keep(float v) { asm(\"\" : \"+v\"(v)); return v; }\n";
   s += "__device__ inline ts_arith_t ts_widen(ts_store_t v) { return " + std::string(t.widen) + "; }\n";
   s += "__device__ inline ts_store_t ts_narrow(ts_arith_t r) { return " + std::string(t.narrow) + "; }\n";
+  s += "__device__ inline ts_store_t ts_apply(ts_store_t xv, ts_store_t yv, ts_arith_t q) {\n"
+       "  (void)q; (void)yv;\n"
+       "  const ts_arith_t x = ts_widen(xv);\n";
+  if (two) s += "  const ts_arith_t y = ts_widen(yv);\n";
+  s += "  return ts_narrow((ts_arith_t)(" + expr + "));\n}\n";
   s += "extern \"C\" __global__ void ts_transform_kernel(const ts_store_t* __restrict__ xs,\n"
        "    const ts_store_t* __restrict__ ys, ts_store_t* ds, double qd, unsigned long long n) {\n"
        "  const ts_arith_t q = (ts_arith_t)qd;\n"
-       "  (void)q;\n"
        "  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;\n"
        "  for (unsigned long long j = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; j < n;\n"
-       "       j += stride) {\n"
-       "    const ts_arith_t x = ts_widen(xs[j]);\n";
-  if (n_inputs == 2) s += "    const ts_arith_t y = ts_widen(ys[j]);\n";
-  s += "    ds[j] = ts_narrow((ts_arith_t)(" + expr + "));\n  }\n}\n";
+       "       j += stride)\n";
+  s += two ? "    ds[j] = ts_apply(xs[j], ys[j], q);\n}\n" : "    ds[j] = ts_apply(xs[j], xs[j], q);\n}\n";
+  s += "extern \"C\" __global__ void ts_transform_vec(const ts_store_t* __restrict__ xs,\n"
+       "    const ts_store_t* __restrict__ ys, ts_store_t* ds, double qd, unsigned long long head,\n"
+       "    unsigned long long nvec, unsigned long long tail) {\n"
+       "  const ts_arith_t q = (ts_arith_t)qd;\n"
+       "  const unsigned long long g = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;\n"
+       "  const unsigned long long t0 = head + nvec * TS_E;\n";
+  s += two ? "  if (g < head) ds[g] = ts_apply(xs[g], ys[g], q);\n"
+             "  if (g < tail) ds[t0 + g] = ts_apply(xs[t0 + g], ys[t0 + g], q);\n"
+           : "  if (g < head) ds[g] = ts_apply(xs[g], xs[g], q);\n"
+             "  if (g < tail) ds[t0 + g] = ts_apply(xs[t0 + g], xs[t0 + g], q);\n";
+  s += "  if (g < nvec) {\n"
+       "    const ts_vec_t xv = __builtin_bit_cast(ts_vec_t,\n"
+       "        __builtin_nontemporal_load(reinterpret_cast<const ts_u4*>(xs + head) + g));\n";
+  s += two ? "    const ts_vec_t yv = __builtin_bit_cast(ts_vec_t,\n"
+             "        __builtin_nontemporal_load(reinterpret_cast<const ts_u4*>(ys + head) + g));\n"
+           : "    const ts_vec_t yv = xv;\n";
+  s += "    ts_vec_t dv;\n"
+       "#pragma unroll\n"
+       "    for (unsigned e = 0; e < TS_E; ++e) dv.v[e] = ts_apply(xv.v[e], yv.v[e], q);\n"
+       "    __builtin_nontemporal_store(__builtin_bit_cast(ts_u4, dv), reinterpret_cast<ts_u4*>(ds + head) + g);\n"
+       "  }\n}\n";
   return s;
 }
 
@@ -132,7 +167,8 @@ struct ts_transform_s {
   int dtype;
   int n_inputs;
   hipModule_t module;
-  hipFunction_t fn;
+  hipFunction_t fn;      // element-wise, grid-stride
+  hipFunction_t fn_vec;  // 16-byte vectors, one pass
   std::string log;
 };
 
@@ -190,8 +226,9 @@ int ts_transform_create(ts_target t, const char* expr, int n_inputs, ts_dtype dt
     hipModule_t mod = nullptr;
     he = hipModuleLoadData(&mod, code->data());
     if (he != hipSuccess) return api_hip_fail(he, "hipModuleLoadData");
-    hipFunction_t fn = nullptr;
+    hipFunction_t fn = nullptr, fn_vec = nullptr;
     he = hipModuleGetFunction(&fn, mod, "ts_transform_kernel");
+    if (he == hipSuccess) he = hipModuleGetFunction(&fn_vec, mod, "ts_transform_vec");
     if (he != hipSuccess) {
       (void)hipModuleUnload(mod);
       return api_hip_fail(he, "hipModuleGetFunction");
@@ -202,6 +239,7 @@ int ts_transform_create(ts_target t, const char* expr, int n_inputs, ts_dtype dt
     x->n_inputs = n_inputs;
     x->module = mod;
     x->fn = fn;
+    x->fn_vec = fn_vec;
     x->log = log;
     x->magic = kTransformMagic;
     *out = x;
@@ -233,9 +271,33 @@ int ts_transform_apply(ts_target t, ts_transform x, ts_array a, ts_array b, ts_a
     const void* xp = a->ptr;
     const void* yp = two ? b->ptr : a->ptr;
     void* dp = d->ptr;
-    unsigned long long n = c.count;
-    void* args[] = {&xp, &yp, &dp, &q, &n};
+    const unsigned long long n = c.count;
+    const unsigned long long es = dtype_size(a->dtype);
+    const unsigned long long per_vec = 16 / es;
+    const uintptr_t xa = reinterpret_cast<uintptr_t>(xp), ya = reinterpret_cast<uintptr_t>(yp),
+                    da = reinterpret_cast<uintptr_t>(dp);
     const unsigned block = 256;
+    if ((xa - da) % 16 == 0 && (ya - da) % 16 == 0) {
+      // Shared misalignment: element-wise head up to the next 16-byte
+      // boundary of every operand, vectors, element-wise tail.
+      unsigned long long head = ((16 - da % 16) % 16) / es;
+      if (head > n) head = n;
+      const unsigned long long nvec = (n - head) / per_vec;
+      const unsigned long long tail = n - head - nvec * per_vec;
+      unsigned long long lanes = nvec > head ? nvec : head;
+      if (tail > lanes) lanes = tail;
+      const unsigned long long grid = (lanes + block - 1) / block;
+      if (grid <= 0x7fffffffull) {
+        void* args[] = {&xp, &yp, &dp, &q, &head, const_cast<unsigned long long*>(&nvec),
+                        const_cast<unsigned long long*>(&tail)};
+        he = hipModuleLaunchKernel(x->fn_vec, static_cast<unsigned>(grid), 1, 1, block, 1, 1, 0, t->stream,
+                                   args, nullptr);
+        if (he != hipSuccess) return api_hip_fail(he, "hipModuleLaunchKernel");
+        return TS_OK;
+      }
+    }
+    unsigned long long nn = n;
+    void* args[] = {&xp, &yp, &dp, &q, &nn};
     unsigned long long grid = (n + block - 1) / block;
     const unsigned long long cap = 32ull * static_cast<unsigned long long>(t->info.compute_units);
     if (grid > cap) grid = cap;  // grid-stride over the rest

@@ -118,3 +118,39 @@ def test_bad_expressions_and_rules(env):
         tr(tgt, a, short)
     assert e.value.status == -2
     tr.close()
+
+
+@pytest.mark.parametrize("offs", [(0, 0, 0), (1, 1, 1), (1, 0, 0), (0, 1, 1), (1, 1, 0)])
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 4099, 100003])
+def test_vector_and_elementwise_paths(env, offs, n):
+    """Operands sharing their misalignment run the 16-byte vector kernel with
+    an element-wise head and tail; others run the element-wise kernel.  Both
+    give numpy's IEEE result of the expression."""
+    ts, torch, tgt = env
+    x = tsgen.uniform_array(8, 0, n)
+    y = tsgen.uniform_array(8, 1, n)
+    X = device_array(ts, torch, tgt, x, "f64", offs[0])
+    Y = device_array(ts, torch, tgt, y, "f64", offs[1])
+    D = empty_array(ts, torch, tgt, n, "f64", offs[2])
+    tr = ts.Transform(tgt, "x * x - q * y", 2, "f64")
+    say(f"[transform paths n={n} offs={offs}]")
+    tr(tgt, X, D, Y, 0.75)
+    assert_same_bits(D.to_host(), x * x - 0.75 * y, "f64", f"offs={offs}")
+    tr(tgt, X, X, Y, 0.75)  # in place
+    assert_same_bits(X.to_host(), x * x - 0.75 * y, "f64", "in place")
+    tr.close()
+
+
+@pytest.mark.parametrize("off_in,off_out", [(0, 0), (3, 3), (5, 0), (15, 15)])
+@pytest.mark.parametrize("n", [1, 15, 16, 33, 65537])
+def test_bytes_to_upper_offsets(env, off_in, off_out, n):
+    """1-byte elements: 16 per vector, heads of up to 15 bytes."""
+    ts, torch, tgt = env
+    rng = np.random.default_rng(n + off_in)
+    text = rng.integers(32, 127, n).astype(np.uint8)
+    S = device_array(ts, torch, tgt, text, "u8", off_in)
+    D = empty_array(ts, torch, tgt, n, "u8", off_out)
+    up = ts.Transform(tgt, TO_UPPER, 1, "u8")
+    up(tgt, S, D)
+    assert D.to_host().tobytes() == text.tobytes().upper()
+    up.close()
