@@ -445,7 +445,7 @@ TS_API int ts_future_ready(ts_future future);
 TS_API int ts_future_destroy(ts_future future);
 
 /* ------------------------------------------------------------------------ */
-/* Generic transforms: a user expression compiled at run time (hipRTC)       */
+/* Generic transforms: a user expression compiled at run time               */
 /* ------------------------------------------------------------------------ */
 /* The paper's GPU executor runs any device callable (Section 4.2) and its
  * hello-world example transforms a vector of chars with to_upper (Section
@@ -457,12 +457,19 @@ TS_API int ts_future_destroy(ts_future future);
  * dst[j] = expr(x[j], y[j], q).  Nothing is contracted (-ffp-contract=off);
  * __builtin_fma(q, y, x) is a fused triad.  The expression is compiled once
  * per (expression, inputs, type, GPU architecture) and cached for the life
- * of the process.  Errors: TS_E_INVALID with the compiler's log when the
- * expression does not compile; TS_E_UNSUPPORTED without hipRTC or on a host
- * target.  ts_transform_apply follows the rules of the algorithm calls
- * (count = n of x; shapes, types, placement, aliasing) and is asynchronous
- * on the executor's stream; work using a transform must have finished
- * before it is destroyed. */
+ * of the process.  GPU targets compile with hipRTC.  Host-CPU targets
+ * (Section 4.1) compile with the system C++ compiler (TS_HOST_CXX, default
+ * "c++", run as a child process) into a shared object that their pinned
+ * workers run over their blocks; they take TS_F64, TS_F32 and TS_U8, and
+ * `fma` there is std::fma.  A transform runs on targets of the kind it was
+ * made for (TS_E_PLACEMENT otherwise).  Errors: TS_E_INVALID with the
+ * compiler's log when the expression does not compile; TS_E_UNSUPPORTED
+ * without hipRTC (GPU) or a host compiler (host), or for 16-bit storage on
+ * a host target.  ts_transform_apply follows the rules of the algorithm
+ * calls (count = n of x; shapes, types, placement, aliasing) and is
+ * asynchronous on the executor's stream (host targets: complete on
+ * return); work using a transform must have finished before it is
+ * destroyed. */
 TS_API int ts_transform_create(ts_target target, const char *expr, int n_inputs,
                                ts_dtype dtype, ts_transform *out);
 TS_API int ts_transform_apply(ts_target exec, ts_transform transform,

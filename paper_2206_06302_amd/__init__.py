@@ -220,10 +220,10 @@ class Array:
     @classmethod
     def wrap_numpy(cls, target: Target, arr: np.ndarray) -> "Array":
         """Borrow a contiguous 1-D numpy array (host memory; host targets)."""
-        names = {np.dtype(np.float64): "f64", np.dtype(np.float32): "f32"}
+        names = {np.dtype(np.float64): "f64", np.dtype(np.float32): "f32", np.dtype(np.uint8): "u8"}
         dtype = names.get(arr.dtype)
         if dtype is None or arr.ndim != 1 or not arr.flags.c_contiguous:
-            raise TSError(-3, "need a contiguous 1-D float64 or float32 array")
+            raise TSError(-3, "need a contiguous 1-D float64, float32 or uint8 array")
         h = ctypes.c_void_p()
         _check(lib.ts_array_wrap(target.handle, DTYPES[dtype], ctypes.c_void_p(arr.ctypes.data), arr.size,
                                  ctypes.byref(h)))

@@ -30,7 +30,7 @@ ARCH = os.environ.get("TS_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["kern_f64.hip", "kern_f32.hip", "kern_bf16.hip", "kern_f16.hip", "kern_aux.hip",
            "capi.cpp", "capi_tune.cpp", "capi_batch.cpp", "capi_async.cpp", "tune.cpp", "host_target.cpp",
-           "transform.cpp"]
+           "transform.cpp", "host_transform.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "../../include/tstream.h"
+#include "host_transform.hpp"
 #include "ts_handles.hpp"
 #include "ts_layout.hpp"
 
@@ -169,6 +170,7 @@ struct ts_transform_s {
   hipModule_t module;
   hipFunction_t fn;      // element-wise, grid-stride
   hipFunction_t fn_vec;  // 16-byte vectors, one pass
+  HostTransformFn host_fn;  // host-CPU targets: the compiled block function
   std::string log;
 };
 
@@ -177,9 +179,26 @@ extern "C" {
 int ts_transform_create(ts_target t, const char* expr, int n_inputs, ts_dtype dtype, ts_transform* out) {
   try {
     if (!ts_ok_target_handle(t) || !expr || !out) return api_fail(TS_E_INVALID, "invalid target, expression or out");
-    if (t->host) return api_fail(TS_E_UNSUPPORTED, "transforms are compiled for GPU targets");
     if (n_inputs != 1 && n_inputs != 2) return api_fail(TS_E_INVALID, "n_inputs must be 1 or 2");
     if (dtype < TS_F64 || dtype > TS_U8) return api_fail(TS_E_INVALID, "unknown dtype");
+    if (t->host) {
+      if (dtype != TS_F64 && dtype != TS_F32 && dtype != TS_U8)
+        return api_fail(TS_E_UNSUPPORTED, "host targets support binary64, binary32 and byte storage");
+      HostTransformFn fn = nullptr;
+      std::string log;
+      const int st = host_transform_compile(expr, n_inputs, static_cast<int>(dtype), &fn, &log);
+      if (st == TS_E_INVALID) return api_fail(st, "expression does not compile: %s", log.c_str());
+      if (st != TS_OK) return api_fail(st, "%s", log.c_str());
+      ts_transform_s* x = new ts_transform_s();
+      x->device = t->device;
+      x->dtype = dtype;
+      x->n_inputs = n_inputs;
+      x->host_fn = fn;
+      x->log = log;
+      x->magic = kTransformMagic;
+      *out = x;
+      return TS_OK;
+    }
     const Rtc& r = rtc();
     if (!r.ok) return api_fail(TS_E_UNSUPPORTED, "%s", r.why.c_str());
     hipError_t he = hipSetDevice(t->device);
@@ -253,7 +272,6 @@ int ts_transform_apply(ts_target t, ts_transform x, ts_array a, ts_array b, ts_a
   try {
     if (!ts_ok_target_handle(t) || !x || x->magic != kTransformMagic)
       return api_fail(TS_E_INVALID, "invalid target or transform handle");
-    if (t->host) return api_fail(TS_E_UNSUPPORTED, "transforms run on GPU targets");
     const bool two = x->n_inputs == 2;
     if (!ts_ok_array_handle(a) || !ts_ok_array_handle(d) || (two && !ts_ok_array_handle(b)))
       return api_fail(TS_E_INVALID, "invalid array handle");
@@ -266,6 +284,20 @@ int ts_transform_apply(ts_target t, ts_transform x, ts_array a, ts_array b, ts_a
     const MapCheck c = check_map(two, t->device, ox, two ? &oy : nullptr, od);
     if (c.status != ST_OK) return api_fail(c.status, "%s", c.msg.c_str());
     if (c.count == 0) return TS_OK;
+    if (t->host) {  // every worker runs the compiled function over its block
+      const void* xp = a->ptr;
+      const void* yp = two ? b->ptr : a->ptr;
+      void* dp = d->ptr;
+      const uint64_t n = c.count;
+      const int W = t->pool->size();
+      const HostTransformFn fn = x->host_fn;
+      t->pool->run([&](int w) {
+        uint64_t lo, hi;
+        HostPool::block(n, W, w, &lo, &hi);
+        fn(xp, yp, dp, q, lo, hi);
+      });
+      return TS_OK;
+    }
     hipError_t he = hipSetDevice(t->device);
     if (he != hipSuccess) return api_hip_fail(he, "hipSetDevice");
     const void* xp = a->ptr;
@@ -318,8 +350,10 @@ int ts_transform_log(ts_transform x, const char** log) {
 int ts_transform_destroy(ts_transform x) {
   if (!x) return TS_OK;
   if (x->magic != kTransformMagic) return api_fail(TS_E_INVALID, "invalid transform handle");
-  (void)hipSetDevice(x->device);
-  (void)hipModuleUnload(x->module);
+  if (x->module) {  // host transforms keep their shared object cached for the process
+    (void)hipSetDevice(x->device);
+    (void)hipModuleUnload(x->module);
+  }
   x->magic = 0xdeadbeefu;
   delete x;
   return TS_OK;

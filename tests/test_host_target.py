@@ -139,7 +139,7 @@ def test_host_target_limits(ts):
     with pytest.raises(ts.TSError):
         ts.Target.host([100000])
     with pytest.raises(ts.TSError) as e:
-        ts.Transform(tgt, "x + 1")
+        ts.Transform(tgt, "x + 1", 1, "bf16")
     assert e.value.status == E_UNSUPPORTED
     with pytest.raises(ts.TSError) as e:
         ts.copy(tgt, ts.Array.alloc(tgt, "u8", 10), ts.Array.alloc(tgt, "u8", 10))
@@ -152,4 +152,65 @@ def test_host_target_limits(ts):
     f.wait()
     ms = ts.time_op(tgt, "triad", a, a, a, 3.0, reps=3)
     assert ms >= 0
+    tgt.close()
+
+
+TO_UPPER = "(x >= 'a' && x <= 'z') ? x - ('a' - 'A') : x"
+
+
+@pytest.mark.parametrize("workers", [1, 4])
+def test_host_transforms(ts, workers):
+    """Generic transforms on a host target (compiled by the system C++
+    compiler, run by the pinned workers): the hello-world to_upper over
+    bytes, the fused triad against the oracle, and a general expression
+    against numpy's IEEE evaluation."""
+    tgt = ts.Target.host(_cpus(ts, workers))
+    text = b"hello world"
+    s = ts.Array.wrap_numpy(tgt, np.frombuffer(text, np.uint8).copy())
+    up = ts.Transform(tgt, TO_UPPER, 1, "u8")
+    up(tgt, s, s)  # in place, Listing 3
+    assert s.to_host().tobytes() == b"HELLO WORLD"
+    n = 100003
+    x = tsgen.uniform_array(12, 0, n)
+    y = tsgen.uniform_array(12, 1, n)
+    X, Y = ts.Array.wrap_numpy(tgt, x.copy()), ts.Array.wrap_numpy(tgt, y.copy())
+    D = ts.Array.alloc(tgt, "f64", n)
+    tr = ts.Transform(tgt, "fma(q, y, x)", 2, "f64")
+    tr(tgt, X, D, Y, 3.0)
+    ref = np.zeros(n)
+    oracle.op(oracle.F64, oracle.TRIAD, x, y, ref, 3.0)
+    assert np.array_equal(D.to_host().view(np.uint64), ref.view(np.uint64))
+    g = ts.Transform(tgt, "x * x - q * y", 2, "f64")
+    g(tgt, X, D, Y, 0.75)
+    assert np.array_equal(D.to_host().view(np.uint64), (x * x - 0.75 * y).view(np.uint64))
+    xf, yf = tsgen.uniform_array(12, 0, n, "f32"), tsgen.uniform_array(12, 1, n, "f32")
+    XF, YF = ts.Array.wrap_numpy(tgt, xf.copy()), ts.Array.wrap_numpy(tgt, yf.copy())
+    DF = ts.Array.alloc(tgt, "f32", n)
+    f = ts.Transform(tgt, "x + y", 2, "f32")
+    f(tgt, XF, DF, YF)
+    ref32 = np.zeros_like(xf)
+    oracle.op(oracle.F32, oracle.ADD, xf, yf, ref32, 0.0)
+    assert np.array_equal(DF.to_host().view(np.uint32), ref32.view(np.uint32))
+    for t_ in (up, tr, g, f):
+        t_.close()
+    tgt.close()
+
+
+def test_host_transform_errors(ts):
+    tgt = ts.Target.host(_cpus(ts, 2))
+    with pytest.raises(ts.TSError) as e:
+        ts.Transform(tgt, "x +* y", 2, "f64")
+    assert e.value.status == E_INVALID and "error" in e.value.message
+    with pytest.raises(ts.TSError) as e:  # y is not defined for one input
+        ts.Transform(tgt, "x + y", 1, "f64")
+    assert e.value.status == E_INVALID
+    tr = ts.Transform(tgt, "x + 1.0", 1, "f64")
+    a, short = ts.Array.alloc(tgt, "f64", 100), ts.Array.alloc(tgt, "f64", 99)
+    with pytest.raises(ts.TSError) as e:
+        tr(tgt, a, short)
+    assert e.value.status == E_SHAPE
+    with pytest.raises(ts.TSError) as e:
+        tr(tgt, ts.Array.alloc(tgt, "f32", 100), ts.Array.alloc(tgt, "f32", 100))
+    assert e.value.status == -3
+    tr.close()
     tgt.close()
