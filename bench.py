@@ -476,6 +476,51 @@ def host_target_leg(ts, n, threads, target_seconds=10.0):
             "iterations": iters, "valid": valid}
 
 
+def metric_records(result: dict) -> list[dict]:
+    """One record per measurement of a run, for --jsonl: the workload
+    (C2 headline, C3 sweep, C4 reduced precision, C5 batched), map, storage
+    type, size, offset, launch configuration, times and rates, and HBM
+    counter bytes where committed profiles cover the kernel."""
+    import platform
+
+    host = platform.node()
+    n = result["config"]["n"]
+    recs = []
+    traffic = result["roofline"].get("traffic")
+    for op, k in result["per_kernel"].items():
+        recs.append({"config": "C2", "op": op, "dtype": "f64", "n": n, "offset": 0, "kernel_cfg": k["cfg"],
+                     "best_ms": k["best_ms"], "avg_ms": k["avg_ms"], "GBps_best": k["best_GBps"],
+                     "GBps_avg": k["avg_GBps"], "pct_peak": k["pct_peak_avg"],
+                     "traffic_bytes": traffic if op == "triad" else None, "host": host, "ndev": 1})
+    for key, rows in result.get("sweep", {}).items():
+        if not isinstance(rows, dict) or "_" not in key:
+            continue
+        dtype, align = key.split("_", 1)
+        for size, row in rows.items():
+            if not isinstance(row, dict):
+                continue
+            p = int(size.split("^")[1])
+            for op in ("copy", "triad"):
+                if f"{op}_GBps" in row:
+                    recs.append({"config": "C3", "op": op, "dtype": dtype, "n": (1 << p) + (0 if align == "aligned" else 7),
+                                 "offset": 0 if align == "aligned" else 1, "GBps_best": row[f"{op}_GBps"],
+                                 "regime": row.get("regime"), "host": host, "ndev": 1})
+    for dtype, ops in result.get("reduced_precision", {}).items():
+        if not isinstance(ops, dict):
+            continue
+        for op, row in ops.items():
+            if isinstance(row, dict) and "GBps" in row:
+                recs.append({"config": "C4", "op": op, "dtype": dtype, "n": 1 << 28, "offset": 0,
+                             "GBps_best": row["GBps"], "rel_err_max": row.get("max_rel_err_vs_f64"),
+                             "host": host, "ndev": 1})
+    b = result.get("batched", {})
+    if "triad_best_GBps" in b:
+        recs.append({"config": "C5", "op": "triad", "dtype": "f64", "n": b["total_elems"], "offset": 0,
+                     "kernel_cfg": b["cfg"], "GBps_best": b["triad_best_GBps"], "GBps_avg": b["triad_avg_GBps"],
+                     "instances": b["instances"], "host": host, "ndev": 1})
+    return recs
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -488,6 +533,8 @@ def main():
     ap.add_argument("--legs", type=lambda v: [x for x in v.split(",") if x], default=None,
                     help="comma-separated extra legs to run after the headline (default: all): "
                          + ", ".join(EXTRA_LEGS))
+    ap.add_argument("--jsonl", default=None,
+                    help="also append one JSON record per measurement to this file")
     ap.add_argument("--order", choices=("listing", "copy_b"), default="listing",
                     help="listing: copy c = a (Listing 4); copy_b: the variant with copy a = b")
     a = ap.parse_args()
@@ -586,6 +633,10 @@ def main():
             except Exception as e:
                 result["host_target"] = {"error": f"{type(e).__name__}: {e}"}
     tgt.close()
+    if a.jsonl:
+        with open(a.jsonl, "a") as f:
+            for rec in metric_records(result):
+                f.write(json.dumps(rec) + "\n")
     print(json.dumps(result))
 
 

@@ -8,10 +8,15 @@ vector width, nontemporal load/store, grid shape) and keeps the fastest; the
 batched maps are tuned over a ragged batch of log-uniform lengths
 (ts_autotune_batch, which also picks the tile size).  Candidates all give
 bit-identical results, so tuning changes speed only.
+
+The table is saved after every size bucket, so an interrupted run loses at
+most one bucket; --resume starts from the table at --out and skips every key
+it already holds.
 """
 from __future__ import annotations
 
 import argparse
+import json
 import os
 import sys
 import time
@@ -21,6 +26,8 @@ def main() -> None:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--out", required=True)
     ap.add_argument("--merge", action="store_true", help="start from the existing table at --out")
+    ap.add_argument("--resume", action="store_true",
+                    help="start from the table at --out and skip the keys it already holds")
     ap.add_argument("--plain", default="f64:16-29,f32:16-29,bf16:26-28,f16:26-28",
                     help="dtype:lo-hi exponent ranges, comma separated")
     ap.add_argument("--ops", default="copy,scale,add,triad")
@@ -36,8 +43,13 @@ def main() -> None:
 
     tgt = ts.Target(0, torch.cuda.Stream())
     ts.tune_cache_clear()
-    if a.merge and os.path.exists(a.out):
+    done = set()
+    if (a.merge or a.resume) and os.path.exists(a.out):
         ts.tune_cache_load(a.out)
+        if a.resume:
+            for e in json.load(open(a.out)).get("entries", []):
+                done.add((e["op"], e["dtype"], int(e["bucket"]), int(e["align"]), int(e["batched"])))
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     ops = a.ops.split(",")
     aligns = [int(x) for x in a.aligns.split(",")]
     t0 = time.time()
@@ -50,9 +62,12 @@ def main() -> None:
             for align in aligns:
                 n = (1 << p) + (7 if align == 1 else 0)
                 for op in ops:
+                    if (op, dtype, p, align, 0) in done:
+                        continue
                     cfg, bps = ts.autotune(tgt, op, dtype, n, offset=1 if align == 1 else 0, reps=a.reps)
                     print(f"[{time.time()-t0:7.1f}s] {dtype} {op:5s} 2^{p}{'+7 off1' if align else ''}: "
                           f"{bps/1e9:8.1f} GB/s  {cfg}", flush=True)
+            ts.tune_cache_save(a.out)  # checkpoint after every size bucket
     if a.batched:
         import tsgen
         lens = tsgen.batched_lengths(a.batched_seed, a.batched)
@@ -69,14 +84,16 @@ def main() -> None:
         batch = ts.Batch(tgt, "f64", descs)
         for k in range(3):
             batch.fill_uniform(tgt, k, a.batched_seed)
+        bucket = int(batch.info()["total_elems"]).bit_length() - 1
         for op in ops:
+            if (op, "f64", bucket, 0, 1) in done:
+                continue
             cfg, bps = ts.autotune_batch(tgt, batch, op, reps=a.reps)
             print(f"[{time.time()-t0:7.1f}s] batched f64 {op:5s} {batch.info()['total_elems']} elems: "
                   f"{bps/1e9:8.1f} GB/s  {cfg}", flush=True)
         batch.close()
         del pools
         torch.cuda.empty_cache()
-    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     ts.tune_cache_save(a.out)
     print(f"wrote {a.out} after {time.time()-t0:.1f}s", flush=True)
     tgt.close()

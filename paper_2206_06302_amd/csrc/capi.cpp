@@ -15,6 +15,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <set>
+#include <tuple>
 
 #include "capi_internal.hpp"
 
@@ -184,7 +186,28 @@ int run_map(ts_target_s* t, int op, ts_array_s* x, ts_array_s* y, ts_array_s* d,
   const int cls = align_class(reinterpret_cast<uintptr_t>(x->ptr), has_y ? &ya : nullptr,
                               reinterpret_cast<uintptr_t>(d->ptr));
   const ts_kernel_cfg cfg = tune_table().lookup(op, x->dtype, count, cls, 0);
+  log_choice(op, x->dtype, count, cls, 0, cfg);
   return launch_map(t, op, x->dtype, x->ptr, has_y ? y->ptr : nullptr, d->ptr, count, q, cfg);
+}
+
+void log_choice(int op, int dtype, uint64_t n, int align, int batched, const ts_kernel_cfg& c) {
+  static const bool enabled = [] {
+    const char* v = std::getenv("TS_LOG");
+    return v && *v && std::strcmp(v, "0") != 0;
+  }();
+  if (!enabled) return;
+  static std::mutex mu;
+  static std::set<std::tuple<int, int, int, int, int>> seen;
+  const int bucket = n ? 63 - __builtin_clzll(n) : 0;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!seen.insert(std::make_tuple(op, dtype, bucket, align, batched)).second) return;
+  static const char* const kOps[] = {"copy", "scale", "add", "triad"};
+  static const char* const kTypes[] = {"f64", "f32", "bf16", "f16", "u8"};
+  std::fprintf(stderr,
+               "tstream: %s %s %s n=2^%d align=%d -> block %d, unroll %d, vec %d B, nt load %d, nt store %d, "
+               "grid/CU %d, tile %lld\n",
+               batched ? "batched" : "plain", kOps[op & 3], kTypes[dtype < 5 ? dtype : 0], bucket, align, c.block,
+               c.unroll, c.vec_bytes, c.nt_load, c.nt_store, c.grid_per_cu, static_cast<long long>(c.tile_elems));
 }
 
 }  // namespace tsapi

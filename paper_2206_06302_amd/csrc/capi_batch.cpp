@@ -81,7 +81,9 @@ void free_op_plans(ts_batch_s* b) {
 }
 
 ts_kernel_cfg batch_cfg(const ts_batch_s* b, int op) {
-  return tune_table().lookup(op, b->dtype, b->total, TS_ALIGN_16, 1);
+  const ts_kernel_cfg c = tune_table().lookup(op, b->dtype, b->total, TS_ALIGN_16, 1);
+  log_choice(op, b->dtype, b->total, TS_ALIGN_16, 1, c);
+  return c;
 }
 
 // Plans for the tile sizes of the four maps' configurations that differ from

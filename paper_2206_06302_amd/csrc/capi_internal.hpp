@@ -153,6 +153,10 @@ int launch_map(ts_target_s* t, int op, int dtype, const void* x, const void* y, 
                double q, const ts_kernel_cfg& cfg);
 int check_exec_arrays(ts_target_s* t, int op, ts_array_s* x, ts_array_s* y, ts_array_s* d, uint64_t* count);
 int run_map(ts_target_s* t, int op, ts_array_s* x, ts_array_s* y, ts_array_s* d, double q);
+// With TS_LOG set (non-empty, not "0"), report on stderr, once per key
+// (map, type, size bucket, alignment class, batched), the launch
+// configuration the library picked.
+void log_choice(int op, int dtype, uint64_t n, int align, int batched, const ts_kernel_cfg& c);
 
 // Batches (capi_batch.cpp).
 void bump_epoch(ts_batch_s* b);
