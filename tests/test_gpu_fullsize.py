@@ -224,3 +224,57 @@ def test_batched_full_4096_instances(env):
     batch.close()
     del pools
     _free(torch)
+
+
+def _boundary_indices(n, rng):
+    idx = set(_sample_indices(n, rng).tolist())
+    for b in (1 << 31, 1 << 32):
+        idx.update(k for k in range(b - 3, b + 4) if 0 <= k < n)
+    return np.array(sorted(idx), np.int64)
+
+
+def test_beyond_32bit_element_indices(env):
+    """Arrays of more than 2^32 elements (binary16, 8.6 GB each, one element
+    past an aligned base) and of 2^31 + 9 binary64 elements: the triad and
+    the copy at every sampled element, including both sides of 2^31 and 2^32,
+    equal the oracle; whole-array checksums see every element."""
+    ts, torch, tgt = env
+    n = (1 << 32) + 37
+    bufs = [torch.empty(n + 1, dtype=torch.float16, device="cuda") for _ in range(3)]
+    torch.cuda.synchronize()
+    views = [b[1:] for b in bufs]
+    X, Y, D = (ts.Array.wrap(tgt, v) for v in views)
+    X.fill_uniform(21, 0), Y.fill_uniform(21, 1)
+    say(f"[triad f16 n=2^32+37]")
+    ts.triad(tgt, X, Y, D, 3.0)
+    tgt.synchronize()
+    idx = _boundary_indices(n, np.random.default_rng(4))
+    u = idx.astype(np.uint64)
+    x = tsgen.narrow(tsgen.uniform_pm1(21, 0, u), "f16")
+    y = tsgen.narrow(tsgen.uniform_pm1(21, 1, u), "f16")
+    ref = np.zeros_like(x)
+    oracle.op(oracle.F16, oracle.TRIAD, x, y, ref, 3.0)
+    got = _gather(torch, views[2], idx).view(torch.int16).numpy().view(np.uint16)
+    bad = mismatches(got, ref, "f16")
+    assert bad.size == 0, (idx[bad[:5]], got[bad[:5]], ref[bad[:5]])
+    X.fill(0.5)
+    cs = ts.checksum(tgt, X, 0.5)
+    assert cs["mismatches"] == 0 and cs["sum"] == 0.5 * n
+    del X, Y, D, views, bufs
+    _free(torch)
+
+    n = (1 << 31) + 9
+    bufs = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(2)]
+    torch.cuda.synchronize()
+    S, T = (ts.Array.wrap(tgt, b) for b in bufs)
+    S.fill_uniform(22, 0)
+    say(f"[copy f64 n=2^31+9]")
+    ts.copy(tgt, S, T)
+    tgt.synchronize()
+    idx = _boundary_indices(n, np.random.default_rng(5))
+    want = tsgen.uniform_pm1(22, 0, idx.astype(np.uint64))
+    got = _gather(torch, bufs[1], idx).numpy()
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+    assert ts.mismatch_count(tgt, S, T) == 0
+    del S, T, bufs
+    _free(torch)
