@@ -44,14 +44,32 @@ __device__ __forceinline__ bool differs(double v, double e) {
   return __builtin_bit_cast(uint64_t, v) != __builtin_bit_cast(uint64_t, e);
 }
 
+// 16 bytes of one repeated element.
+template <class T>
+struct Splat {
+  T e[16 / sizeof(T)];
+};
+
+// Elements [0, head) and those after the `nvec` 16-byte vectors are stored
+// one by one; the vectors in between with 16-byte nontemporal stores.
 template <int DT>
-__global__ __launch_bounds__(256) void fill_const_kernel(void* p, uint64_t n, double value) {
+__global__ __launch_bounds__(256) void fill_const_kernel(void* p, uint64_t n, double value, uint64_t head,
+                                                         uint64_t nvec) {
   using T = typename Fmt<DT>::T;
+  using R = typename Raw<16>::type;
+  constexpr uint64_t E = 16 / sizeof(T);
   T* d = static_cast<T*>(p);
   const T v = from_f64<DT>(value);
+  const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n; j += stride)
-    d[j] = v;
+  for (uint64_t j = g; j < head; j += stride) d[j] = v;
+  for (uint64_t j = head + nvec * E + g; j < n; j += stride) d[j] = v;
+  Splat<T> s;
+#pragma unroll
+  for (uint64_t e = 0; e < E; ++e) s.e[e] = v;
+  const R r = __builtin_bit_cast(R, s);
+  R* dv = reinterpret_cast<R*>(d + head);
+  for (uint64_t k = g; k < nvec; k += stride) __builtin_nontemporal_store(r, dv + k);
 }
 
 // lo + w * u01 with u01 = (h >> 11) * 2^-53 in [0, 1): a product and a sum,
@@ -110,14 +128,22 @@ __global__ __launch_bounds__(256) void checksum_pass1(const void* xv, uint64_t n
   const uint64_t lo = static_cast<uint64_t>(blockIdx.x) * n / nparts;
   const uint64_t hi = static_cast<uint64_t>(blockIdx.x + 1) * n / nparts;
   CsPart acc{0.0, 0.0, __builtin_nan(""), 0ull};
-  for (uint64_t j = lo + threadIdx.x; j < hi; j += kReduceBlock) {
-    const double v = to_f64<DT>(x[j]);
+  auto add = [&](double v) {
     const double dv = fabs(v - expected);
     acc.sum += v;
     acc.absdev += dv;
     acc.maxdev = fmax(acc.maxdev, dv);
     acc.mism += differs(v, expected) ? 1ull : 0ull;
+  };
+  // Each lane folds its elements in ascending order; four loads are issued
+  // before they are folded, to keep more of them in flight.
+  uint64_t j = lo + threadIdx.x;
+  for (; j + 3 * kReduceBlock < hi; j += 4 * kReduceBlock) {
+    const double v0 = to_f64<DT>(x[j]), v1 = to_f64<DT>(x[j + kReduceBlock]);
+    const double v2 = to_f64<DT>(x[j + 2 * kReduceBlock]), v3 = to_f64<DT>(x[j + 3 * kReduceBlock]);
+    add(v0), add(v1), add(v2), add(v3);
   }
+  for (; j < hi; j += kReduceBlock) add(to_f64<DT>(x[j]));
   const CsPart r = block_reduce(acc);
   if (threadIdx.x == 0) parts[blockIdx.x] = r;
 }
@@ -125,7 +151,13 @@ __global__ __launch_bounds__(256) void checksum_pass1(const void* xv, uint64_t n
 // Pass 2: one workgroup folds the parts in a fixed order.
 __global__ __launch_bounds__(256) void reduce_pass2(const CsPart* parts, uint32_t nparts, CsPart* out) {
   CsPart acc{0.0, 0.0, __builtin_nan(""), 0ull};
-  for (uint32_t j = threadIdx.x; j < nparts; j += kReduceBlock) combine(acc, parts[j]);
+  uint32_t j = threadIdx.x;
+  for (; j + 3 * kReduceBlock < nparts; j += 4 * kReduceBlock) {  // loads first, then the folds in order
+    const CsPart p0 = parts[j], p1 = parts[j + kReduceBlock], p2 = parts[j + 2 * kReduceBlock],
+                 p3 = parts[j + 3 * kReduceBlock];
+    combine(acc, p0), combine(acc, p1), combine(acc, p2), combine(acc, p3);
+  }
+  for (; j < nparts; j += kReduceBlock) combine(acc, parts[j]);
   const CsPart r = block_reduce(acc);
   if (threadIdx.x == 0) *out = r;
 }
@@ -139,15 +171,20 @@ __global__ __launch_bounds__(256) void mismatch_pass1(const void* xv, const void
   const uint64_t lo = static_cast<uint64_t>(blockIdx.x) * n / nparts;
   const uint64_t hi = static_cast<uint64_t>(blockIdx.x + 1) * n / nparts;
   CsPart acc{0.0, 0.0, 0.0, 0ull};
-  for (uint64_t j = lo + threadIdx.x; j < hi; j += kReduceBlock) {
-    const T a = x[j], b = r[j];
+  auto count = [&](T a, T b) {
     bool diff;
     if constexpr (sizeof(T) == 8) diff = __builtin_bit_cast(uint64_t, a) != __builtin_bit_cast(uint64_t, b);
     else if constexpr (sizeof(T) == 4) diff = __builtin_bit_cast(uint32_t, a) != __builtin_bit_cast(uint32_t, b);
     else diff = a != b;
     if (diff && __builtin_isnan(to_f64<DT>(a)) && __builtin_isnan(to_f64<DT>(b))) diff = false;
     acc.mism += diff ? 1ull : 0ull;
+  };
+  uint64_t j = lo + threadIdx.x;
+  for (; j + kReduceBlock < hi; j += 2 * kReduceBlock) {  // two pairs of loads in flight per lane
+    const T a0 = x[j], b0 = r[j], a1 = x[j + kReduceBlock], b1 = r[j + kReduceBlock];
+    count(a0, b0), count(a1, b1);
   }
+  for (; j < hi; j += kReduceBlock) count(x[j], r[j]);
   const CsPart res = block_reduce(acc);
   if (threadIdx.x == 0) parts[blockIdx.x] = res;
 }
@@ -201,7 +238,7 @@ uint32_t fill_grid(uint64_t n) {
 }  // namespace
 
 uint32_t reduce_parts(uint64_t n) {
-  const uint64_t p = (n + 4095) / 4096;
+  const uint64_t p = (n + 2047) / 2048;
   return static_cast<uint32_t>(p < 1 ? 1 : (p > kReduceMaxParts ? kReduceMaxParts : p));
 }
 
@@ -216,7 +253,16 @@ uint32_t reduce_parts(uint64_t n) {
   return hipGetLastError();
 
 hipError_t launch_fill_const(int dt, void* p, uint64_t n, double value, hipStream_t s) {
-  TS_BY_FORMAT(dt, fill_const_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, n, value)
+  const uint64_t es = dtype_size(dt), per = 16 / es;
+  const uint64_t a = reinterpret_cast<uintptr_t>(p) % 16;  // a multiple of es
+  uint64_t head = ((16 - a) % 16) / es;
+  if (head > n) head = n;
+  const uint64_t nvec = (n - head) / per;
+  uint64_t grid = (nvec + 255) / 256;  // one pass over the vectors, up to 2^20 workgroups
+  if (grid < 1) grid = 1;
+  if (grid > (1u << 20)) grid = 1u << 20;
+  TS_BY_FORMAT(dt, fill_const_kernel, dim3(static_cast<uint32_t>(grid)), dim3(256), 0, s, p, n, value, head,
+               nvec)
 }
 
 hipError_t launch_fill_uniform(int dt, void* p, uint64_t n, uint64_t seed, uint64_t stream_id,

@@ -23,7 +23,7 @@ struct PlainLaunch {
   hipStream_t stream;
 };
 
-// Arguments of one persistent batched launch over a tile table.
+// Arguments of one batched launch over a tile table.
 struct BatchLaunch {
   const BatchTile* tiles;
   uint64_t ntiles;
@@ -52,7 +52,7 @@ struct CsPart {
 
 // Fixed reduction shape: depends only on n, never on tuning.
 constexpr uint32_t kReduceBlock = 256;
-constexpr uint32_t kReduceMaxParts = 1024;
+constexpr uint32_t kReduceMaxParts = 8192;
 uint32_t reduce_parts(uint64_t n);
 // Device scratch a target needs for one reduction: parts plus the result.
 constexpr size_t kReduceScratchBytes = (kReduceMaxParts + 1) * sizeof(CsPart);

@@ -186,6 +186,24 @@ def test_fill_uniform_matches_generator(env, dtype, first):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+def test_fill_small_and_offset(env, dtype):
+    """Constant fills store an element-wise head, 16-byte vectors and an
+    element-wise tail: every split of n and offset writes exactly [0, n)."""
+    ts, torch, tgt = env
+    es = ts.ELEM_SIZE[dtype]
+    for n in (1, 2, 3, 5, 7, 8, 9, 15, 16, 17, 31, 33, 1000):
+        for off in range(8):
+            buf = torch.empty(n + off + 8, dtype=ts.TORCH_DTYPES[dtype], device="cuda")
+            buf.view(torch.uint8).fill_(0x55)
+            torch.cuda.synchronize()
+            A = ts.Array.wrap(tgt, buf[off:off + n])
+            A.fill(-2.5)
+            assert_same_bits(A.to_host(), tsgen.narrow(np.full(n, -2.5), dtype), dtype, f"n={n} off={off}")
+            raw = buf.view(torch.uint8).cpu().numpy()
+            assert np.all(raw[:off * es] == 0x55) and np.all(raw[(off + n) * es:] == 0x55), (n, off)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
 @pytest.mark.parametrize("lo,hi", [(0.5, 4.0), (-3.0, 1e-3), (-1.0, 1.0)])
 def test_fill_uniform_range_matches_generator(env, dtype, lo, hi):
     """The range form draws the host generator's values; on [-1, 1) it is the
