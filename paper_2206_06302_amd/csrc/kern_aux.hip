@@ -80,14 +80,28 @@ __device__ __forceinline__ double uniform_range(uint64_t state0, uint64_t counte
   return lo + w * (static_cast<double>(h >> 11) * 0x1p-53);
 }
 
+// Element j gets counter first + j + 1; the layout (head, 16-byte vectors,
+// tail) is that of fill_const_kernel and does not change any value.
 template <int DT>
 __global__ __launch_bounds__(256) void fill_uniform_kernel(void* p, uint64_t n, uint64_t state0,
-                                                           uint64_t first, double lo, double w) {
+                                                           uint64_t first, double lo, double w, uint64_t head,
+                                                           uint64_t nvec) {
   using T = typename Fmt<DT>::T;
+  using R = typename Raw<16>::type;
+  constexpr uint64_t E = 16 / sizeof(T);
   T* d = static_cast<T*>(p);
+  const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n; j += stride)
-    d[j] = from_f64<DT>(uniform_range(state0, first + j + 1, lo, w));
+  auto value = [&](uint64_t j) { return from_f64<DT>(uniform_range(state0, first + j + 1, lo, w)); };
+  for (uint64_t j = g; j < head; j += stride) d[j] = value(j);
+  for (uint64_t j = head + nvec * E + g; j < n; j += stride) d[j] = value(j);
+  R* dv = reinterpret_cast<R*>(d + head);
+  for (uint64_t k = g; k < nvec; k += stride) {
+    Splat<T> s;
+#pragma unroll
+    for (uint64_t e = 0; e < E; ++e) s.e[e] = value(head + k * E + e);
+    __builtin_nontemporal_store(__builtin_bit_cast(R, s), dv + k);
+  }
 }
 
 __device__ __forceinline__ void combine(CsPart& a, const CsPart& b) {
@@ -252,15 +266,22 @@ uint32_t reduce_parts(uint64_t n) {
   }                                                                                            \
   return hipGetLastError();
 
-hipError_t launch_fill_const(int dt, void* p, uint64_t n, double value, hipStream_t s) {
+// Element-wise head up to the first 16-byte boundary, whole 16-byte vectors,
+// and the grid for one pass over the vectors (up to 2^20 workgroups of 256
+// lanes; the kernels stride over the rest).
+static void vector_split(int dt, const void* p, uint64_t n, uint64_t* head, uint64_t* nvec, uint64_t* grid) {
   const uint64_t es = dtype_size(dt), per = 16 / es;
   const uint64_t a = reinterpret_cast<uintptr_t>(p) % 16;  // a multiple of es
-  uint64_t head = ((16 - a) % 16) / es;
-  if (head > n) head = n;
-  const uint64_t nvec = (n - head) / per;
-  uint64_t grid = (nvec + 255) / 256;  // one pass over the vectors, up to 2^20 workgroups
-  if (grid < 1) grid = 1;
-  if (grid > (1u << 20)) grid = 1u << 20;
+  *head = ((16 - a) % 16) / es;
+  if (*head > n) *head = n;
+  *nvec = (n - *head) / per;
+  uint64_t g = (*nvec + 255) / 256;
+  *grid = g < 1 ? 1 : (g > (1u << 20) ? (1u << 20) : g);
+}
+
+hipError_t launch_fill_const(int dt, void* p, uint64_t n, double value, hipStream_t s) {
+  uint64_t head, nvec, grid;
+  vector_split(dt, p, n, &head, &nvec, &grid);
   TS_BY_FORMAT(dt, fill_const_kernel, dim3(static_cast<uint32_t>(grid)), dim3(256), 0, s, p, n, value, head,
                nvec)
 }
@@ -268,8 +289,10 @@ hipError_t launch_fill_const(int dt, void* p, uint64_t n, double value, hipStrea
 hipError_t launch_fill_uniform(int dt, void* p, uint64_t n, uint64_t seed, uint64_t stream_id,
                                uint64_t first_index, double lo, double w, hipStream_t s) {
   const uint64_t state0 = seed ^ (stream_id << 48);
-  TS_BY_FORMAT(dt, fill_uniform_kernel, dim3(fill_grid(n)), dim3(256), 0, s, p, n, state0, first_index,
-               lo, w)
+  uint64_t head, nvec, grid;
+  vector_split(dt, p, n, &head, &nvec, &grid);
+  TS_BY_FORMAT(dt, fill_uniform_kernel, dim3(static_cast<uint32_t>(grid)), dim3(256), 0, s, p, n, state0,
+               first_index, lo, w, head, nvec)
 }
 
 hipError_t launch_checksum(int dt, const void* x, uint64_t n, double expected, void* scratch,

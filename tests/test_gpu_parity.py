@@ -201,6 +201,11 @@ def test_fill_small_and_offset(env, dtype):
             assert_same_bits(A.to_host(), tsgen.narrow(np.full(n, -2.5), dtype), dtype, f"n={n} off={off}")
             raw = buf.view(torch.uint8).cpu().numpy()
             assert np.all(raw[:off * es] == 0x55) and np.all(raw[(off + n) * es:] == 0x55), (n, off)
+            A.fill_uniform(17, 3, 1000 + off)
+            assert_same_bits(A.to_host(), tsgen.uniform_array(17, 3, n, dtype, start=1000 + off), dtype,
+                             f"uniform n={n} off={off}")
+            raw = buf.view(torch.uint8).cpu().numpy()
+            assert np.all(raw[:off * es] == 0x55) and np.all(raw[(off + n) * es:] == 0x55), (n, off)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
