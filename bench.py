@@ -539,7 +539,7 @@ def main():
                     help="listing: copy c = a (Listing 4); copy_b: the variant with copy a = b")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(STREAM shards with no exchange: each GPU would run the same kernels on its own block).", file=sys.stderr)
         sys.exit(2)
     if a.steps < 1 or a.warmup < 0:

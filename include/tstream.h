@@ -68,7 +68,7 @@ typedef enum {
     TS_E_ALIAS = -5,       /* output partly overlaps an input                 */
     TS_E_DEVICE = -6,      /* HIP runtime error (message has its text)        */
     TS_E_OOM = -7,         /* device or host allocation failed                */
-    TS_E_UNSUPPORTED = -8  /* valid request this build cannot serve           */
+    TS_E_UNSUPPORTED = -8  /* valid request the library cannot serve         */
 } ts_status;
 
 /* Storage types.  TS_U8 (bytes, e.g. characters) is accepted by the array,
