@@ -31,7 +31,7 @@ on host cores.
 from __future__ import annotations
 
 import argparse
-import hashlib
+import importlib.util
 import json
 import os
 import re
@@ -50,22 +50,14 @@ PROFILE_PMC = os.path.join(ROOT, "profiles", "triad_f64_n2p27_pmc.md")
 
 
 def kernel_source_digest() -> str:
-    """Digest of what determines the f64 kernels the headline launches: their
-    source (comments and whitespace aside) and the tuned launch configurations
-    (measured rates excluded)."""
-    h = hashlib.sha256()
-    for rel in ("paper_2206_06302_amd/csrc/ts_device.hpp", "paper_2206_06302_amd/csrc/kern_f64.hip"):
-        text = open(os.path.join(ROOT, rel)).read()
-        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)  # comments and layout do not change code
-        text = re.sub(r"//[^\n]*", " ", text)
-        h.update(" ".join(text.split()).encode())
-    tune = os.path.join(ROOT, "paper_2206_06302_amd", "tune", "gfx950.json")
-    if os.path.exists(tune):
-        entries = json.load(open(tune)).get("entries", [])
-        cfgs = sorted(json.dumps({k: v for k, v in e.items() if k != "bytes_per_s"}, sort_keys=True)
-                      for e in entries if e.get("dtype") == "f64" and not e.get("batched"))
-        h.update("\n".join(cfgs).encode())
-    return h.hexdigest()[:16]
+    """Digest of the headline kernels' source and tuned configurations, as
+    recorded in the profile summaries (paper_2206_06302_amd/profiling.py,
+    loaded by path: it needs neither torch nor the library)."""
+    spec = importlib.util.spec_from_file_location(
+        "_tstream_profiling", os.path.join(ROOT, "paper_2206_06302_amd", "profiling.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.source_digest(ROOT)
 
 
 def committed_traffic():

@@ -48,3 +48,24 @@ def test_metric_records():
     assert len(by["C3"]) == 3
     assert {(r["dtype"], r["n"], r["offset"]) for r in by["C3"]} == {("f64", 1 << 16, 0), ("f32", (1 << 20) + 7, 1)}
     assert by["C4"][0]["rel_err_max"] == 3.8e-3 and by["C5"][0]["instances"] == 2
+
+
+def test_profiler_runs_follow_the_rules():
+    """Each rocprofv3 run names the program directly after `--`; counter runs
+    collect one counter each and combine it with no trace option."""
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location("_prof", os.path.join(ROOT, "paper_2206_06302_amd", "profiling.py"))
+    prof = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(prof)
+    assert prof.source_digest() == bench.kernel_source_digest()
+    names = []
+    for name, cmd, out in prof.runs("/tmp/raw"):
+        names.append(name)
+        assert cmd[0] == "rocprofv3"
+        after = cmd[cmd.index("--") + 1:]
+        assert after[0] == sys.executable and after[1].endswith("bench.py")
+        if "--pmc" in cmd:
+            assert len(cmd[cmd.index("--pmc") + 1].split()) == 1
+            assert not {"--kernel-trace", "--sys-trace", "--runtime-trace", "-s", "-r"} & set(cmd[:cmd.index("--")])
+    assert names == ["headline trace", "batched trace", "fetch counters", "write counters"]
