@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import tsgen
-from gpu_util import device_array, say
+from gpu_util import assert_same_bits, device_array, say
 
 pytestmark = pytest.mark.gpu
 
@@ -93,3 +93,38 @@ def test_every_batched_candidate_matches_plain(env):
     for op in OPS:
         ts.set_kernel_cfg(op, "f64", None, batched=True)
     bref.close(), bw.close()
+
+
+def test_random_cross_product_matches_oracle(env):
+    """300 seeded random cases over storage type x map x size x per-operand
+    misalignment x forced launch configuration (any plain candidate), each
+    compared with the oracle bit for bit.  Sizes are log-uniform up to 2^20
+    so heads, tails and partial last vectors all occur."""
+    ts, torch, tgt = env
+    rng = np.random.default_rng(2206)
+    cands = ts.candidates()
+    dtypes, ops = ["f64", "f32", "bf16", "f16"], ["copy", "scale", "add", "triad"]
+    try:
+        for case in range(300):
+            dtype, op = dtypes[rng.integers(4)], ops[rng.integers(4)]
+            n = int(np.floor(10 ** rng.uniform(0, 6)))
+            offs = tuple(int(v) for v in rng.integers(0, 8, 3))
+            cfg = cands[rng.integers(len(cands))]
+            q = float(rng.choice([3.0, -0.7, 1e-3, 2.5e4]))
+            seed = int(rng.integers(1 << 30))
+            ts.set_kernel_cfg(op, dtype, cfg)
+            x = tsgen.uniform_array(seed, 0, n, dtype)
+            y = tsgen.uniform_array(seed, 1, n, dtype)
+            d0 = tsgen.uniform_array(seed, 2, n, dtype)
+            X = device_array(ts, torch, tgt, x, dtype, offs[0])
+            Y = device_array(ts, torch, tgt, y, dtype, offs[1])
+            D = device_array(ts, torch, tgt, d0, dtype, offs[2])
+            ts.run_op(tgt, op, X, Y, D, q)
+            ref = d0.copy()
+            oracle.op(oracle.DTYPES[dtype], oracle.OPS[op], x, y if op in ("add", "triad") else None, ref, q)
+            assert_same_bits(D.to_host(), ref, dtype, f"case {case}: {dtype} {op} n={n} offs={offs} cfg={cfg}")
+            ts.set_kernel_cfg(op, dtype, None)
+    finally:
+        for dtype in dtypes:
+            for op in ops:
+                ts.set_kernel_cfg(op, dtype, None)
