@@ -7,12 +7,16 @@
  * device and on elements copied back, then runs a small ragged batch through
  * a captured multi-iteration graph and checks each instance's closed form.
  *
- * Usage: stream_client [n]   (default n = 1000003).  Exit status 0 when
- * every check passes; each step prints one line.
+ * Usage: stream_client [n] [host]   (default n = 1000003).  With "host" the
+ * same STREAM checks run on a host-CPU target (no GPU needed), followed by
+ * a run-time-compiled transform (to_upper over bytes); batches and graphs
+ * must then report TS_E_UNSUPPORTED.  Exit status 0 when every check
+ * passes; each step prints one line.
  */
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include "tstream.h"
 
@@ -55,12 +59,16 @@ static void closed_form(double q, int k, double *a, double *b, double *c)
 int main(int argc, char **argv)
 {
     size_t n = argc > 1 ? (size_t)strtoull(argv[1], NULL, 10) : 1000003u;
+    const int on_host = argc > 2 && strcmp(argv[2], "host") == 0;
     int major = 0, minor = 0;
     CHECK(ts_version(&major, &minor));
-    printf("libtstream %d.%d, n = %zu\n", major, minor, n);
+    printf("libtstream %d.%d, n = %zu, %s target\n", major, minor, n, on_host ? "host" : "GPU");
 
     ts_target tgt;
-    CHECK(ts_target_create_owned(0, &tgt));
+    if (on_host)
+        CHECK(ts_target_create_host(NULL, 0, &tgt));
+    else
+        CHECK(ts_target_create_owned(0, &tgt));
     ts_array arr[3];
     const double init[3] = {1.0, 2.0, 0.0};
     for (int k = 0; k < 3; ++k) {
@@ -90,6 +98,33 @@ int main(int argc, char **argv)
     expect(host[0] == expected[0] && host[n / 2] == expected[0] && host[n - 1] == expected[0],
            "copied-back elements of a equal 15^10");
     free(host);
+
+    if (on_host) {
+        /* Listing 3 on the host: upper-case a byte array in place. */
+        const char text[] = "hello world";
+        ts_array s;
+        CHECK(ts_array_alloc(tgt, TS_U8, sizeof text - 1, 0, &s));
+        CHECK(ts_copy_from_host(s, text, sizeof text - 1));
+        ts_transform up;
+        CHECK(ts_transform_create(tgt, "(x >= 'a' && x <= 'z') ? x - ('a' - 'A') : x", 1, TS_U8, &up));
+        CHECK(ts_transform_apply(tgt, up, s, NULL, s, 0.0));
+        char back[sizeof text] = {0};
+        CHECK(ts_copy_to_host(back, s, sizeof text - 1));
+        expect(strcmp(back, "HELLO WORLD") == 0, "to_upper transform on the host target");
+        CHECK(ts_transform_destroy(up));
+        CHECK(ts_array_free(s));
+        ts_batch none;
+        ts_batch_desc d0 = {NULL, NULL, NULL, 0, 1.0};
+        ts_graph g0;
+        expect(ts_batch_create(tgt, TS_F64, &d0, 1, &none) == TS_E_UNSUPPORTED &&
+                   ts_graph_capture_arrays_iteration(tgt, arr[0], arr[1], arr[2], 3.0, &g0) == TS_E_UNSUPPORTED,
+               "batches and graphs are GPU-only (TS_E_UNSUPPORTED)");
+        for (int k = 0; k < 3; ++k)
+            CHECK(ts_array_free(arr[k]));
+        CHECK(ts_target_destroy(tgt));
+        printf("%s\n", fail_count ? "FAILED" : "all checks passed");
+        return fail_count ? 1 : 0;
+    }
 
     /* A ragged batch carved out of the three arrays: instance i covers
      * elements [off_i, off_i + len_i) of each, with its own scalar. */

@@ -351,10 +351,16 @@ def test_header_is_plain_c_and_cxx(cmd, tmp_path):
     subprocess.run(cmd + ["-fsyntax-only", "-I" + os.path.join(ROOT, "include"), str(src)], check=True)
 
 
-def test_c_client_compiles_against_the_header_and_library(tmp_path):
+def test_c_client_on_a_host_target(tmp_path):
+    """The plain C consumer of the ABI, built against the header and the
+    library alone, runs its host-target mode: STREAM with the closed form,
+    a run-time-compiled transform, and GPU-only calls refused."""
     out = tmp_path / "stream_client"
+    lib_dir = os.path.join(ROOT, "paper_2206_06302_amd")
     subprocess.run(["gcc", "-std=c99", "-O2", "-Wall", "-Wextra", "-Werror", "-ffp-contract=off",
                     "-I" + os.path.join(ROOT, "include"), "-o", str(out),
-                    os.path.join(ROOT, "tests", "cpp", "stream_client.c"),
-                    "-L" + os.path.join(ROOT, "paper_2206_06302_amd"), "-ltstream"], check=True)
-    assert out.exists()
+                    os.path.join(ROOT, "tests", "cpp", "stream_client.c"), "-L" + lib_dir, "-ltstream",
+                    "-Wl,-rpath," + lib_dir], check=True)
+    r = subprocess.run([str(out), "100003", "host"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "all checks passed" in r.stdout and r.stdout.count("ok  ") == 6
