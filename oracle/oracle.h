@@ -28,9 +28,14 @@
  * q rounded once to binary32), and the result is narrowed back by
  * round-to-nearest-even with this file's own converters.
  *
- * Pins (tests under tests/, "not gpu"): closed form of the iteration from
- * (1, 2, 0) with q = 3; exact rational brute force on tiny random inputs for
- * every op and dtype; exhaustive converter comparison against numpy/torch.
+ * Pins (tests under tests/ that need no GPU): the closed form of the
+ * iteration from (1, 2, 0) with q = 3, and the closed form (Binet) of the
+ * variant whose copy is a <- b; exact rational arithmetic rounded once, for
+ * every op and storage type on tiny random and special inputs and for chains
+ * of up to 80 iterations (which also tells one rounding of the triad from
+ * two); the converters against numpy and torch over every rounding class
+ * (all 2^32 inputs with TS_EXHAUSTIVE=1); checksums against math.fsum; and
+ * the stored fixtures in tests/golden/.
  */
 #ifndef STREAM_ORACLE_H
 #define STREAM_ORACLE_H
