@@ -128,3 +128,56 @@ def test_random_cross_product_matches_oracle(env):
         for dtype in dtypes:
             for op in ops:
                 ts.set_kernel_cfg(op, dtype, None)
+
+
+def test_autotuner_on_small_problems(env, tmp_path):
+    """ts_autotune and ts_autotune_batch time every candidate, keep the
+    fastest in the table (which then serves it), and leave results
+    unchanged; the table survives a save and load."""
+    ts, torch, tgt = env
+    cands = ts.candidates()
+    try:
+        cfg, bps = ts.autotune(tgt, "triad", "f64", (1 << 16) + 7, offset=1, reps=1)
+        assert bps > 0 and cfg in cands
+        assert ts.get_kernel_cfg("triad", "f64", (1 << 16) + 7, align_class=ts.ALIGN_SHARED) == cfg
+        n = (1 << 16) + 7
+        x, y = tsgen.uniform_array(31, 0, n), tsgen.uniform_array(31, 1, n)
+        X, Y = device_array(ts, torch, tgt, x, "f64", 1), device_array(ts, torch, tgt, y, "f64", 1)
+        D = device_array(ts, torch, tgt, np.zeros(n), "f64", 1)
+        ts.triad(tgt, X, Y, D, 3.0)
+        ref = np.zeros(n)
+        oracle.op(oracle.F64, oracle.TRIAD, x, y, ref, 3.0)
+        assert_same_bits(D.to_host(), ref, "f64", "after tuning")
+
+        lens = [1000, 5000, 17, 70001, 0, 3]
+        offs, pos = [], 0
+        for k in lens:
+            offs.append((pos + 31) // 32 * 32)
+            pos = offs[-1] + k
+        pools = [torch.zeros(pos + 64, dtype=torch.float64, device="cuda") for _ in range(3)]
+        ref_pools = [torch.zeros(pos + 64, dtype=torch.float64, device="cuda") for _ in range(3)]
+        torch.cuda.synchronize()
+        mk = lambda p: [(p[0].data_ptr() + o * 8, p[1].data_ptr() + o * 8, p[2].data_ptr() + o * 8, k, 1.5)
+                        for o, k in zip(offs, lens)]
+        b, r = ts.Batch(tgt, "f64", mk(pools)), ts.Batch(tgt, "f64", mk(ref_pools))
+        bcfg, bbps = ts.autotune_batch(tgt, b, "add", reps=1)
+        assert bbps > 0 and bcfg in ts.candidates(batched=True)
+        assert ts.get_kernel_cfg("add", "f64", sum(lens), batched=True) == bcfg
+        for batch in (b, r):
+            for k in range(3):
+                batch.fill_uniform(tgt, k, 8)
+        b.op(tgt, "add")  # the batch re-planned to its own tile, the map to its tuned tile
+        r.op_plain(tgt, "add")
+        tgt.synchronize()
+        assert torch.equal(pools[2].view(torch.int64), ref_pools[2].view(torch.int64))
+        b.close(), r.close()
+
+        path = tmp_path / "tuned.json"
+        ts.tune_cache_save(str(path))
+        ts.tune_cache_clear()
+        ts.tune_cache_load(str(path))
+        assert ts.get_kernel_cfg("triad", "f64", (1 << 16) + 7, align_class=ts.ALIGN_SHARED) == cfg
+        assert ts.get_kernel_cfg("add", "f64", sum(lens), batched=True) == bcfg
+    finally:
+        ts.tune_cache_clear()
+        ts.load_default_tuning()
