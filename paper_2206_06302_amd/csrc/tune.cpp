@@ -36,14 +36,15 @@ ts_kernel_cfg default_cfg(int batched, int dtype) {
   c.vec_bytes = 16;
   c.nt_store = 1;
   if (batched) {
-    // One workgroup per tile, one 16-byte vector per lane: tiles of 16 KiB
-    // per array, the shape that measured best on the ragged batch.
+    // One workgroup of 256 lanes per tile, one 16-byte vector per lane: tiles
+    // of 4 KiB per array, the shape the tuner picks for binary64 on the
+    // ragged batch.
     const int64_t es = dtype == TS_F64 ? 8 : dtype == TS_F32 ? 4 : 2;
-    c.block = 1024;
+    c.block = 256;
     c.unroll = 1;
     c.nt_load = 1;
     c.grid_per_cu = 0;
-    c.tile_elems = 16384 / es;
+    c.tile_elems = 4096 / es;
   } else {
     c.block = 256;
     c.unroll = 4;
