@@ -457,7 +457,9 @@ TS_API int ts_future_destroy(ts_future future);
  * dst[j] = expr(x[j], y[j], q).  Nothing is contracted (-ffp-contract=off);
  * __builtin_fma(q, y, x) is a fused triad.  The expression is compiled once
  * per (expression, inputs, type, GPU architecture) and cached for the life
- * of the process.  GPU targets compile with hipRTC.  Host-CPU targets
+ * of the process.  The expression is compiled as C++ source and runs with
+ * the caller's privileges: pass only trusted text.  GPU targets compile
+ * with hipRTC.  Host-CPU targets
  * (Section 4.1) compile with the system C++ compiler (TS_HOST_CXX, default
  * "c++", run as a child process) into a shared object that their pinned
  * workers run over their blocks; they take TS_F64, TS_F32 and TS_U8, and
