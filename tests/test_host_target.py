@@ -42,6 +42,32 @@ def test_host_maps_match_oracle(ts, workers, dtype, n):
     tgt.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("offset", [0, 1, 3])
+def test_host_maps_large_blocks(ts, dtype, offset):
+    """Blocks of 1 MiB and more take the streaming-store path (32-byte
+    stores after an element-wise head, element-wise tail): still the
+    oracle's results bit for bit, in place too."""
+    tgt = ts.Target.host(_cpus(ts, 2))
+    n = (1 << 20) + 13
+    x = tsgen.uniform_array(14, 0, n, dtype)
+    y = tsgen.uniform_array(14, 1, n, dtype)
+    for op in OPS:
+        X = ts.Array.alloc(tgt, dtype, n, offset)
+        X.copy_from_host(x)
+        Y = ts.Array.alloc(tgt, dtype, n, offset)
+        Y.copy_from_host(y)
+        D = ts.Array.alloc(tgt, dtype, n, offset)
+        D.fill(0.0)
+        ts.run_op(tgt, op, X, Y, D, -1.25)
+        ref = np.zeros_like(x)
+        oracle.op(oracle.DTYPES[dtype], oracle.OPS[op], x, y if op in ("add", "triad") else None, ref, -1.25)
+        assert np.array_equal(D.to_host().view(np.uint8), ref.view(np.uint8)), op
+        ts.run_op(tgt, op, X, Y, X, -1.25)  # in place
+        assert np.array_equal(X.to_host().view(np.uint8), ref.view(np.uint8)), (op, "in place")
+    tgt.close()
+
+
 @pytest.mark.parametrize("workers", [1, 5])
 def test_host_iteration_matches_oracle_chain(ts, workers):
     """Random init, 50 iterations (the fused-triad detector length)."""
