@@ -284,11 +284,33 @@ void host_map_f32(int op, const float* x, const float* y, float* d, uint64_t lo,
   else map_fma<float>(op, x, y, d, lo, hi, q);
 }
 
+namespace {
+
+// Constant fill of a large block with 32-byte streaming stores (the owning
+// worker still touches every page first).
+template <class T>
+__attribute__((target("avx2"))) void fill_stream(T* d, uint64_t lo, uint64_t hi, T v) {
+  uint64_t j = lo;
+  for (; j < hi && (reinterpret_cast<uintptr_t>(d + j) & 31); ++j) d[j] = v;
+  constexpr uint64_t E = 32 / sizeof(T);
+  __m256i pattern;
+  T lanes[E];
+  for (uint64_t e = 0; e < E; ++e) lanes[e] = v;
+  std::memcpy(&pattern, lanes, 32);
+  for (; j + E <= hi; j += E) _mm256_stream_si256(reinterpret_cast<__m256i*>(d + j), pattern);
+  for (; j < hi; ++j) d[j] = v;
+  _mm_sfence();
+}
+
+}  // namespace
+
 void host_fill_f64(double* d, uint64_t lo, uint64_t hi, double v) {
+  if (cpu_has_fma() && (hi - lo) * sizeof(double) >= kStreamBytes) return fill_stream(d, lo, hi, v);
   for (uint64_t j = lo; j < hi; ++j) d[j] = v;
 }
 
 void host_fill_f32(float* d, uint64_t lo, uint64_t hi, float v) {
+  if (cpu_has_fma() && (hi - lo) * sizeof(float) >= kStreamBytes) return fill_stream(d, lo, hi, v);
   for (uint64_t j = lo; j < hi; ++j) d[j] = v;
 }
 

@@ -68,6 +68,23 @@ def test_host_maps_large_blocks(ts, dtype, offset):
     tgt.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_host_fill_large_blocks(ts, dtype):
+    """Large-block constant fills (streaming stores) write exactly the
+    array, at every offset, with the value's exact bits."""
+    tgt = ts.Target.host(_cpus(ts, 3))
+    n = (1 << 20) + 5
+    for off in range(4):
+        A = ts.Array.alloc(tgt, dtype, n, off)
+        A.fill(-0.0)
+        A.fill(-2.5)
+        got = A.to_host()
+        assert np.all(got == -2.5), off
+        A.fill(-0.0)
+        assert np.all(np.signbit(A.to_host())), off
+    tgt.close()
+
+
 @pytest.mark.parametrize("workers", [1, 5])
 def test_host_iteration_matches_oracle_chain(ts, workers):
     """Random init, 50 iterations (the fused-triad detector length)."""
