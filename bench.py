@@ -384,16 +384,33 @@ def transform_leg(ts, tgt, n, reps=20):
 
 
 def comparator_leg(torch, n, reps=20):
-    """The same traffic through library kernels, for context: the runtime's
-    device-to-device copy (hipMemcpyAsync behind torch's copy_) and torch's
-    elementwise b + q*c, on N binary64 elements per array, timed with events
-    on torch's current stream (where these kernels run)."""
+    """The same traffic through library kernels, for context, on N binary64
+    elements per array, timed with events on torch's current stream (where
+    these kernels run): the runtime's device-to-device copy (hipMemcpyAsync
+    behind torch's copy_), torch's elementwise b + q*c, and rocBLAS level-1
+    routines from the rocBLAS that torch bundles (same HIP runtime):
+    daxpy y = a*x + y (two reads, one write, like the triad), dcopy and dscal."""
+    import ctypes
+
     x = torch.ones(n, dtype=torch.float64, device="cuda")
     y = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
     z = torch.empty(n, dtype=torch.float64, device="cuda")
     cases = {"runtime_memcpy_d2d": (lambda: z.copy_(x), 16 * n),
              "torch_add_alpha_triad": (lambda: torch.add(x, y, alpha=3.0, out=z), 24 * n)}
     out = {}
+    blas, handle = None, ctypes.c_void_p()
+    try:
+        blas = ctypes.CDLL(os.path.join(os.path.dirname(torch.__file__), "lib", "librocblas.so"))
+        if blas.rocblas_create_handle(ctypes.byref(handle)) != 0:
+            raise RuntimeError("rocblas_create_handle failed")
+        blas.rocblas_set_stream(handle, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        alpha = ctypes.c_double(3.0)
+        px, py, pz = (ctypes.c_void_p(t.data_ptr()) for t in (x, y, z))
+        cases["rocblas_daxpy"] = (lambda: blas.rocblas_daxpy(handle, n, ctypes.byref(alpha), px, 1, py, 1), 24 * n)
+        cases["rocblas_dcopy"] = (lambda: blas.rocblas_dcopy(handle, n, px, 1, pz, 1), 16 * n)
+        cases["rocblas_dscal"] = (lambda: blas.rocblas_dscal(handle, n, ctypes.byref(alpha), pz, 1), 16 * n)
+    except (OSError, AttributeError, RuntimeError) as e:
+        out["rocblas"] = {"error": str(e)}
     for name, (fn, nbytes) in cases.items():
         fn()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
@@ -405,6 +422,8 @@ def comparator_leg(torch, n, reps=20):
         ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
         out[name] = {"best_GBps": round(nbytes / min(ms) / 1e6, 1),
                      "avg_GBps": round(nbytes / (sum(ms) / len(ms)) / 1e6, 1)}
+    if blas is not None and handle.value:
+        blas.rocblas_destroy_handle(handle)
     del x, y, z
     torch.cuda.empty_cache()
     return out
