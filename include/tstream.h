@@ -358,8 +358,9 @@ TS_API int ts_batch_info(ts_batch batch, size_t *count, uint64_t *total_elems,
                          uint64_t *tiles, int64_t *tile_elems);
 /* Re-plan with tile_elems (multiple of 8, > 0) and pin it: every map then
  * runs on this one plan, whatever its configuration's tile size.  Blocking.
- * Re-planning (this call, ts_autotune_batch) frees the old tile tables, so
- * graphs captured from the batch before it must not be launched again. */
+ * Re-planning (this call, ts_autotune_batch) frees the old tile tables;
+ * graphs captured from the batch before it are then refused at launch
+ * (TS_E_INVALID). */
 TS_API int ts_batch_set_tile(ts_batch batch, int64_t tile_elems);
 /* Apply map `op` to every instance in one launch (bulk
  * execution over all instances, Sections 3.3 and 4.2). */
@@ -386,8 +387,8 @@ TS_API int ts_batch_mismatch_count(ts_target exec, ts_batch batch, int which,
 /* Capture the four batched maps of one benchmark iteration (copy, scale,
  * add, triad) on the target's stream into an instantiated graph.  The
  * target's stream must not be the legacy default stream
- * (TS_E_UNSUPPORTED).  The batch must outlive the graph and must not be
- * re-planned while the graph is in use. */
+ * (TS_E_UNSUPPORTED).  A graph whose batch was re-planned or destroyed
+ * after the capture is refused at launch (TS_E_INVALID). */
 TS_API int ts_graph_capture_stream_iteration(ts_target target, ts_batch batch,
                                              ts_graph *out);
 /* Capture a single batched map (one graph node). */
@@ -409,7 +410,10 @@ TS_API int ts_graph_capture_arrays_iterations(ts_target target, ts_array a,
                                               int iterations, ts_graph *out);
 TS_API int ts_graph_capture_stream_iterations(ts_target target, ts_batch batch,
                                               int iterations, ts_graph *out);
-/* Enqueue the graph `repeats` times on the target's stream. */
+/* Enqueue the graph `repeats` times on the target's stream.  TS_E_INVALID
+ * (nothing enqueued) when the graph's batch was re-planned or destroyed, or
+ * one of its library-allocated arrays freed, after the capture; borrowed
+ * memory must stay valid while the graph is in use. */
 TS_API int ts_graph_launch(ts_target target, ts_graph graph, int repeats);
 TS_API int ts_graph_destroy(ts_graph graph);
 
