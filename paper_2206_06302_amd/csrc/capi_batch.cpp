@@ -183,7 +183,6 @@ int ts_batch_create(ts_target t, ts_dtype dtype, const ts_batch_desc* descs, siz
   b->device = t->device;
   b->dtype = dtype;
   b->host.resize(count);
-  const size_t es = dtype_size(dtype);
   // Placement: every instance's first element must be device memory of this
   // device (one query per array; instances are not required to be distinct
   // allocations).
@@ -217,7 +216,6 @@ int ts_batch_create(ts_target t, ts_dtype dtype, const ts_batch_desc* descs, siz
         return cleanup(fail(TS_E_PLACEMENT, "instance %zu: array is not on the target's device", i));
     }
   }
-  (void)es;
   const ts_kernel_cfg cfg = tune_table().lookup(TS_TRIAD, dtype, 0, TS_ALIGN_16, 1);
   uint64_t total = 0;
   for (size_t i = 0; i < count; ++i) total += descs[i].len;
