@@ -35,6 +35,7 @@ def main() -> None:
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--batched", type=int, default=4096, help="instances of the batched tuning batch (0: skip)")
     ap.add_argument("--batched-seed", type=int, default=5)
+    ap.add_argument("--batched-dtypes", default="f64", help="storage types of the batched tuning, comma separated")
     a = ap.parse_args()
 
     import torch
@@ -72,28 +73,32 @@ def main() -> None:
         import tsgen
         lens = tsgen.batched_lengths(a.batched_seed, a.batched)
         qs = tsgen.batched_scalars(a.batched_seed, a.batched)
-        offs, pos = [], 0
-        for n in lens:
-            start = (pos + 31) // 32 * 32
-            offs.append(start)
-            pos = start + int(n)
-        pools = [torch.empty(pos + 32, dtype=torch.float64, device="cuda") for _ in range(3)]
-        torch.cuda.synchronize()
-        descs = [(pools[0].data_ptr() + o * 8, pools[1].data_ptr() + o * 8, pools[2].data_ptr() + o * 8, int(n),
-                  float(q)) for o, n, q in zip(offs, lens, qs)]
-        batch = ts.Batch(tgt, "f64", descs)
-        for k in range(3):
-            batch.fill_uniform(tgt, k, a.batched_seed)
-        bucket = int(batch.info()["total_elems"]).bit_length() - 1
-        for op in ops:
-            if (op, "f64", bucket, 0, 1) in done:
-                continue
-            cfg, bps = ts.autotune_batch(tgt, batch, op, reps=a.reps)
-            print(f"[{time.time()-t0:7.1f}s] batched f64 {op:5s} {batch.info()['total_elems']} elems: "
-                  f"{bps/1e9:8.1f} GB/s  {cfg}", flush=True)
-        batch.close()
-        del pools
-        torch.cuda.empty_cache()
+        for dtype in a.batched_dtypes.split(","):
+            es = ts.ELEM_SIZE[dtype]
+            align = 256 // es  # every instance starts on a 256-byte boundary
+            offs, pos = [], 0
+            for n in lens:
+                start = (pos + align - 1) // align * align
+                offs.append(start)
+                pos = start + int(n)
+            pools = [torch.empty(pos + align, dtype=ts.TORCH_DTYPES[dtype], device="cuda") for _ in range(3)]
+            torch.cuda.synchronize()
+            descs = [(pools[0].data_ptr() + o * es, pools[1].data_ptr() + o * es, pools[2].data_ptr() + o * es,
+                      int(n), float(q)) for o, n, q in zip(offs, lens, qs)]
+            batch = ts.Batch(tgt, dtype, descs)
+            for k in range(3):
+                batch.fill_uniform(tgt, k, a.batched_seed)
+            bucket = int(batch.info()["total_elems"]).bit_length() - 1
+            for op in ops:
+                if (op, dtype, bucket, 0, 1) in done:
+                    continue
+                cfg, bps = ts.autotune_batch(tgt, batch, op, reps=a.reps)
+                print(f"[{time.time()-t0:7.1f}s] batched {dtype} {op:5s} {batch.info()['total_elems']} elems: "
+                      f"{bps/1e9:8.1f} GB/s  {cfg}", flush=True)
+            ts.tune_cache_save(a.out)
+            batch.close()
+            del pools
+            torch.cuda.empty_cache()
     ts.tune_cache_save(a.out)
     print(f"wrote {a.out} after {time.time()-t0:.1f}s", flush=True)
     tgt.close()
