@@ -634,8 +634,11 @@ def main():
                 result["batched"]["triad_best_GBps"] / tri["best_GBps"], 3)
     if not a.no_cpu:
         log("cpu baseline leg (oracle)")
-        result["cpu_baseline"] = cpu_baseline_leg(a.n)
-        if not a.quick:
+        try:
+            result["cpu_baseline"] = cpu_baseline_leg(a.n)
+        except Exception as e:  # the baseline must not hide the headline
+            result["cpu_baseline"] = {"error": f"{type(e).__name__}: {e}", "kind": "oracle"}
+        if not a.quick and "value" in result["cpu_baseline"]:
             log("host target leg")
             try:
                 result["host_target"] = host_target_leg(ts, a.n, result["cpu_baseline"]["cores"])
