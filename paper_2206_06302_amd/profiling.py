@@ -6,9 +6,9 @@
 `run` starts four rocprofv3 runs, each a process of its own with the program
 directly after `--`, from /tmp with TMPDIR=/tmp:
 
-  headline trace   --kernel-trace --stats of bench.py --quick --no-cpu --steps 20
-  batched trace    --kernel-trace --stats of bench.py --no-cpu --legs batched
-  fetch counters   --pmc FETCH_SIZE of bench.py --no-cpu --legs batched --steps 3
+  headline trace   --kernel-trace --stats of bench.py --quick --no-cpu --warmup 1 --steps 20
+  batched trace    --kernel-trace --stats of bench.py --no-cpu --legs batched --warmup 1 --steps 20
+  fetch counters   --pmc FETCH_SIZE of bench.py --no-cpu --legs batched --warmup 1 --steps 3
   write counters   --pmc WRITE_SIZE of the same command
 
 `summarize` turns the raw CSV files into four short markdown summaries: the
@@ -74,19 +74,19 @@ def runs(raw: str) -> list[tuple[str, list[str], str]]:
     return [
         ("headline trace", ["rocprofv3", "--kernel-trace", "--stats", "--output-format", "csv", "-d",
                             os.path.join(raw, "trace_headline"), "-o", "run", "--",
-                            *_bench("--quick", "--no-cpu", "--steps", "20")],
+                            *_bench("--quick", "--no-cpu", "--warmup", "1", "--steps", "20")],
          os.path.join(raw, "trace_headline.json")),
         ("batched trace", ["rocprofv3", "--kernel-trace", "--stats", "--output-format", "csv", "-d",
                            os.path.join(raw, "trace_batched"), "-o", "run", "--",
-                           *_bench("--no-cpu", "--legs", "batched")],
+                           *_bench("--no-cpu", "--legs", "batched", "--warmup", "1", "--steps", "20")],
          os.path.join(raw, "trace_batched.json")),
         ("fetch counters", ["rocprofv3", "--pmc", "FETCH_SIZE", "--output-format", "csv", "-d",
                             os.path.join(raw, "pmc_fetch"), "-o", "run", "--",
-                            *_bench("--no-cpu", "--legs", "batched", "--steps", "3")],
+                            *_bench("--no-cpu", "--legs", "batched", "--warmup", "1", "--steps", "3")],
          os.path.join(raw, "pmc_fetch.json")),
         ("write counters", ["rocprofv3", "--pmc", "WRITE_SIZE", "--output-format", "csv", "-d",
                             os.path.join(raw, "pmc_write"), "-o", "run", "--",
-                            *_bench("--no-cpu", "--legs", "batched", "--steps", "3")],
+                            *_bench("--no-cpu", "--legs", "batched", "--warmup", "1", "--steps", "3")],
          os.path.join(raw, "pmc_write.json")),
     ]
 
