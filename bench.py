@@ -6,7 +6,7 @@ each) placed on the GPU by the library's allocator, initialised on the device
 to a = 1, b = 2, c = 0, scalar q = 3.  One step = one iteration of the
 generic STREAM benchmark (Section 5, Listing 4 of the paper): copy c = a,
 scale b = q*c, add c = a + b, triad a = b + q*c, four launches in that order.
-W untimed warm-up steps (default 10), then exactly K timed steps (default 100) bracketed by device
+W untimed warm-up steps (default 10), then exactly K timed steps (default 20) bracketed by device
 synchronisation.  Every launch is bracketed by events on the target's stream,
 giving per-kernel best/average times; bytes follow the STREAM convention
 (copy and scale move 2 arrays, add and triad 3; GB = 1e9 B).
@@ -535,7 +535,7 @@ def metric_records(result: dict) -> list[dict]:
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=1 << 27)
     ap.add_argument("--quick", action="store_true", help="headline leg only")
