@@ -13,12 +13,12 @@ using namespace tsapi;
 
 namespace tsapi {
 
+// Notifies while holding the lock: ts_future_destroy may free the future as
+// soon as it sees `ready`, so the callback must not touch it after unlocking.
 void future_ready_cb(void* p) {
   ts_future_s* f = static_cast<ts_future_s*>(p);
-  {
-    std::lock_guard<std::mutex> lk(f->mu);
-    f->ready = true;
-  }
+  std::lock_guard<std::mutex> lk(f->mu);
+  f->ready = true;
   f->cv.notify_all();
 }
 
