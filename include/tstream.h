@@ -353,6 +353,8 @@ typedef struct {
 TS_API int ts_batch_create(ts_target target, ts_dtype dtype,
                            const ts_batch_desc *host_descs, size_t count,
                            ts_batch *out);
+/* Waits for the work enqueued on the batch's device, then frees its tile
+ * tables. */
 TS_API int ts_batch_destroy(ts_batch batch);
 TS_API int ts_batch_info(ts_batch batch, size_t *count, uint64_t *total_elems,
                          uint64_t *tiles, int64_t *tile_elems);
@@ -415,6 +417,7 @@ TS_API int ts_graph_capture_stream_iterations(ts_target target, ts_batch batch,
  * one of its library-allocated arrays freed, after the capture; borrowed
  * memory must stay valid while the graph is in use. */
 TS_API int ts_graph_launch(ts_target target, ts_graph graph, int repeats);
+/* Waits for the work enqueued on the graph's device, then releases it. */
 TS_API int ts_graph_destroy(ts_graph graph);
 
 /* ------------------------------------------------------------------------ */
@@ -474,8 +477,8 @@ TS_API int ts_future_destroy(ts_future future);
  * a host target.  ts_transform_apply follows the rules of the algorithm
  * calls (count = n of x; shapes, types, placement, aliasing) and is
  * asynchronous on the executor's stream (host targets: complete on
- * return); work using a transform must have finished before it is
- * destroyed. */
+ * return).  ts_transform_destroy first waits for the work enqueued on its
+ * device, so launches still in flight finish before the code is unloaded. */
 TS_API int ts_transform_create(ts_target target, const char *expr, int n_inputs,
                                ts_dtype dtype, ts_transform *out);
 TS_API int ts_transform_apply(ts_target exec, ts_transform transform,

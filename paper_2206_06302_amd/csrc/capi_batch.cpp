@@ -479,6 +479,7 @@ int ts_graph_destroy(ts_graph g) {
   if (!g) return TS_OK;
   if (!ok_graph(g)) return fail(TS_E_INVALID, "invalid graph handle");
   (void)use_device(g->device);
+  (void)hipDeviceSynchronize();  // launches of it may still run on any stream of the device
   (void)hipGraphExecDestroy(g->exec);
   (void)hipGraphDestroy(g->graph);
   g->magic = kDead;

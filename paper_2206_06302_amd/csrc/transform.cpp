@@ -352,6 +352,7 @@ int ts_transform_destroy(ts_transform x) {
   if (x->magic != kTransformMagic) return api_fail(TS_E_INVALID, "invalid transform handle");
   if (x->module) {  // host transforms keep their shared object cached for the process
     (void)hipSetDevice(x->device);
+    (void)hipDeviceSynchronize();  // launches of it may still run on any stream of the device
     (void)hipModuleUnload(x->module);
   }
   x->magic = 0xdeadbeefu;
