@@ -252,7 +252,8 @@ typedef struct {
 } ts_checksum_out;
 
 /* Binary64 reductions over the whole array, in a fixed two-pass tree whose
- * shape depends only on n (so results are reproducible run to run).
+ * shape depends only on n and on the array's address modulo 16 bytes (so
+ * results are reproducible run to run for an array).
  * Blocking.  The sums differ from a sequential sum only by rounding order. */
 TS_API int ts_checksum(ts_target exec, ts_array x, double expected,
                        ts_checksum_out *out);

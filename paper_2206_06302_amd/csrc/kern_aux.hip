@@ -133,11 +133,36 @@ __device__ CsPart block_reduce(CsPart v) {
   return CsPart{s_sum[0], s_abs[0], s_max[0], s_cnt[0]};
 }
 
-// Pass 1: workgroup g reduces the contiguous range [g*n/P, (g+1)*n/P).
+// Split the range [lo, hi) of `x` into an element-wise head up to the next
+// 16-byte boundary, whole 16-byte vectors, and an element-wise tail (both
+// shorter than one vector).  `x` is aligned to its element size.
+template <class T>
+struct VecRange {
+  uint64_t head, v0, nvec, t0;  // head elements at lo; vectors from v0; tail from t0 to hi
+};
+
+template <class T>
+__device__ __forceinline__ VecRange<T> vec_range(const T* x, uint64_t lo, uint64_t hi) {
+  constexpr uint64_t E = 16 / sizeof(T);
+  const uint64_t mis = reinterpret_cast<uintptr_t>(x + lo) % 16;
+  uint64_t head = ((16 - mis) % 16) / sizeof(T);
+  if (head > hi - lo) head = hi - lo;
+  const uint64_t v0 = lo + head;
+  const uint64_t nvec = (hi - v0) / E;
+  return VecRange<T>{head, v0, nvec, v0 + nvec * E};
+}
+
+// Pass 1: workgroup g reduces the contiguous range [g*n/P, (g+1)*n/P): its
+// head and tail elements one per lane, the 16-byte vectors between them
+// with nontemporal loads, four in flight per lane.  Each lane folds its
+// elements in ascending order, so the tree depends only on n and on the
+// array's address modulo 16 bytes.
 template <int DT>
 __global__ __launch_bounds__(256) void checksum_pass1(const void* xv, uint64_t n, double expected,
                                                       CsPart* parts, uint32_t nparts) {
   using T = typename Fmt<DT>::T;
+  using R = typename Raw<16>::type;
+  constexpr uint32_t E = 16 / sizeof(T);
   const T* x = static_cast<const T*>(xv);
   const uint64_t lo = static_cast<uint64_t>(blockIdx.x) * n / nparts;
   const uint64_t hi = static_cast<uint64_t>(blockIdx.x + 1) * n / nparts;
@@ -149,15 +174,23 @@ __global__ __launch_bounds__(256) void checksum_pass1(const void* xv, uint64_t n
     acc.maxdev = fmax(acc.maxdev, dv);
     acc.mism += differs(v, expected) ? 1ull : 0ull;
   };
-  // Each lane folds its elements in ascending order; four loads are issued
-  // before they are folded, to keep more of them in flight.
-  uint64_t j = lo + threadIdx.x;
-  for (; j + 3 * kReduceBlock < hi; j += 4 * kReduceBlock) {
-    const double v0 = to_f64<DT>(x[j]), v1 = to_f64<DT>(x[j + kReduceBlock]);
-    const double v2 = to_f64<DT>(x[j + 2 * kReduceBlock]), v3 = to_f64<DT>(x[j + 3 * kReduceBlock]);
-    add(v0), add(v1), add(v2), add(v3);
+  auto fold = [&](R r) {
+    const Splat<T> v = __builtin_bit_cast(Splat<T>, r);
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) add(to_f64<DT>(v.e[e]));
+  };
+  const VecRange<T> vr = vec_range(x, lo, hi);
+  if (threadIdx.x < vr.head) add(to_f64<DT>(x[lo + threadIdx.x]));
+  const R* xr = reinterpret_cast<const R*>(x + vr.v0);
+  uint64_t k = threadIdx.x;
+  for (; k + 3 * kReduceBlock < vr.nvec; k += 4 * kReduceBlock) {
+    const R r0 = __builtin_nontemporal_load(xr + k), r1 = __builtin_nontemporal_load(xr + k + kReduceBlock);
+    const R r2 = __builtin_nontemporal_load(xr + k + 2 * kReduceBlock);
+    const R r3 = __builtin_nontemporal_load(xr + k + 3 * kReduceBlock);
+    fold(r0), fold(r1), fold(r2), fold(r3);
   }
-  for (; j < hi; j += kReduceBlock) add(to_f64<DT>(x[j]));
+  for (; k < vr.nvec; k += kReduceBlock) fold(__builtin_nontemporal_load(xr + k));
+  if (threadIdx.x < hi - vr.t0) add(to_f64<DT>(x[vr.t0 + threadIdx.x]));
   const CsPart r = block_reduce(acc);
   if (threadIdx.x == 0) parts[blockIdx.x] = r;
 }
@@ -176,10 +209,16 @@ __global__ __launch_bounds__(256) void reduce_pass2(const CsPart* parts, uint32_
   if (threadIdx.x == 0) *out = r;
 }
 
+// Count of elements whose bits differ between x and r (two NaNs agree), over
+// the same ranges as checksum_pass1.  When x and r share their address
+// modulo 16 bytes the vectors of both are read 16 bytes at a time;
+// otherwise every element is read alone.
 template <int DT>
 __global__ __launch_bounds__(256) void mismatch_pass1(const void* xv, const void* rv, uint64_t n,
                                                       CsPart* parts, uint32_t nparts) {
   using T = typename Fmt<DT>::T;
+  using R = typename Raw<16>::type;
+  constexpr uint32_t E = 16 / sizeof(T);
   const T* x = static_cast<const T*>(xv);
   const T* r = static_cast<const T*>(rv);
   const uint64_t lo = static_cast<uint64_t>(blockIdx.x) * n / nparts;
@@ -193,12 +232,33 @@ __global__ __launch_bounds__(256) void mismatch_pass1(const void* xv, const void
     if (diff && __builtin_isnan(to_f64<DT>(a)) && __builtin_isnan(to_f64<DT>(b))) diff = false;
     acc.mism += diff ? 1ull : 0ull;
   };
-  uint64_t j = lo + threadIdx.x;
-  for (; j + kReduceBlock < hi; j += 2 * kReduceBlock) {  // two pairs of loads in flight per lane
-    const T a0 = x[j], b0 = r[j], a1 = x[j + kReduceBlock], b1 = r[j + kReduceBlock];
-    count(a0, b0), count(a1, b1);
+  auto fold = [&](R ra, R rb) {
+    const Splat<T> va = __builtin_bit_cast(Splat<T>, ra), vb = __builtin_bit_cast(Splat<T>, rb);
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) count(va.e[e], vb.e[e]);
+  };
+  if ((reinterpret_cast<uintptr_t>(x) - reinterpret_cast<uintptr_t>(r)) % 16 == 0) {
+    const VecRange<T> vr = vec_range(x, lo, hi);
+    if (threadIdx.x < vr.head) count(x[lo + threadIdx.x], r[lo + threadIdx.x]);
+    const R* xr = reinterpret_cast<const R*>(x + vr.v0);
+    const R* rr = reinterpret_cast<const R*>(r + vr.v0);
+    uint64_t k = threadIdx.x;
+    for (; k + kReduceBlock < vr.nvec; k += 2 * kReduceBlock) {  // two pairs of vectors in flight
+      const R a0 = __builtin_nontemporal_load(xr + k), b0 = __builtin_nontemporal_load(rr + k);
+      const R a1 = __builtin_nontemporal_load(xr + k + kReduceBlock);
+      const R b1 = __builtin_nontemporal_load(rr + k + kReduceBlock);
+      fold(a0, b0), fold(a1, b1);
+    }
+    for (; k < vr.nvec; k += kReduceBlock) fold(__builtin_nontemporal_load(xr + k), __builtin_nontemporal_load(rr + k));
+    if (threadIdx.x < hi - vr.t0) count(x[vr.t0 + threadIdx.x], r[vr.t0 + threadIdx.x]);
+  } else {
+    uint64_t j = lo + threadIdx.x;
+    for (; j + kReduceBlock < hi; j += 2 * kReduceBlock) {  // two pairs of loads in flight per lane
+      const T a0 = x[j], b0 = r[j], a1 = x[j + kReduceBlock], b1 = r[j + kReduceBlock];
+      count(a0, b0), count(a1, b1);
+    }
+    for (; j < hi; j += kReduceBlock) count(x[j], r[j]);
   }
-  for (; j < hi; j += kReduceBlock) count(x[j], r[j]);
   const CsPart res = block_reduce(acc);
   if (threadIdx.x == 0) parts[blockIdx.x] = res;
 }

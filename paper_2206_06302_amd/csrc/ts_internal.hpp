@@ -50,7 +50,8 @@ struct CsPart {
   unsigned long long mism;
 };
 
-// Fixed reduction shape: depends only on n, never on tuning.
+// Fixed reduction shape: depends only on n (and the address modulo 16
+// bytes), never on tuning.
 constexpr uint32_t kReduceBlock = 256;
 constexpr uint32_t kReduceMaxParts = 8192;
 uint32_t reduce_parts(uint64_t n);

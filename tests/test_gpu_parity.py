@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import tsgen
-from gpu_util import assert_same_bits, device_array, empty_array, say
+from gpu_util import UINT as UINT_OF, assert_same_bits, device_array, empty_array, say
 
 pytestmark = pytest.mark.gpu
 
@@ -241,7 +241,7 @@ def test_checksum_against_oracle(env, dtype):
     assert abs(cs["abs_dev_sum"] - ref.abs_dev_sum) <= 2 * n * 2.0 ** -53 * float(dev.sum())
     assert cs["max_abs_dev"] == ref.max_abs_dev
     assert cs["mismatches"] == ref.mismatches
-    # reproducible: the reduction tree depends only on n
+    # reproducible: the reduction tree depends only on n and the address
     assert ts.checksum(tgt, X, expected) == cs
 
 
@@ -256,6 +256,62 @@ def test_mismatch_count(env):
     R = device_array(ts, torch, tgt, r, "f64", 1)
     assert ts.mismatch_count(tgt, X, R) == 4
     assert ts.mismatch_count(tgt, X, X) == 0
+
+
+ELEMS_PER_16B = {"f64": 2, "f32": 4, "bf16": 8, "f16": 8}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+def test_checksum_and_mismatch_layouts(env, dtype):
+    """The reductions read each part as a head up to a 16-byte boundary,
+    16-byte vectors and a tail: every element offset within 16 bytes, sizes
+    below one vector, around one part (2048 elements) and across several
+    parts give the oracle's counts and maximum exactly and its sums within
+    the summation bound; the mismatch count also takes operands whose
+    offsets differ modulo 16 bytes (element-wise path)."""
+    ts, torch, tgt = env
+    E = ELEMS_PER_16B[dtype]
+    odt = oracle.DTYPES[dtype]
+    for n in (1, E - 1, E + 1, 2047, 2049, 3 * 2048 + 7, 70001):
+        if n < 1:
+            continue
+        x = tsgen.uniform_array(11, n, n, dtype)
+        w = oracle.widen_f64(odt, x)
+        expected = float(w[n // 2])
+        r = x.copy()
+        plant = sorted({0, n // 3, n - 1})
+        r.view(UINT_OF[dtype])[plant] ^= 1  # flip the lowest bit
+        want_mm = oracle.mismatch_count(odt, x, r)
+        assert want_mm == len(plant)
+        ref = oracle.checksum(odt, x, expected)
+        for off in range(E):
+            say(f"[checksum/mismatch {dtype} n={n} offset={off}]")
+            X = device_array(ts, torch, tgt, x, dtype, off)
+            cs = ts.checksum(tgt, X, expected)
+            assert cs["mismatches"] == ref.mismatches
+            assert cs["max_abs_dev"] == ref.max_abs_dev
+            assert abs(cs["sum"] - ref.sum) <= 2 * n * 2.0 ** -53 * float(np.abs(w).sum())
+            assert abs(cs["abs_dev_sum"] - ref.abs_dev_sum) <= 2 * n * 2.0 ** -53 * float(np.abs(w - expected).sum())
+            for roff in sorted({off, (off + 1) % E, 0}):
+                R = device_array(ts, torch, tgt, r, dtype, roff)
+                assert ts.mismatch_count(tgt, X, R) == want_mm, (n, off, roff)
+                assert ts.mismatch_count(tgt, R, R) == 0
+
+
+def test_mismatch_count_nan_payloads(env):
+    """Two NaNs agree whatever their payloads; a NaN against a number differs."""
+    ts, torch, tgt = env
+    n = 5000
+    x = tsgen.uniform_array(12, 0, n, "f64")
+    r = x.copy()
+    xb, rb = x.view(np.uint64), r.view(np.uint64)
+    xb[[3, 2500, 4999]] = 0x7ff8000000000001
+    rb[[3, 2500, 4999]] = 0xfff8000000000abc
+    rb[17] = 0x7ff8000000000000
+    X = device_array(ts, torch, tgt, x, "f64")
+    R = device_array(ts, torch, tgt, r, "f64")
+    assert oracle.mismatch_count(oracle.F64, x, r) == 1
+    assert ts.mismatch_count(tgt, X, R) == 1
 
 
 def test_time_op_and_events(env):
@@ -371,3 +427,21 @@ def test_futures_become_ready_after_the_work(env):
         f.close()
     tgt.synchronize()
     assert ts.checksum(tgt, A, 15.0 ** 9)["mismatches"] == 0
+
+
+def test_futures_destroyed_as_their_callbacks_run(env):
+    """Futures destroyed right after they are made, over short work, so that
+    destruction meets the stream callback at every point of its run: each
+    destroy returns once the callback is done with the future."""
+    ts, torch, tgt = env
+    n = 1 << 12
+    A, B, C = (empty_array(ts, torch, tgt, n, "f64") for _ in range(3))
+    A.fill(1.0), B.fill(2.0), C.fill(0.0)
+    for k in range(2000):
+        ts.run_op(tgt, "copy", A, None, C, 3.0)
+        f = tgt.async_()
+        if k % 3 == 0:
+            f.wait()
+        f.close()
+    tgt.synchronize()
+    assert ts.checksum(tgt, C, 1.0)["mismatches"] == 0
