@@ -263,38 +263,97 @@ __global__ __launch_bounds__(256) void mismatch_pass1(const void* xv, const void
   if (threadIdx.x == 0) parts[blockIdx.x] = res;
 }
 
-template <int DT>
-__global__ __launch_bounds__(256) void batch_fill_kernel(const BatchTile* tiles, uint64_t ntiles,
-                                                         int which, int uniform, double value,
-                                                         uint64_t seed) {
+// Whole 16-byte vectors [vs, ve) inside the tile [start, end) of an array
+// whose first `h` elements come before its first 16-byte boundary.
+__device__ __forceinline__ void tile_vectors(uint64_t start, uint64_t end, uint64_t h, uint64_t V,
+                                             uint64_t& vs, uint64_t& ve) {
+  vs = start < h ? h : h + (start - h + V - 1) / V * V;
+  if (vs > end) vs = end;
+  ve = end < h ? vs : h + (end - h) / V * V;
+  if (ve < vs) ve = vs;
+}
+
+template <class T>
+__device__ __forceinline__ uint64_t head_of(const T* p) {
+  return ((16 - reinterpret_cast<uintptr_t>(p) % 16) % 16) / sizeof(T);
+}
+
+// Tiles [c, c + per_wg) of the table go to workgroup c / per_wg (striding
+// by the grid over any beyond it): fewer, longer workgroups than one per
+// tile, which the hardware dispatches at a limited rate.
+#define TS_FOR_TILES(t)                                                                           \
+  for (uint64_t c_ = static_cast<uint64_t>(blockIdx.x) * per_wg; c_ < ntiles;                    \
+       c_ += static_cast<uint64_t>(gridDim.x) * per_wg)                                           \
+    for (uint64_t t = c_, e_ = ntiles - c_ < per_wg ? ntiles : c_ + per_wg; t < e_; ++t)
+
+// Fill one array of every instance (which: 0 a, 1 b, 2 c), tile by tile:
+// elements before and after the tile's whole 16-byte vectors one per lane,
+// the vectors with nontemporal stores.  Element j of instance i gets the
+// constant (UNIFORM false), or uniform draw j + 1 of stream 16 + 3i + which.
+// The tile table is read-only here, so its records are scalar loads.
+template <int DT, bool UNIFORM>
+__global__ __launch_bounds__(256) void batch_fill_kernel(const BatchTile* __restrict__ tiles,
+                                                         uint64_t ntiles, uint32_t per_wg, int which,
+                                                         double value, uint64_t seed) {
   using T = typename Fmt<DT>::T;
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  using R = typename Raw<16>::type;
+  constexpr uint64_t V = 16 / sizeof(T);
+  TS_FOR_TILES(t) {
     const BatchTile tl = tiles[t];
     T* d = static_cast<T*>(const_cast<void*>(which == 0 ? tl.a : which == 1 ? tl.b : tl.c));
     const uint64_t state0 = seed ^ ((16ull + 3ull * tl.inst + static_cast<uint64_t>(which)) << 48);
     const T cv = from_f64<DT>(value);
+    auto at = [&](uint64_t j) {
+      if constexpr (UNIFORM) return from_f64<DT>(uniform_pm1(state0, j + 1));
+      else return cv;
+    };
     const uint64_t end = tl.start + tl.count;
-    for (uint64_t j = tl.start + threadIdx.x; j < end; j += blockDim.x)
-      d[j] = uniform ? from_f64<DT>(uniform_pm1(state0, j + 1)) : cv;
+    uint64_t vs, ve;
+    tile_vectors(tl.start, end, head_of(d), V, vs, ve);
+    for (uint64_t j = tl.start + threadIdx.x; j < vs; j += blockDim.x) d[j] = at(j);
+    for (uint64_t j = ve + threadIdx.x; j < end; j += blockDim.x) d[j] = at(j);
+    R* dv = reinterpret_cast<R*>(d + vs);
+    const uint64_t nvec = (ve - vs) / V;
+    for (uint64_t k = threadIdx.x; k < nvec; k += blockDim.x) {
+      Splat<T> v;
+#pragma unroll
+      for (uint64_t e = 0; e < V; ++e) v.e[e] = at(vs + k * V + e);
+      __builtin_nontemporal_store(__builtin_bit_cast(R, v), dv + k);
+    }
   }
 }
 
+// Per-instance count of elements of one array whose binary64 value differs
+// in bits from the instance's expected value, read like batch_fill_kernel
+// writes.  Each lane counts its own elements of a tile and adds its count
+// to the instance's counter only when it found a mismatch (integer adds, so
+// the totals do not depend on their order).
 template <int DT>
-__global__ __launch_bounds__(256) void batch_mismatch_kernel(const BatchTile* tiles, uint64_t ntiles,
-                                                             int which, const double* expected,
+__global__ __launch_bounds__(256) void batch_mismatch_kernel(const BatchTile* __restrict__ tiles,
+                                                             uint64_t ntiles, uint32_t per_wg, int which,
+                                                             const double* __restrict__ expected,
                                                              unsigned long long* counts) {
   using T = typename Fmt<DT>::T;
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  using R = typename Raw<16>::type;
+  constexpr uint64_t V = 16 / sizeof(T);
+  TS_FOR_TILES(t) {
     const BatchTile tl = tiles[t];
     const T* x = static_cast<const T*>(which == 0 ? tl.a : which == 1 ? tl.b : tl.c);
     const double e = expected[tl.inst];
     const uint64_t end = tl.start + tl.count;
-    CsPart acc{0.0, 0.0, 0.0, 0ull};
-    for (uint64_t j = tl.start + threadIdx.x; j < end; j += kReduceBlock)
-      acc.mism += differs(to_f64<DT>(x[j]), e) ? 1ull : 0ull;
-    const CsPart r = block_reduce(acc);
-    if (threadIdx.x == 0 && r.mism) atomicAdd(&counts[tl.inst], r.mism);
-    __syncthreads();  // the next tile reuses the shared reduction arrays
+    uint64_t vs, ve;
+    tile_vectors(tl.start, end, head_of(x), V, vs, ve);
+    unsigned long long c = 0;
+    for (uint64_t j = tl.start + threadIdx.x; j < vs; j += blockDim.x) c += differs(to_f64<DT>(x[j]), e) ? 1 : 0;
+    for (uint64_t j = ve + threadIdx.x; j < end; j += blockDim.x) c += differs(to_f64<DT>(x[j]), e) ? 1 : 0;
+    const R* xv = reinterpret_cast<const R*>(x + vs);
+    const uint64_t nvec = (ve - vs) / V;
+    for (uint64_t k = threadIdx.x; k < nvec; k += blockDim.x) {
+      const Splat<T> v = __builtin_bit_cast(Splat<T>, __builtin_nontemporal_load(xv + k));
+#pragma unroll
+      for (uint64_t i = 0; i < V; ++i) c += differs(to_f64<DT>(v.e[i]), e) ? 1 : 0;
+    }
+    if (c) atomicAdd(&counts[tl.inst], c);
   }
 }
 
@@ -315,6 +374,17 @@ uint32_t reduce_parts(uint64_t n) {
   const uint64_t p = (n + 2047) / 2048;
   return static_cast<uint32_t>(p < 1 ? 1 : (p > kReduceMaxParts ? kReduceMaxParts : p));
 }
+
+// The batched fill for storage format dt, constant (U false) or uniform.
+#define TS_BY_FORMAT_U(dt, U, ...)                                                             \
+  switch (dt) {                                                                                \
+    case DT_F64: hipLaunchKernelGGL((batch_fill_kernel<DT_F64, U>), __VA_ARGS__); break;       \
+    case DT_F32: hipLaunchKernelGGL((batch_fill_kernel<DT_F32, U>), __VA_ARGS__); break;       \
+    case DT_BF16: hipLaunchKernelGGL((batch_fill_kernel<DT_BF16, U>), __VA_ARGS__); break;     \
+    case DT_F16: hipLaunchKernelGGL((batch_fill_kernel<DT_F16, U>), __VA_ARGS__); break;       \
+    default: return hipErrorInvalidValue;                                                      \
+  }                                                                                            \
+  return hipGetLastError();
 
 #define TS_BY_FORMAT(dt, KERNEL, ...)                                                          \
   switch (dt) {                                                                                \
@@ -389,16 +459,18 @@ hipError_t launch_mismatch(int dt, const void* x, const void* ref, uint64_t n, v
   return hipGetLastError();
 }
 
-hipError_t launch_batch_fill(int dt, const BatchTile* tiles, uint64_t ntiles, int which, int uniform,
-                             double value, uint64_t seed, uint32_t grid, hipStream_t s) {
-  TS_BY_FORMAT(dt, batch_fill_kernel, dim3(grid), dim3(256), 0, s, tiles, ntiles, which, uniform, value,
-               seed)
+hipError_t launch_batch_fill(int dt, const BatchTile* tiles, uint64_t ntiles, uint32_t per_wg, int which,
+                             int uniform, double value, uint64_t seed, uint32_t grid, hipStream_t s) {
+  if (uniform) {
+    TS_BY_FORMAT_U(dt, true, dim3(grid), dim3(256), 0, s, tiles, ntiles, per_wg, which, value, seed)
+  }
+  TS_BY_FORMAT_U(dt, false, dim3(grid), dim3(256), 0, s, tiles, ntiles, per_wg, which, value, seed)
 }
 
-hipError_t launch_batch_mismatch(int dt, const BatchTile* tiles, uint64_t ntiles, int which,
+hipError_t launch_batch_mismatch(int dt, const BatchTile* tiles, uint64_t ntiles, uint32_t per_wg, int which,
                                  const double* expected, unsigned long long* counts, uint32_t grid,
                                  hipStream_t s) {
-  TS_BY_FORMAT(dt, batch_mismatch_kernel, dim3(grid), dim3(kReduceBlock), 0, s, tiles, ntiles, which,
+  TS_BY_FORMAT(dt, batch_mismatch_kernel, dim3(grid), dim3(kReduceBlock), 0, s, tiles, ntiles, per_wg, which,
                expected, counts)
 }
 

@@ -68,11 +68,13 @@ hipError_t launch_checksum(int dt, const void* x, uint64_t n, double expected, v
 // Leaves the count in the `mism` field of the part after kReduceMaxParts.
 hipError_t launch_mismatch(int dt, const void* x, const void* ref, uint64_t n, void* scratch,
                            hipStream_t s);
-hipError_t launch_batch_fill(int dt, const BatchTile* tiles, uint64_t ntiles, int which, int uniform,
-                             double value, uint64_t seed, uint32_t grid, hipStream_t s);
+// Batched fills and mismatch counts give `per_wg` consecutive tiles to each
+// workgroup of `grid` (which strides over any tiles beyond).
+hipError_t launch_batch_fill(int dt, const BatchTile* tiles, uint64_t ntiles, uint32_t per_wg, int which,
+                             int uniform, double value, uint64_t seed, uint32_t grid, hipStream_t s);
 // counts: device array of one unsigned long long per instance, zeroed by the
 // caller's fill kernel (launch_zero_u64).
-hipError_t launch_batch_mismatch(int dt, const BatchTile* tiles, uint64_t ntiles, int which,
+hipError_t launch_batch_mismatch(int dt, const BatchTile* tiles, uint64_t ntiles, uint32_t per_wg, int which,
                                  const double* expected, unsigned long long* counts, uint32_t grid,
                                  hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, uint64_t n, hipStream_t s);

@@ -240,6 +240,54 @@ def test_multi_iteration_batched_graph(env):
     batch.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+def test_batched_fill_and_count_over_tiles(env, dtype):
+    """Fills and mismatch counts read and write each tile as an element-wise
+    head, 16-byte vectors and a tail: with tiles that start off the vector
+    grid, every misalignment of each array and instances shorter than one
+    vector, the fills give the generator's bits, nothing outside the
+    instances is written, and the counts equal numpy's."""
+    ts, torch, tgt = env
+    rng = np.random.default_rng(21)
+    es = ts.ELEM_SIZE[dtype]
+    lens = [1, 2, 3, 5, 7, 8, 9, 15, 17, 100, 513, 1000, 4099, 20001]
+    mis = [tuple(int(v) for v in rng.integers(0, 16 // es, 3)) for _ in lens]
+    for tile in (8, 24, 512, 4096):
+        say(f"[batched fill/count {dtype} tile {tile}]")
+        pool = Pool(ts, torch, lens, dtype, mis)
+        batch = ts.Batch(tgt, dtype, pool.descs([1.0] * len(lens)))
+        batch.set_tile(tile)
+        batch.fill_uniform(tgt, 0, 31)
+        batch.fill(tgt, 1, -0.375)
+        batch.fill_uniform(tgt, 2, 32)
+        tgt.synchronize()
+        inside = [np.zeros(pool.t[k].numel(), bool) for k in range(3)]
+        for i, n in enumerate(lens):
+            for k in range(3):
+                inside[k][pool.offs[k][i]:pool.offs[k][i] + n] = True
+            assert_same_bits(pool.download(0, i), tsgen.uniform_array(31, tsgen.instance_stream(i, 0), n, dtype),
+                             dtype, f"uniform a[{i}]")
+            assert_same_bits(pool.download(1, i), tsgen.narrow(np.full(n, -0.375), dtype), dtype, f"b[{i}]")
+            assert_same_bits(pool.download(2, i), tsgen.uniform_array(32, tsgen.instance_stream(i, 2), n, dtype),
+                             dtype, f"uniform c[{i}]")
+        for k in range(3):
+            whole = pool.t[k].view(torch.int16 if es == 2 else torch.int32 if es == 4 else torch.int64).cpu().numpy()
+            assert not whole[~inside[k]].any(), f"array {k}: a write outside the instances"
+        # plant mismatches at the first, a middle and the last element of some instances
+        want = np.zeros(len(lens), np.uint64)
+        for i, n in enumerate(lens):
+            if i % 2:
+                continue
+            for j in sorted({0, n // 2, n - 1}):
+                pool.view(1, i)[j] = 0.5
+                want[i] += 1
+        torch.cuda.synchronize()
+        exp = np.full(len(lens), -0.375)  # exact in every storage type
+        assert list(batch.mismatch_count(tgt, 1, exp)) == list(want)
+        assert list(batch.mismatch_count(tgt, 1, exp + 1.0)) == lens
+        batch.close()
+
+
 def test_batch_mismatch_count_counts(env):
     ts, torch, tgt = env
     lens = [10, 0, 5000, 3]
