@@ -121,7 +121,7 @@ def main_leg(ts, torch, tgt, n, steps, warmup, order="listing"):
     tgt.synchronize()
     roles = {"copy": (A, None, C) if order == "listing" else (B, None, A),
              "scale": (C, None, B), "add": (A, B, C), "triad": (B, C, A)}
-    ev = [[ts.Event() for _ in range(5)] for _ in range(steps)]
+    ev = [[ts.Event(timing=True) for _ in range(5)] for _ in range(steps)]
     for _ in range(warmup):
         ts.stream_iteration(tgt, A, B, C, 3.0, order=order)
     tgt.synchronize()
@@ -177,7 +177,7 @@ def batched_leg(ts, torch, tgt, count=4096, seed=5, replays=50, triad_reps=20):
     batch.fill(tgt, 0, 1.0), batch.fill(tgt, 1, 2.0), batch.fill(tgt, 2, 0.0)
     tgt.synchronize()
     g = ts.Graph.capture_stream_iteration(tgt, batch)
-    e0, e1 = ts.Event(), ts.Event()
+    e0, e1 = ts.Event(timing=True), ts.Event(timing=True)
     g.launch(tgt, 1)  # warm-up
     e0.record(tgt)
     g.launch(tgt, replays - 1)
@@ -193,7 +193,7 @@ def batched_leg(ts, torch, tgt, count=4096, seed=5, replays=50, triad_reps=20):
     # Launches are enqueued back to back with an event between consecutive
     # ones, so the device never waits for the host inside a measurement.
     def timed(launch, reps):
-        ev = [ts.Event() for _ in range(reps + 1)]
+        ev = [ts.Event(timing=True) for _ in range(reps + 1)]
         launch()  # warm-up, also keeps the device busy while the host enqueues
         ev[0].record(tgt)
         for i in range(reps):
@@ -317,7 +317,7 @@ def overhead_leg(ts, torch, tgt, lo=12, hi=22, iters=192, per_graph=16):
     `per_graph` iterations each.  A graph launch has a fixed cost that only a
     graph of many nodes amortises."""
     out = {}
-    e0, e1 = ts.Event(), ts.Event()
+    e0, e1 = ts.Event(timing=True), ts.Event(timing=True)
 
     def per_iteration(run, count):
         run(2)
@@ -365,7 +365,7 @@ def transform_leg(ts, tgt, n, reps=20):
     out = {}
     for name, fn in (("transform_fma_expression", lambda: tr(tgt, B, D, C, 3.0)),
                      ("tuned_triad_kernel", lambda: ts.triad(tgt, B, C, A, 3.0))):
-        ev = [ts.Event() for _ in range(reps + 1)]
+        ev = [ts.Event(timing=True) for _ in range(reps + 1)]
         fn()
         ev[0].record(tgt)
         for i in range(reps):
@@ -383,18 +383,22 @@ def transform_leg(ts, tgt, n, reps=20):
     return out
 
 
-def comparator_leg(torch, n, reps=20):
+def comparator_leg(ts, torch, n, reps=20):
     """The same traffic through library kernels, for context, on N binary64
-    elements per array, timed with events on torch's current stream (where
-    these kernels run): the runtime's device-to-device copy (hipMemcpyAsync
+    elements per array: the runtime's device-to-device copy (hipMemcpyAsync
     behind torch's copy_), torch's elementwise b + q*c, and rocBLAS level-1
     routines from the rocBLAS that torch bundles (same HIP runtime):
-    daxpy y = a*x + y (two reads, one write, like the triad), dcopy and dscal."""
+    daxpy y = a*x + y (two reads, one write, like the triad), dcopy and dscal.
+    They run on one stream of their own and are timed with the same kind of
+    events as the library's kernels in the headline leg."""
     import ctypes
 
     x = torch.ones(n, dtype=torch.float64, device="cuda")
     y = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
     z = torch.empty(n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    tgt = ts.Target(0, stream)
     cases = {"runtime_memcpy_d2d": (lambda: z.copy_(x), 16 * n),
              "torch_add_alpha_triad": (lambda: torch.add(x, y, alpha=3.0, out=z), 24 * n)}
     out = {}
@@ -403,7 +407,7 @@ def comparator_leg(torch, n, reps=20):
         blas = ctypes.CDLL(os.path.join(os.path.dirname(torch.__file__), "lib", "librocblas.so"))
         if blas.rocblas_create_handle(ctypes.byref(handle)) != 0:
             raise RuntimeError("rocblas_create_handle failed")
-        blas.rocblas_set_stream(handle, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        blas.rocblas_set_stream(handle, ctypes.c_void_p(stream.cuda_stream))
         alpha = ctypes.c_double(3.0)
         px, py, pz = (ctypes.c_void_p(t.data_ptr()) for t in (x, y, z))
         cases["rocblas_daxpy"] = (lambda: blas.rocblas_daxpy(handle, n, ctypes.byref(alpha), px, 1, py, 1), 24 * n)
@@ -411,19 +415,22 @@ def comparator_leg(torch, n, reps=20):
         cases["rocblas_dscal"] = (lambda: blas.rocblas_dscal(handle, n, ctypes.byref(alpha), pz, 1), 16 * n)
     except (OSError, AttributeError, RuntimeError) as e:
         out["rocblas"] = {"error": str(e)}
-    for name, (fn, nbytes) in cases.items():
-        fn()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
-        ev[0].record()
-        for i in range(reps):
+    with torch.cuda.stream(stream):
+        for name, (fn, nbytes) in cases.items():
             fn()
-            ev[i + 1].record()
-        ev[-1].synchronize()
-        ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
-        out[name] = {"best_GBps": round(nbytes / min(ms) / 1e6, 1),
-                     "avg_GBps": round(nbytes / (sum(ms) / len(ms)) / 1e6, 1)}
+            ev = [ts.Event(timing=True) for _ in range(reps + 1)]
+            ev[0].record(tgt)
+            for i in range(reps):
+                fn()
+                ev[i + 1].record(tgt)
+            ev[-1].synchronize()
+            ms = [ev[i].elapsed_ms(ev[i + 1]) for i in range(reps)]
+            out[name] = {"best_GBps": round(nbytes / min(ms) / 1e6, 1),
+                         "avg_GBps": round(nbytes / (sum(ms) / len(ms)) / 1e6, 1)}
+    stream.synchronize()
     if blas is not None and handle.value:
         blas.rocblas_destroy_handle(handle)
+    tgt.close()
     del x, y, z
     torch.cuda.empty_cache()
     return out
@@ -620,7 +627,7 @@ def main():
                          ("reduced_precision", lambda: reduced_leg(ts, torch, tgt)),
                          ("sweep", lambda: sweep_leg(ts, tgt)),
                          ("launch_overhead", lambda: overhead_leg(ts, torch, tgt)),
-                         ("comparators", lambda: comparator_leg(torch, a.n)),
+                         ("comparators", lambda: comparator_leg(ts, torch, a.n)),
                          ("transform", lambda: transform_leg(ts, tgt, a.n))):
             if a.legs and name not in a.legs:
                 continue

@@ -426,6 +426,12 @@ TS_API int ts_graph_destroy(ts_graph graph);
 /* ------------------------------------------------------------------------ */
 
 TS_API int ts_event_create(ts_event *out);
+/* An event for timing only: recording it makes no system-scope release, so
+ * the runtime neither writes back nor invalidates caches around it and it
+ * perturbs the work it brackets less.  Its completion does not make device
+ * writes visible to the host: synchronize the target (or use an event from
+ * ts_event_create) before the host reads results. */
+TS_API int ts_event_create_timing(ts_event *out);
 TS_API int ts_event_destroy(ts_event event);
 /* Mark the current end of the target's stream. */
 TS_API int ts_event_record(ts_event event, ts_target target);

@@ -534,11 +534,15 @@ class Graph:
 
 
 class Event:
-    """Completion marker on a target's stream (Listing 2's futures)."""
+    """Completion marker on a target's stream (Listing 2's futures).
 
-    def __init__(self):
+    timing=True makes an event for timing only (ts_event_create_timing): no
+    system-scope release when recorded, so it disturbs the work it brackets
+    less; synchronize the target before the host reads results."""
+
+    def __init__(self, timing: bool = False):
         h = ctypes.c_void_p()
-        _check(lib.ts_event_create(ctypes.byref(h)))
+        _check((lib.ts_event_create_timing if timing else lib.ts_event_create)(ctypes.byref(h)))
         self.handle = h
 
     def record(self, target: Target) -> "Event":

@@ -143,6 +143,7 @@ PROTOTYPES = {
     "ts_graph_launch": [H, H, I],
     "ts_graph_destroy": [H],
     "ts_event_create": [ctypes.POINTER(H)],
+    "ts_event_create_timing": [ctypes.POINTER(H)],
     "ts_event_destroy": [H],
     "ts_event_record": [H, H],
     "ts_event_synchronize": [H],

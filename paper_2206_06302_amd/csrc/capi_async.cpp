@@ -29,13 +29,14 @@ extern "C" {
 // ---------------------------------------------------------------------------
 // Events
 // ---------------------------------------------------------------------------
-int ts_event_create(ts_event* out) {
+namespace {
+int event_create(ts_event* out, unsigned flags) {
   TS_GUARD_BEGIN
   if (!out) return fail(TS_E_INVALID, "NULL out");
   int dev = 0;
   TS_HIP(hipGetDevice(&dev));
   hipEvent_t ev = nullptr;
-  TS_HIP(hipEventCreate(&ev));
+  TS_HIP(hipEventCreateWithFlags(&ev, flags));
   ts_event_s* e = new ts_event_s();
   e->device = dev;
   e->ev = ev;
@@ -45,6 +46,11 @@ int ts_event_create(ts_event* out) {
   return TS_OK;
   TS_GUARD_END
 }
+}  // namespace
+
+int ts_event_create(ts_event* out) { return event_create(out, hipEventDefault); }
+
+int ts_event_create_timing(ts_event* out) { return event_create(out, kTimingEventFlags); }
 
 int ts_event_destroy(ts_event e) {
   if (!e) return TS_OK;

@@ -27,6 +27,8 @@ namespace tsapi {
 
 // Largest grid.x of a launch; kernels stride over whatever lies beyond it.
 constexpr uint64_t kMaxGridX = 0x7fffffffull;
+// Events that only time work: no system-scope release when recorded.
+constexpr unsigned kTimingEventFlags = hipEventDisableSystemFence;
 constexpr uint32_t kBatchMagic = 0x42415431u;
 constexpr uint32_t kGraphMagic = 0x47524631u;
 constexpr uint32_t kEventMagic = 0x45564e31u;

@@ -23,9 +23,9 @@ int time_candidate(ts_target_s* t, int reps, int inner, Launch&& launch, double*
   std::vector<hipEvent_t> ev(2 * static_cast<size_t>(reps), nullptr);
   int st = TS_OK;
   for (auto& e : ev) {
-    const hipError_t he = hipEventCreate(&e);
+    const hipError_t he = hipEventCreateWithFlags(&e, kTimingEventFlags);
     if (he != hipSuccess) {
-      st = hip_fail(he, "hipEventCreate");
+      st = hip_fail(he, "hipEventCreateWithFlags");
       break;
     }
   }
@@ -244,11 +244,11 @@ int ts_time_op(ts_target exec, ts_op op, ts_array x, ts_array y, ts_array dst, d
   }
   if ((st = use_device(exec->device)) != TS_OK) return st;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  TS_HIP(hipEventCreate(&e0));
-  hipError_t he = hipEventCreate(&e1);
+  TS_HIP(hipEventCreateWithFlags(&e0, kTimingEventFlags));
+  hipError_t he = hipEventCreateWithFlags(&e1, kTimingEventFlags);
   if (he != hipSuccess) {
     (void)hipEventDestroy(e0);
-    return hip_fail(he, "hipEventCreate");
+    return hip_fail(he, "hipEventCreateWithFlags");
   }
   he = hipEventRecord(e0, exec->stream);
   for (int r = 0; r < reps && he == hipSuccess && st == TS_OK; ++r) st = run_map(exec, op, x, y, dst, q);

@@ -327,6 +327,17 @@ def test_time_op_and_events(env):
     e1.record(tgt)
     e1.synchronize()
     assert e1.query() and e0.elapsed_ms(e1) >= 0
+    # timing-only events bracket work the same way; results are read after a
+    # target synchronisation
+    t0, t1 = ts.Event(timing=True), ts.Event(timing=True)
+    t0.record(tgt)
+    for _ in range(3):
+        ts.triad(tgt, B, C, A, 3.0)
+    t1.record(tgt)
+    t1.synchronize()
+    assert t1.query() and t0.elapsed_ms(t1) > 0
+    tgt.synchronize()
+    assert ts.checksum(tgt, A, 2.0 + 3.0 * 2.0)["mismatches"] == 0  # c = a = 2 after time_op and copy
     done = []
     ts.scale(tgt, C, B, 3.0)
     tgt.then(lambda: done.append(1))
