@@ -436,30 +436,72 @@ def comparator_leg(ts, torch, n, reps=20):
     return out
 
 
-def cpu_baseline_leg(n, target_seconds=10.0):
-    """The oracle's timed mode on the host (pinned threads, first touch)."""
+def host_cpu_info() -> dict:
+    """The host's CPU model, sockets, NUMA nodes and the CPUs this process may use."""
+    info = {}
+    try:
+        model, sockets = None, set()
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                key, _, val = line.partition(":")
+                key = key.strip()
+                if key == "model name" and model is None:
+                    model = val.strip()
+                elif key == "physical id":
+                    sockets.add(val.strip())
+        info["model"] = model
+        info["sockets"] = len(sockets) or None
+    except OSError:
+        pass
+    try:
+        info["numa_nodes"] = len([d for d in os.listdir("/sys/devices/system/node")
+                                  if d.startswith("node") and d[4:].isdigit()])
+    except OSError:
+        pass
+    try:
+        info["cpus_allowed"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        info["cpus_allowed"] = os.cpu_count()
+    info["cpus_online"] = os.cpu_count()
+    return info
+
+
+def _oracle_timed(oracle, n, threads, target_seconds, max_iters):
+    """Iterations of the oracle's timed mode sized to about target_seconds;
+    returns (per-op seconds, final values, iterations, wall seconds)."""
+    t0 = time.perf_counter()
+    secs, _ = oracle.stream_timed_f64(n, 1, threads)
+    one = float(secs.sum())
+    iters = int(max(2, min(max_iters, target_seconds / max(one, 1e-3))))
+    secs, fin = oracle.stream_timed_f64(n, iters, threads)
+    return secs, fin, iters, time.perf_counter() - t0
+
+
+def cpu_baseline_leg(n, target_seconds=10.0, single_seconds=3.0):
+    """The oracle's timed mode on the host (pinned threads, first touch), on
+    up to 16 threads and on one thread."""
     import oracle
     try:
         cpus = len(os.sched_getaffinity(0))
     except AttributeError:
         cpus = os.cpu_count() or 1
     threads = max(1, min(16, cpus))
-    t0 = time.perf_counter()
-    secs, _ = oracle.stream_timed_f64(n, 1, threads)
-    one = float(secs.sum())
-    iters = int(max(2, min(300, target_seconds / max(one, 1e-3))))
-    secs, fin = oracle.stream_timed_f64(n, iters, threads)
-    spent = time.perf_counter() - t0
+    secs, fin, iters, spent = _oracle_timed(oracle, n, threads, target_seconds, 300)
     exp = oracle.stream_scalar_f64(1.0, 2.0, 0.0, 3.0, iters)
     ok = tuple(fin[:3]) == exp
     per_iter = secs.sum(axis=1)  # seconds per iteration (4 maps)
     agg = 80 * n / per_iter.mean() / 1e9
     best = {op: round(ts_bytes / secs[:, k].min() / 1e9, 2)
             for k, (op, ts_bytes) in enumerate(zip(OPS, (16 * n, 16 * n, 24 * n, 24 * n)))}
+    s1, f1, it1, spent1 = _oracle_timed(oracle, n, 1, single_seconds, 50)
+    ok = ok and tuple(f1[:3]) == oracle.stream_scalar_f64(1.0, 2.0, 0.0, 3.0, it1)
     return {"value": round(agg, 2), "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": f"N=2^{n.bit_length()-1} f64 x3 arrays, {iters} iterations of copy/scale/add/triad, "
                       f"{threads} pinned threads, first-touch blocks; {spent:.1f} s wall",
-            "best_GBps_per_kernel": best, "valid": bool(ok)}
+            "best_GBps_per_kernel": best,
+            "one_thread": {"value": round(80 * n / s1.sum(axis=1).mean() / 1e9, 2), "unit": "GB/s",
+                           "iterations": it1, "wall_s": round(spent1, 1)},
+            "host": host_cpu_info(), "valid": bool(ok)}
 
 
 def host_target_leg(ts, n, threads, target_seconds=10.0):
