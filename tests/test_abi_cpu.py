@@ -72,6 +72,8 @@ def test_version_and_errors(ts):
     assert L.ts_batch_op(None, None, 3) == TS_E_INVALID
     assert L.ts_graph_launch(None, None, 1) == TS_E_INVALID
     assert L.ts_event_query(None) == TS_E_INVALID
+    assert L.ts_event_create(None) == TS_E_INVALID
+    assert L.ts_event_create_timing(None) == TS_E_INVALID
     assert L.ts_future_wait(None) == TS_E_INVALID
     assert L.ts_future_ready(None) == TS_E_INVALID
     assert L.ts_future_destroy(None) == TS_OK
