@@ -132,9 +132,11 @@ TS_API int ts_target_create_owned(int device, ts_target *out);
  * algorithm call run each block on its own worker (the pinned executor), so
  * the first touch places a block's pages on its worker's NUMA node.  `cpus`
  * NULL (or ncpus 0) takes every CPU the process may run on, grouped by NUMA
- * domain.  Calls on a host target complete before they return.  Binary64
- * and binary32 storage only (TS_E_UNSUPPORTED otherwise); batches, graphs,
- * events and tuning are GPU-only (TS_E_UNSUPPORTED).  Its arrays and its
+ * domain.  Calls on a host target complete before they return.  Its arrays
+ * may hold any storage type and copy to and from host memory; the maps,
+ * fills, checksums and mismatch counts take binary64 and binary32 storage,
+ * transforms also bytes (TS_U8), TS_E_UNSUPPORTED otherwise.  Batches,
+ * graphs, events and tuning are GPU-only (TS_E_UNSUPPORTED).  Its arrays and its
  * executor report device -1, so host and GPU arrays never mix
  * (TS_E_PLACEMENT). */
 TS_API int ts_target_create_host(const int *cpus, int ncpus, ts_target *out);
