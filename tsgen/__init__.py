@@ -79,11 +79,12 @@ def narrow(x64: np.ndarray, dtype: str) -> np.ndarray:
     x64 = np.asarray(x64, np.float64)
     if dtype == "f64":
         return x64.copy()
-    x32 = x64.astype(np.float32)
-    if dtype == "f32":
-        return x32
-    if dtype == "f16":
-        return x32.astype(np.float16).view(np.uint16)
+    with np.errstate(over="ignore"):  # overflow rounds to infinity, as IEEE 754 defines
+        x32 = x64.astype(np.float32)
+        if dtype == "f32":
+            return x32
+        if dtype == "f16":
+            return x32.astype(np.float16).view(np.uint16)
     if dtype == "bf16":
         return _f32_to_bf16_bits(x32)
     raise ValueError(dtype)
