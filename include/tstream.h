@@ -65,7 +65,8 @@ typedef enum {
     TS_E_SHAPE = -2,       /* an operand shorter than the element count       */
     TS_E_DTYPE = -3,       /* operands of different storage types             */
     TS_E_PLACEMENT = -4,   /* an array not placed on the executor's device    */
-    TS_E_ALIAS = -5,       /* output partly overlaps an input                 */
+    TS_E_ALIAS = -5,       /* output partly overlaps an input; batch
+                              instances share memory                       */
     TS_E_DEVICE = -6,      /* HIP runtime error (message has its text)        */
     TS_E_OOM = -7,         /* device or host allocation failed                */
     TS_E_UNSUPPORTED = -8  /* valid request the library cannot serve         */
@@ -170,9 +171,13 @@ TS_API int ts_array_alloc(ts_target target, ts_dtype dtype, size_t n,
                           size_t offset_elems, ts_array *out);
 /* Borrow n elements at `dev_ptr` (device pointer of the target's device,
  * aligned to the element size).  ts_array_free releases only the handle.
- * The memory must outlive every enqueued use.
+ * The memory must outlive every enqueued use.  The n elements must lie in
+ * the one device allocation that holds dev_ptr (as the runtime reports it:
+ * for memory carved out of a larger allocation, as torch's caching allocator
+ * does, that is the larger allocation).
  * Errors: TS_E_INVALID (NULL with n > 0, misaligned), TS_E_PLACEMENT
- * (pointer of another device or of host memory). */
+ * (pointer of another device, of host memory, or of no known allocation),
+ * TS_E_SHAPE (the allocation ends before the n-th element). */
 TS_API int ts_array_wrap(ts_target target, ts_dtype dtype, void *dev_ptr,
                          size_t n, ts_array *out);
 /* Release the handle (and the memory, if the array owns it).  Work still
@@ -349,10 +354,18 @@ typedef struct {
  * and upload the tile tables to the target's device.  The primary plan uses
  * the triad's tile size from the tuning table (or the forced configuration);
  * a map whose configuration asks for another tile size gets a plan of its
- * own, so each map runs on its tuned tiles.  The instances' arrays must not
- * overlap one another.  Zero-length instances are allowed.
+ * own, so each map runs on its tuned tiles.  Zero-length instances are
+ * allowed and hold no memory.  One launch runs every instance at once, so
+ * the rules are checked here, before anything is planned:
+ *  - each of a_i, b_i, c_i (len_i elements) lies in one device allocation
+ *    of the target's device (TS_E_PLACEMENT otherwise; TS_E_SHAPE when the
+ *    allocation ends before element len_i - 1);
+ *  - inside one instance two arrays are the very same pointer (in place) or
+ *    share no byte; arrays of different instances share no byte
+ *    (TS_E_ALIAS otherwise).
  * Errors: TS_E_INVALID (NULL pointer with len > 0, misaligned element),
- * TS_E_PLACEMENT, TS_E_OOM, TS_E_DEVICE.  Blocking (uploads complete). */
+ * TS_E_PLACEMENT, TS_E_SHAPE, TS_E_ALIAS, TS_E_OOM, TS_E_DEVICE.  Blocking
+ * (uploads complete). */
 TS_API int ts_batch_create(ts_target target, ts_dtype dtype,
                            const ts_batch_desc *host_descs, size_t count,
                            ts_batch *out);

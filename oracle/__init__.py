@@ -85,7 +85,7 @@ def lib() -> ctypes.CDLL:
             "oracle_stream_run": [I, P, P, P, S, D, I],
             "oracle_checksum_array": [I, P, S, D, ctypes.POINTER(Checksum)],
             "oracle_mismatch_count": [I, P, P, S, ctypes.POINTER(ctypes.c_uint64)],
-            "oracle_stream_timed_f64": [S, I, I, D, P, P],
+            "oracle_stream_timed_f64": [S, I, I, D, P, P, ctypes.POINTER(ctypes.c_int)],
         }.items():
             f = getattr(L, name)
             f.argtypes, f.restype = args, ctypes.c_int
@@ -233,10 +233,11 @@ def mismatch_count(dtype: int, x: np.ndarray, ref: np.ndarray, n: int | None = N
 def stream_timed_f64(n: int, iterations: int, threads: int, q: float = 3.0):
     """Timed host run (block-partitioned pinned threads, first touch).
 
-    Returns (op_seconds[iterations, 4], final_abc[6])."""
+    Returns (op_seconds[iterations, 4], final_abc[6], threads_used)."""
     secs = np.zeros(4 * max(iterations, 1), np.float64)
     fin = np.zeros(6, np.float64)
-    rc = lib().oracle_stream_timed_f64(n, iterations, threads, q, _ptr(secs), _ptr(fin))
+    used = ctypes.c_int(0)
+    rc = lib().oracle_stream_timed_f64(n, iterations, threads, q, _ptr(secs), _ptr(fin), ctypes.byref(used))
     if rc != 0:
         raise RuntimeError(f"oracle_stream_timed_f64 failed ({rc})")
-    return secs[: 4 * iterations].reshape(iterations, 4), fin
+    return secs[: 4 * iterations].reshape(iterations, 4), fin, used.value

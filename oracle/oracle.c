@@ -363,6 +363,11 @@ typedef struct {
     pthread_barrier_t barrier;
     cpu_set_t allowed;
     int n_allowed;
+    /* Start gate: workers wait until every thread that could be created
+     * exists; `go` is then 1 (threads = that number) or -1 (give up). */
+    pthread_mutex_t gate_mu;
+    pthread_cond_t gate_cv;
+    int go;
 } timed_shared;
 
 typedef struct {
@@ -400,6 +405,13 @@ static void *timed_worker(void *p)
     timed_arg *arg = p;
     timed_shared *s = arg->s;
     int t = arg->tid;
+    pthread_mutex_lock(&s->gate_mu);
+    while (s->go == 0)
+        pthread_cond_wait(&s->gate_cv, &s->gate_mu);
+    int go = s->go;
+    pthread_mutex_unlock(&s->gate_mu);
+    if (go < 0)
+        return NULL;
     pin_to_allowed_cpu(s, t);
     size_t lo = (size_t)t * s->n / (size_t)s->threads;
     size_t hi = (size_t)(t + 1) * s->n / (size_t)s->threads;
@@ -431,62 +443,71 @@ static void *timed_worker(void *p)
 }
 
 int oracle_stream_timed_f64(size_t n, int iterations, int threads, double q,
-                            double *op_seconds, double *final_abc)
+                            double *op_seconds, double *final_abc,
+                            int *threads_used)
 {
     if (n == 0 || iterations < 0 || threads < 1 || threads > 1024 ||
-        op_seconds == NULL || final_abc == NULL)
+        op_seconds == NULL || final_abc == NULL || threads_used == NULL)
         return -1;
+    *threads_used = 0;
     timed_shared s;
     memset(&s, 0, sizeof s);
     size_t bytes = ((n * sizeof(double)) + 4095u) & ~(size_t)4095u;
     s.a = aligned_alloc(4096, bytes);
     s.b = aligned_alloc(4096, bytes);
     s.c = aligned_alloc(4096, bytes);
-    if (!s.a || !s.b || !s.c) {
+    pthread_t *tids = calloc((size_t)threads, sizeof *tids);
+    timed_arg *args = calloc((size_t)threads, sizeof *args);
+    if (!s.a || !s.b || !s.c || !tids || !args) {
         free(s.a);
         free(s.b);
         free(s.c);
+        free(tids);
+        free(args);
         return -2;
     }
     s.n = n;
-    s.threads = threads;
     s.iterations = iterations;
     s.q = q;
     s.op_seconds = op_seconds;
     CPU_ZERO(&s.allowed);
     if (sched_getaffinity(0, sizeof s.allowed, &s.allowed) == 0)
         s.n_allowed = CPU_COUNT(&s.allowed);
-    pthread_barrier_init(&s.barrier, NULL, (unsigned)threads);
-    pthread_t *tids = calloc((size_t)threads, sizeof *tids);
-    timed_arg *args = calloc((size_t)threads, sizeof *args);
-    int started = 0, rc = 0;
-    if (!tids || !args) {
-        rc = -2;
-    } else {
-        for (int t = 0; t < threads; ++t) {
-            args[t].s = &s;
-            args[t].tid = t;
-            if (pthread_create(&tids[t], NULL, timed_worker, &args[t]) != 0) {
-                rc = -2;
-                break;
-            }
-            ++started;
-        }
+    pthread_mutex_init(&s.gate_mu, NULL);
+    pthread_cond_init(&s.gate_cv, NULL);
+    int started = 0;
+    for (int t = 0; t < threads; ++t) {
+        args[t].s = &s;
+        args[t].tid = t;
+        if (pthread_create(&tids[t], NULL, timed_worker, &args[t]) != 0)
+            break;
+        ++started;
     }
-    /* A partial start cannot pass the barrier; only a full start is joined. */
-    if (rc == 0) {
-        for (int t = 0; t < started; ++t)
-            pthread_join(tids[t], NULL);
+    /* The run uses the threads that exist: the blocks and the barrier are
+     * sized to them before any worker passes the gate. */
+    s.threads = started;
+    if (started > 0)
+        pthread_barrier_init(&s.barrier, NULL, (unsigned)started);
+    pthread_mutex_lock(&s.gate_mu);
+    s.go = started > 0 ? 1 : -1;
+    pthread_cond_broadcast(&s.gate_cv);
+    pthread_mutex_unlock(&s.gate_mu);
+    for (int t = 0; t < started; ++t)
+        pthread_join(tids[t], NULL);
+    int rc = -2;
+    if (started > 0) {
+        pthread_barrier_destroy(&s.barrier);
         final_abc[0] = s.a[0];
         final_abc[1] = s.b[0];
         final_abc[2] = s.c[0];
         final_abc[3] = s.a[n - 1];
         final_abc[4] = s.b[n - 1];
         final_abc[5] = s.c[n - 1];
-    } else if (started > 0) {
-        abort(); /* threads are blocked in the barrier; nothing sane remains */
+        *threads_used = started;
+        rc = 0;
     }
-    pthread_barrier_destroy(&s.barrier);
+    pthread_cond_destroy(&s.gate_cv);
+    pthread_mutex_destroy(&s.gate_mu);
     free(tids);
     free(args);
     free(s.a);

@@ -120,10 +120,15 @@ int oracle_mismatch_count(int dtype, const void *x, const void *ref, size_t n,
  * (1, 2, 0) into its own block itself (first touch).  The four maps run in
  * listing order with a barrier around each; op_seconds[4*it + op] receives
  * the wall time of map `op` in iteration `it`.  final_abc receives
- * a[0], b[0], c[0], a[n-1], b[n-1], c[n-1] at the end.
- * Returns 0, -1 on bad arguments, -2 on allocation failure. */
+ * a[0], b[0], c[0], a[n-1], b[n-1], c[n-1] at the end.  T is the number of
+ * threads the system let the call create (at most `threads`, reported in
+ * *threads_used): the blocks and the barrier are sized to them before any
+ * of them starts, so a partial start still runs to the end.
+ * Returns 0, -1 on bad arguments, -2 on allocation failure or when no
+ * thread could be created. */
 int oracle_stream_timed_f64(size_t n, int iterations, int threads, double q,
-                            double *op_seconds, double *final_abc);
+                            double *op_seconds, double *final_abc,
+                            int *threads_used);
 
 #ifdef __cplusplus
 }

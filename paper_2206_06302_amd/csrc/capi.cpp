@@ -47,6 +47,36 @@ int host_only_gpu(const char* what) {
 }
 
 // Make `device` current for the calling thread (cheap when it already is).
+int check_device_range(int device, const void* ptr, uint64_t n, size_t es, const char* what) {
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof attr);
+  hipError_t e = hipPointerGetAttributes(&attr, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(TS_E_PLACEMENT, "%s: pointer is not device memory known to the HIP runtime", what);
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return fail(TS_E_PLACEMENT, "%s: pointer is not device memory (memory type %d)", what,
+                static_cast<int>(attr.type));
+  if (attr.device != device)
+    return fail(TS_E_PLACEMENT, "%s: pointer lives on device %d, the target is device %d", what, attr.device,
+                device);
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  e = hipMemGetAddressRange(&base, &size, const_cast<void*>(ptr));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(TS_E_PLACEMENT, "%s: the allocation holding the pointer is unknown to the HIP runtime", what);
+  }
+  const uintptr_t p = reinterpret_cast<uintptr_t>(ptr);
+  const uintptr_t lo = reinterpret_cast<uintptr_t>(base);
+  const uint64_t room = (lo + size - p) / es;  // whole elements from ptr to the allocation's end
+  if (n > room)
+    return fail(TS_E_SHAPE, "%s: %llu elements from the pointer run past the end of its allocation (room for %llu)",
+                what, static_cast<unsigned long long>(n), static_cast<unsigned long long>(room));
+  return TS_OK;
+}
+
 int use_device(int device) {
   int cur = -1;
   if (hipGetDevice(&cur) == hipSuccess && cur == device) return TS_OK;
@@ -496,17 +526,7 @@ int ts_array_wrap(ts_target t, ts_dtype dtype, void* dev_ptr, size_t n, ts_array
   } else if (n > 0) {
     int st = use_device(t->device);
     if (st != TS_OK) return st;
-    hipPointerAttribute_t attr;
-    std::memset(&attr, 0, sizeof attr);
-    const hipError_t e = hipPointerGetAttributes(&attr, dev_ptr);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(TS_E_PLACEMENT, "pointer is not device memory known to the HIP runtime");
-    }
-    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
-      return fail(TS_E_PLACEMENT, "pointer is not device memory (memory type %d)", static_cast<int>(attr.type));
-    if (attr.device != t->device)
-      return fail(TS_E_PLACEMENT, "pointer lives on device %d, the target is device %d", attr.device, t->device);
+    if ((st = check_device_range(t->device, dev_ptr, n, es, "array")) != TS_OK) return st;
   }
   ts_array_s* a = new ts_array_s();
   a->alive = std::make_shared<bool>(true);

@@ -5,6 +5,7 @@
 // every instance into tiles and uploads a table of self-contained tile
 // records; each map reads the table of its configuration's tile size.
 // Graphs capture one or more four-map iterations for replay.
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -191,9 +192,6 @@ int ts_batch_create(ts_target t, ts_dtype dtype, const ts_batch_desc* descs, siz
   b->device = t->device;
   b->dtype = dtype;
   b->host.resize(count);
-  // Placement: every instance's first element must be device memory of this
-  // device (one query per array; instances are not required to be distinct
-  // allocations).
   for (size_t i = 0; i < count; ++i) {
     const ts_batch_desc& d = descs[i];
     b->host[i] = HostDesc{reinterpret_cast<uintptr_t>(d.a), reinterpret_cast<uintptr_t>(d.b),
@@ -207,22 +205,25 @@ int ts_batch_create(ts_target t, ts_dtype dtype, const ts_batch_desc* descs, siz
     delete b;
     return status;
   };
-  std::vector<uintptr_t> seen;
+  // Placement: every array of every instance lies, whole, in one device
+  // allocation of this device; then no two instances share memory, and the
+  // arrays of one instance are identical or disjoint.
+  const size_t es = dtype_size(dtype);
   for (size_t i = 0; i < count; ++i) {
     if (descs[i].len == 0) continue;
-    for (void* ptr : {descs[i].a, descs[i].b, descs[i].c}) {
-      if (!ptr) return cleanup(fail(TS_E_INVALID, "instance %zu: NULL array with len > 0", i));
-      hipPointerAttribute_t attr;
-      std::memset(&attr, 0, sizeof attr);
-      const hipError_t e = hipPointerGetAttributes(&attr, ptr);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return cleanup(fail(TS_E_PLACEMENT, "instance %zu: pointer is not device memory", i));
-      }
-      if ((attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged) ||
-          attr.device != t->device)
-        return cleanup(fail(TS_E_PLACEMENT, "instance %zu: array is not on the target's device", i));
+    const void* arrs[3] = {descs[i].a, descs[i].b, descs[i].c};
+    for (int w = 0; w < 3; ++w) {
+      if (!arrs[w]) return cleanup(fail(TS_E_INVALID, "instance %zu: NULL array with len > 0", i));
+      char what[64];
+      std::snprintf(what, sizeof what, "instance %zu array %c", i, "abc"[w]);
+      const int rs = check_device_range(t->device, arrs[w], descs[i].len, es, what);
+      if (rs != TS_OK) return cleanup(rs);
     }
+  }
+  {
+    std::string err;
+    const int os = check_batch_overlap(b->host.data(), b->host.size(), es, err);
+    if (os != ST_OK) return cleanup(fail(os, "%s", err.c_str()));
   }
   const ts_kernel_cfg cfg = tune_table().lookup(TS_TRIAD, dtype, 0, TS_ALIGN_16, 1);
   uint64_t total = 0;

@@ -142,6 +142,10 @@ void host_blocks(ts_target_s* t, uint64_t n, F&& fn) {
 void future_ready_cb(void* p);
 // Make `device` current for the calling thread (cheap when it already is).
 int use_device(int device);
+// `ptr` must be device memory of `device` whose allocation holds n elements
+// of es bytes from ptr on: TS_E_PLACEMENT (not device memory, another device,
+// unknown allocation) or TS_E_SHAPE (the allocation ends before n elements).
+int check_device_range(int device, const void* ptr, uint64_t n, size_t es, const char* what);
 // Storage types of arrays (bytes included) and of the STREAM maps.
 bool valid_dtype(int dt);
 bool map_dtype(int dt);

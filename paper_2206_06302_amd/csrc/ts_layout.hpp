@@ -7,6 +7,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -183,6 +184,59 @@ struct HostDesc {
   uint64_t len;
   double q;
 };
+
+// Overlap rule of a batch (one launch runs every instance at once, so
+// instances that share memory would race): inside one instance a, b and c
+// are each either the very same array or disjoint from one another (in
+// place, as the algorithm calls allow); arrays of different instances never
+// share a byte.  Instances of length 0 hold no memory.  Returns ST_OK,
+// ST_SHAPE when a range runs past the end of the address space, or ST_ALIAS
+// naming the first overlapping pair.
+inline int check_batch_overlap(const HostDesc* in, size_t count, size_t es, std::string& err) {
+  struct Range {
+    uintptr_t lo, hi;
+    size_t inst;
+    int which;
+  };
+  static const char* const kNames[3] = {"a", "b", "c"};
+  std::vector<Range> r;
+  r.reserve(3 * count);
+  for (size_t i = 0; i < count; ++i) {
+    const HostDesc& h = in[i];
+    if (h.len == 0) continue;
+    const uintptr_t p[3] = {h.a, h.b, h.c};
+    for (int w = 0; w < 3; ++w) {
+      bool same = false;  // the same array as an earlier one of this instance
+      for (int v = 0; v < w; ++v) same = same || p[v] == p[w];
+      if (same) continue;
+      if (es == 0 || h.len > (UINTPTR_MAX - p[w]) / es) {
+        err = "instance " + std::to_string(i) + ": array " + kNames[w] + " runs past the end of the address space";
+        return ST_SHAPE;
+      }
+      r.push_back(Range{p[w], p[w] + static_cast<uintptr_t>(h.len * es), i, w});
+    }
+  }
+  std::sort(r.begin(), r.end(), [](const Range& x, const Range& y) {
+    return x.lo != y.lo ? x.lo < y.lo : x.hi < y.hi;
+  });
+  size_t reach = 0;  // the range reaching furthest so far
+  for (size_t k = 1; k < r.size(); ++k) {
+    if (r[k].lo < r[reach].hi) {
+      const Range& x = r[reach];
+      const Range& y = r[k];
+      if (x.inst == y.inst)
+        err = "instance " + std::to_string(x.inst) + ": arrays " + kNames[x.which] + " and " + kNames[y.which] +
+              " partly overlap";
+      else
+        err = "instances " + std::to_string(std::min(x.inst, y.inst)) + " and " +
+              std::to_string(std::max(x.inst, y.inst)) + " share memory (arrays " + kNames[x.which] + " and " +
+              kNames[y.which] + ")";
+      return ST_ALIAS;
+    }
+    if (r[k].hi > r[reach].hi) reach = k;
+  }
+  return ST_OK;
+}
 
 // Build the device descriptors and the tile table.  Tiles of one instance
 // are consecutive in the table; instances follow one another in order.

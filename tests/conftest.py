@@ -14,17 +14,20 @@ def pytest_configure(config):
 
 
 def pytest_sessionstart(session):
-    """Build the library and the C client when nothing is built yet (a fresh
-    checkout); an existing build is used as it is."""
-    lib = os.path.join(ROOT, "paper_2206_06302_amd", "libtstream.so")
-    client = os.path.join(ROOT, "tests", "cpp", "stream_client")
-    if os.path.exists(lib) and os.path.exists(client):
-        return
+    """Build the library when it is missing or older than any of its sources,
+    and the C client when it is missing or older than its source or the
+    library, so the tests always run the sources of this tree."""
     import __graft_entry__ as entry
 
-    if not os.path.exists(lib):
-        entry._load_build_module().build(verbose=True)
-    entry.build_c_client()
+    lib = os.path.join(ROOT, "paper_2206_06302_amd", "libtstream.so")
+    client = os.path.join(ROOT, "tests", "cpp", "stream_client")
+    client_src = client + ".c"
+    builder = entry._load_build_module()
+    if builder.stale():
+        builder.build(verbose=True)
+    if (not os.path.exists(client) or os.path.getmtime(client) < os.path.getmtime(client_src)
+            or os.path.getmtime(client) < os.path.getmtime(lib)):
+        entry.build_c_client()
 
 
 @pytest.fixture(scope="session")

@@ -68,4 +68,19 @@ int shim_plan_batch(const uint64_t* descs, size_t count, uint64_t es, int64_t ti
   return 0;
 }
 
+// descs: count x {a, b, c, len}; err receives the message (cap bytes).
+int shim_check_batch_overlap(const uint64_t* descs, size_t count, uint64_t es, char* err, size_t cap) {
+  std::vector<ts::HostDesc> in(count);
+  for (size_t i = 0; i < count; ++i)
+    in[i] = ts::HostDesc{static_cast<uintptr_t>(descs[4 * i]), static_cast<uintptr_t>(descs[4 * i + 1]),
+                         static_cast<uintptr_t>(descs[4 * i + 2]), descs[4 * i + 3], 1.0};
+  std::string msg;
+  const int st = ts::check_batch_overlap(in.data(), count, es, msg);
+  if (cap) {
+    strncpy(err, msg.c_str(), cap - 1);
+    err[cap - 1] = 0;
+  }
+  return st;
+}
+
 }  // extern "C"

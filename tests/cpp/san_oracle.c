@@ -46,7 +46,8 @@ int main(int argc, char **argv)
             free(buf[k]);
     }
     double secs[4 * 4], fin[6];
-    if (oracle_stream_timed_f64(1u << 18, 4, threads, 3.0, secs, fin))
+    int used = 0;
+    if (oracle_stream_timed_f64(1u << 18, 4, threads, 3.0, secs, fin, &used) || used != threads)
         return 1;
     printf("oracle ok: a = %g after the timed run\n", fin[0]);
     return 0;

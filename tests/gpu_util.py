@@ -62,3 +62,70 @@ def assert_same_bits(got, ref, dtype, what=""):
         j = int(bad[0])
         raise AssertionError(f"{what}: {bad.size} elements differ; first at {j}: "
                              f"got {widen(dtype, got[j:j+1])[0]!r} expected {widen(dtype, ref[j:j+1])[0]!r}")
+
+
+# ---------------------------------------------------------------------------
+# Whole-array comparison at full size
+# ---------------------------------------------------------------------------
+CHUNK = 1 << 24
+
+
+def host_workers() -> int:
+    """Threads for host-side oracle work: the CPUs this process may use,
+    at most 16."""
+    import os
+
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _host_bits(buf, dtype: str) -> np.ndarray:
+    import torch
+
+    if dtype in ("bf16", "f16"):
+        return buf.view(torch.int16).numpy().view(np.uint16)
+    return buf.numpy()
+
+
+def compare_whole(torch, views, dtype: str, expected, n: int, what: str = "", chunk: int = CHUNK):
+    """Compare EVERY element of the device tensors `views` with the oracle.
+
+    ``expected(start, stop)`` returns ``(arrays, info)``: one host storage
+    array per view holding the oracle's results for elements [start, stop),
+    and any per-chunk value the caller wants back.  It runs on a thread pool
+    (the oracle's C calls and numpy's loops release the GIL), a few chunks
+    ahead of the main thread, which copies each device chunk into a pinned
+    host buffer and compares stored bits (NaN matches NaN).  The device work
+    must be complete (synchronised) before the call.  Returns the infos in
+    chunk order; raises AssertionError naming the first differing element."""
+    import concurrent.futures as cf
+
+    ranges = [(s, min(n, s + chunk)) for s in range(0, n, chunk)]
+    if not ranges:
+        return []
+    workers = host_workers()
+    pinned = torch.empty(min(chunk, n), dtype=views[0].dtype, pin_memory=True)
+    infos = []
+    with cf.ThreadPoolExecutor(workers) as pool:
+        futs, nxt = {}, 0
+        for i, (s, e) in enumerate(ranges):
+            while nxt < len(ranges) and nxt <= i + workers + 1:
+                futs[nxt] = pool.submit(expected, *ranges[nxt])
+                nxt += 1
+            arrays, info = futs.pop(i).result()
+            infos.append(info)
+            for k, (v, ref) in enumerate(zip(views, arrays)):
+                buf = pinned[: e - s]
+                buf.copy_(v[s:e])  # synchronous copy into pinned host memory
+                got = _host_bits(buf, dtype)
+                bad = mismatches(got, ref, dtype)
+                if bad.size:
+                    j = int(bad[0])
+                    raise AssertionError(
+                        f"{what}: array {k}: {bad.size} of {e - s} elements differ in chunk [{s}, {e}); "
+                        f"first at {s + j}: got {widen(dtype, got[j:j + 1])[0]!r} "
+                        f"expected {widen(dtype, ref[j:j + 1])[0]!r}")
+    return infos

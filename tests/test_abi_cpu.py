@@ -213,6 +213,8 @@ def shim(tmp_path_factory):
                                     ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, U]
     lib.shim_plan_batch.argtypes = [U, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int64, U, ctypes.c_size_t,
                                     U, U, U]
+    lib.shim_check_batch_overlap.argtypes = [U, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_char_p,
+                                             ctypes.c_size_t]
     return lib
 
 
@@ -366,3 +368,72 @@ def test_c_client_on_a_host_target(tmp_path):
     r = subprocess.run([str(out), "100003", "host"], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "all checks passed" in r.stdout and r.stdout.count("ok  ") == 6
+
+
+# ------------------------------------------------------- batch overlap rule
+def batch_overlap(shim, descs, es):
+    flat = [v for d in descs for v in d]
+    msg = ctypes.create_string_buffer(256)
+    st = shim.shim_check_batch_overlap(_u64(flat or [0]), len(descs), es, msg, 256)
+    return st, msg.value.decode()
+
+
+def _brute_overlap(descs, es):
+    """Reference: every pair of distinct arrays, within one instance
+    (identical pointers allowed) or across instances (any shared byte)."""
+    arrs = []
+    for i, (a, b, c, n) in enumerate(descs):
+        if n == 0:
+            continue
+        seen = set()
+        for p in (a, b, c):
+            if p in seen:
+                continue
+            seen.add(p)
+            arrs.append((p, p + n * es, i))
+    for k in range(len(arrs)):
+        for m in range(k + 1, len(arrs)):
+            (lo1, hi1, _), (lo2, hi2, _) = arrs[k], arrs[m]
+            if lo1 < hi2 and lo2 < hi1:
+                return TS_E_ALIAS
+    return TS_OK
+
+
+def test_batch_overlap_rules(shim):
+    B = 1 << 30
+    n = 1000
+    ok = [[B, B + 8 * n, B + 16 * n, n], [B + 24 * n, B + 32 * n, B + 40 * n, n]]
+    assert batch_overlap(shim, ok, 8) == (TS_OK, "")
+    # in place inside one instance: the very same array is allowed
+    assert batch_overlap(shim, [[B, B, B + 8 * n, n]], 8)[0] == TS_OK
+    assert batch_overlap(shim, [[B, B, B, n]], 8)[0] == TS_OK
+    # partial overlap inside one instance
+    st, msg = batch_overlap(shim, [[B, B + 8, B + 16 * n, n]], 8)
+    assert st == TS_E_ALIAS and "instance 0" in msg and "partly overlap" in msg
+    # two instances sharing an array, identical or shifted
+    st, msg = batch_overlap(shim, [ok[0], [B, B + 48 * n, B + 56 * n, n]], 8)
+    assert st == TS_E_ALIAS and "instances 0 and 1" in msg
+    st, msg = batch_overlap(shim, [ok[0], [B + 16 * n + 8 * (n - 1), B + 48 * n, B + 56 * n, n]], 8)
+    assert st == TS_E_ALIAS
+    # adjacent arrays share no byte
+    assert batch_overlap(shim, [ok[0], [B + 24 * n, B + 32 * n, B + 40 * n, n]], 8)[0] == TS_OK
+    # zero-length instances hold no memory
+    assert batch_overlap(shim, [ok[0], [B, B, B, 0]], 8)[0] == TS_OK
+    # a range past the end of the address space
+    assert batch_overlap(shim, [[2 ** 64 - 64, B, B + 8 * n, 16]], 8)[0] == TS_E_SHAPE
+    assert batch_overlap(shim, [], 8)[0] == TS_OK
+
+
+@pytest.mark.parametrize("es", [8, 2])
+def test_batch_overlap_matches_brute_force(shim, es):
+    rng = np.random.default_rng(es)
+    for _ in range(400):
+        count = int(rng.integers(1, 7))
+        descs = []
+        for _ in range(count):
+            n = int(rng.choice([0, 1, 5, 40]))
+            ptrs = [int(rng.integers(0, 64)) * es * 8 for _ in range(3)]
+            if rng.random() < 0.3:
+                ptrs[1] = ptrs[0]
+            descs.append(ptrs + [n])
+        assert batch_overlap(shim, descs, es)[0] == _brute_overlap(descs, es), descs

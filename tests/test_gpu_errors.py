@@ -152,3 +152,35 @@ def test_batch_errors(env):
     empty.op(tgt, "triad")
     assert empty.info()["tiles"] == 0
     empty.close()
+
+
+def test_batch_and_wrap_refuse_overlap_and_overrun(env):
+    """ts_batch_create refuses instances that share memory (TS_E_ALIAS) and
+    arrays that run past the end of their device allocation (TS_E_SHAPE);
+    ts_array_wrap refuses the overrun too.  Only the create and wrap calls
+    run: nothing is launched on a refused batch."""
+    ts, torch, tgt = env
+    n = 1000
+    A = ts.Array.alloc(tgt, "f64", 8 * n)  # one allocation of 8n doubles
+    p = A.ptr()
+    ok = [(p, p + 8 * n, p + 16 * n, n, 2.0), (p + 24 * n, p + 32 * n, p + 40 * n, n, 3.0)]
+    b = ts.Batch(tgt, "f64", ok)
+    b.close()
+    b = ts.Batch(tgt, "f64", [(p, p, p + 16 * n, n, 2.0)])  # in place: the very same array
+    b.close()
+    cases = {
+        "partial overlap inside an instance": ([(p, p + 8, p + 16 * n, n, 2.0)], E_ALIAS),
+        "two instances share an array": ([ok[0], (p, p + 48 * n, p + 56 * n, n, 3.0)], E_ALIAS),
+        "two instances overlap partly": ([ok[0], (p + 16 * n + 8, p + 48 * n, p + 56 * n, n, 3.0)], E_ALIAS),
+        "array runs past its allocation": ([(p, p + 8 * n, p + 16 * n, n + (4 << 20), 2.0)], E_SHAPE),
+    }
+    for what, (descs, want) in cases.items():
+        with pytest.raises(ts.TSError) as e:
+            ts.Batch(tgt, "f64", descs)
+        assert e.value.status == want, (what, e.value)
+    h = ctypes.c_void_p()
+    assert ts.lib.ts_array_wrap(tgt.handle, 0, p, 8 * n + (4 << 20), ctypes.byref(h)) == E_SHAPE
+    assert "past the end" in ts.last_error()
+    assert ts.lib.ts_array_wrap(tgt.handle, 0, p, 8 * n, ctypes.byref(h)) == 0
+    ts.lib.ts_array_free(h)
+    A.free()

@@ -381,7 +381,8 @@ def test_mismatch_count(oracle_lib):
 # ------------------------------------------------------------------ timed mode
 @pytest.mark.parametrize("threads", [1, 3, 8])
 def test_timed_mode_closed_form(oracle_lib, threads):
-    secs, fin = oracle_lib.stream_timed_f64(100003, 4, threads)
+    secs, fin, used = oracle_lib.stream_timed_f64(100003, 4, threads)
+    assert used == threads
     assert secs.shape == (4, 4) and np.all(secs > 0)
     exp = (15.0 ** 4, 3 * 15.0 ** 3, 4 * 15.0 ** 3)
     assert tuple(fin[:3]) == exp and tuple(fin[3:]) == exp
