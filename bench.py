@@ -470,10 +470,10 @@ def _oracle_timed(oracle, n, threads, target_seconds, max_iters):
     """Iterations of the oracle's timed mode sized to about target_seconds;
     returns (per-op seconds, final values, iterations, wall seconds)."""
     t0 = time.perf_counter()
-    secs, _ = oracle.stream_timed_f64(n, 1, threads)
+    secs, _, _ = oracle.stream_timed_f64(n, 1, threads)
     one = float(secs.sum())
     iters = int(max(2, min(max_iters, target_seconds / max(one, 1e-3))))
-    secs, fin = oracle.stream_timed_f64(n, iters, threads)
+    secs, fin, _ = oracle.stream_timed_f64(n, iters, threads)
     return secs, fin, iters, time.perf_counter() - t0
 
 
