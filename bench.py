@@ -33,6 +33,7 @@ from __future__ import annotations
 import argparse
 import importlib.util
 import json
+import math
 import os
 import re
 import sys
@@ -45,7 +46,7 @@ if ROOT not in sys.path:
 METRIC = "STREAM Triad/Copy GB/s and % of HBM peak, FP64 N=2^27; batched vs plain"
 PEAK_GBPS = 8000.0
 OPS = ("copy", "scale", "add", "triad")
-EXTRA_LEGS = ("batched", "reduced_precision", "sweep", "launch_overhead", "comparators", "transform")
+EXTRA_LEGS = ("ceiling", "batched", "reduced_precision", "sweep", "launch_overhead", "comparators", "transform")
 PROFILE_PMC = os.path.join(ROOT, "profiles", "triad_f64_n2p27_pmc.md")
 
 
@@ -77,41 +78,55 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def first_value(arr) -> float:
-    return float(arr.to_host(1)[0])
+def _fma(x: float, y: float, z: float) -> float:
+    """x*y + z rounded once to binary64 (nearest, ties to even): the exact
+    rational value is formed with fractions and divided out by CPython's
+    integer true division, which rounds correctly; a finite value beyond the
+    largest binary64 rounds to infinity.  Non-finite operands use binary64
+    arithmetic directly (its result is then exact)."""
+    from fractions import Fraction
+
+    if not (math.isfinite(x) and math.isfinite(y) and math.isfinite(z)):
+        return x * y + z
+    v = Fraction(x) * Fraction(y) + Fraction(z)
+    try:
+        return v.numerator / v.denominator
+    except OverflowError:
+        return math.copysign(math.inf, v)
 
 
-def uniform_arrays(ts, tgt, arrays) -> bool:
-    """Every element equals element 0 of its array, bit for bit."""
-    return all(ts.checksum(tgt, arr, first_value(arr))["mismatches"] == 0 for arr in arrays)
-
-
-def expected_integers(order, iters):
-    """(a, b, c) after `iters` iterations from (1, 2, 0) with q = 3, in exact
-    integer arithmetic (every intermediate is an integer below 2^53 here, so
-    binary64 reproduces it exactly).  Listing order: a = 15^k, b = 3*15^(k-1),
-    c = 4*15^(k-1); the copy_b variant follows its own recurrence."""
-    a, b, c = 1, 2, 0
+def exact_chain(a: float, b: float, c: float, q: float, iters: int, order: str = "listing", fused: bool = True):
+    """(a, b, c) of one element after `iters` iterations of Listing 4's four
+    maps, every operation rounded once to binary64: copy, scale b = q*c (one
+    product), add c = a + b (one sum), triad a = b + q*c as one fused
+    multiply-add (fused=False rounds the product first: a second rounding,
+    which a 50-iteration run from (1, 2, 0) with q = 3 tells apart).  Python
+    float products and sums are binary64 operations rounded to nearest even;
+    only the fused step needs exact rationals."""
     for _ in range(iters):
         if order == "listing":
             c = a
         else:
             a = b
-        b = 3 * c
+        b = q * c
         c = a + b
-        a = b + 3 * c
-    assert max(a, b, c) < 2 ** 53
-    return float(a), float(b), float(c)
+        a = _fma(q, c, b) if fused else b + q * c
+    return a, b, c
 
 
-def closed_form_check(ts, tgt, A, B, C, iters=10, order="listing") -> bool:
-    """The 10-iteration run from (1, 2, 0) with q = 3 must give the exact
-    integers of STREAM's closed form, at every element."""
+def chain_check(ts, tgt, arrays, expected) -> bool:
+    """Every element of every array equals its expected value bit for bit."""
+    return all(ts.checksum(tgt, arr, e)["mismatches"] == 0 for arr, e in zip(arrays, expected))
+
+
+def fused_chain_check(ts, tgt, A, B, C, iters=50, order="listing") -> bool:
+    """A run of `iters` iterations from (1, 2, 0) with q = 3 in the tuned
+    launch shapes: every element must equal the exactly rounded chain, whose
+    triad rounds once (at 50 iterations an unfused triad differs)."""
     A.fill(1.0), B.fill(2.0), C.fill(0.0)
     for _ in range(iters):
         ts.stream_iteration(tgt, A, B, C, 3.0, order=order)
-    exp = expected_integers(order, iters)
-    return all(ts.checksum(tgt, arr, e)["mismatches"] == 0 for arr, e in zip((A, B, C), exp))
+    return chain_check(ts, tgt, (A, B, C), exact_chain(1.0, 2.0, 0.0, 3.0, iters, order))
 
 
 def main_leg(ts, torch, tgt, n, steps, warmup, order="listing"):
@@ -139,8 +154,11 @@ def main_leg(ts, torch, tgt, n, steps, warmup, order="listing"):
     wall = time.perf_counter() - t0
     per = {op: [ev[s][k].elapsed_ms(ev[s][k + 1]) for s in range(steps)] for k, op in enumerate(OPS)}
     step_ms = [ev[s][0].elapsed_ms(ev[s][4]) for s in range(steps)]
-    # every element followed the same chain; then STREAM's closed form
-    valid = uniform_arrays(ts, tgt, (A, B, C)) and closed_form_check(ts, tgt, A, B, C, order=order)
+    # The timed arrays: every element equals the exactly rounded chain after
+    # the warm-up and timed steps.  Then a 50-iteration run in the same
+    # launch shapes, which an unfused triad would fail.
+    valid_timed = chain_check(ts, tgt, (A, B, C), exact_chain(1.0, 2.0, 0.0, 3.0, warmup + steps, order))
+    valid_fused = fused_chain_check(ts, tgt, A, B, C, 50, order)
     kernels = {}
     for op in OPS:
         b = ts.stream_bytes(op, n)
@@ -152,7 +170,67 @@ def main_leg(ts, torch, tgt, n, steps, warmup, order="listing"):
                        "cfg": ts.get_kernel_cfg(op, "f64", n)}
     for arr in (A, B, C):
         arr.free()
-    return {"wall_s": wall, "step_ms": step_ms, "kernels": kernels, "valid": valid}
+    return {"wall_s": wall, "step_ms": step_ms, "kernels": kernels, "valid": valid_timed and valid_fused,
+            "valid_timed_arrays": valid_timed, "valid_k50_fused_chain": valid_fused}
+
+
+PROBE_KINDS = (("read_1r", 1, 0), ("read_2r", 2, 0), ("write_1w", 0, 1), ("copy_1r1w", 1, 1),
+               ("triad_2r1w", 2, 1))
+LDS_PER_CU = 160 * 1024  # gfx950
+
+
+def probe_shapes():
+    """Launch shapes the ceiling leg searches for every mix of traffic:
+    lanes per workgroup, 16-byte vectors per lane and their layout,
+    nontemporal loads, and a cap on the workgroups resident per CU (through
+    dynamic LDS)."""
+    shapes = []
+    for block in (256, 512, 1024):
+        for unroll in (1, 2, 4):
+            for wave in ((0,) if unroll == 1 else (0, 1)):
+                for ntl in (0, 1):
+                    for cap in (0, 2, 4):
+                        lds = 0 if cap == 0 else LDS_PER_CU // cap
+                        if cap and 1024 // block * 2 <= cap:
+                            continue  # the cap would not bind at this block size
+                        shapes.append({"block": block, "unroll": unroll, "wave_contiguous": wave, "nt_load": ntl,
+                                       "nt_store": 1, "lds_bytes": lds})
+    return shapes
+
+
+def ceiling_leg(ts, tgt, n, reps=20):
+    """What the memory system delivers for each mix of traffic, on the
+    headline's array size (n binary64 elements per array): the library's
+    straight-line probe (ts_probe_bandwidth) reads one or two arrays and
+    writes none or one, over a search of launch shapes; per mix, the shape
+    with the best average over `reps` launches.  Bytes = arrays touched x
+    array bytes, as the STREAM convention counts them."""
+    nbytes = 8 * n
+    A, B, C = (ts.Array.alloc(tgt, "f64", n) for _ in range(3))
+    for k, arr in enumerate((A, B, C)):
+        arr.fill_uniform(6, k)
+    out = {}
+    for name, reads, writes in PROBE_KINDS:
+        moved = (reads + writes) * nbytes
+        ranked = []
+        for shape in probe_shapes():
+            cfg = dict(shape, reads=reads, writes=writes)
+            try:
+                ms = timed_launches(ts, tgt, lambda: ts.probe_bandwidth(tgt, cfg, A, B, C, nbytes), reps)
+            except ts.TSError as e:
+                if "lds_bytes" in str(e):
+                    continue  # this device offers less LDS per CU
+                raise
+            ranked.append((sum(ms) / len(ms), min(ms), shape))
+        ranked.sort(key=lambda r: r[0])
+        avg, best, shape = ranked[0]
+        out[name] = {"avg_GBps": round(moved / avg / 1e6, 1), "best_GBps": round(moved / best / 1e6, 1),
+                     "frac_avg": round(moved / avg / 1e6 / PEAK_GBPS, 4), "shape": shape,
+                     "runner_up_avg_GBps": [round(moved / r[0] / 1e6, 1) for r in ranked[1:4]],
+                     "shapes_tried": len(ranked)}
+    for arr in (A, B, C):
+        arr.free()
+    return out
 
 
 def batched_leg(ts, torch, tgt, count=4096, seed=5, replays=50, triad_reps=20):
@@ -184,32 +262,27 @@ def batched_leg(ts, torch, tgt, count=4096, seed=5, replays=50, triad_reps=20):
     e1.record(tgt)
     e1.synchronize()
     graph_ms = e0.elapsed_ms(e1) / (replays - 1)
-    # every element of instance i equals its first element, and that value
-    # follows a = (q(2+q))^K up to the rounding of 4K operations
-    firsts = [pools[k][torch.tensor(offs, device="cuda")].cpu().numpy() for k in range(3)]
-    valid = all(int(batch.mismatch_count(tgt, k, firsts[k]).sum()) == 0 for k in range(3))
-    growth = (qs * (2.0 + qs)) ** replays
-    valid = valid and bool(np.all(np.abs(firsts[0] - growth) <= 4 * replays * 2.0 ** -52 * growth))
-    # Launches are enqueued back to back with an event between consecutive
-    # ones, so the device never waits for the host inside a measurement.
-    def timed(launch, reps):
-        ev = [ts.Event(timing=True) for _ in range(reps + 1)]
-        launch()  # warm-up, also keeps the device busy while the host enqueues
-        ev[0].record(tgt)
-        for i in range(reps):
-            launch()
-            ev[i + 1].record(tgt)
-        ev[-1].synchronize()
-        return [ev[i].elapsed_ms(ev[i + 1]) for i in range(reps)]
+    # every element of instance i equals the exactly rounded chain of
+    # `replays` iterations from (1, 2, 0) with its own q_i
+    expected = [exact_chain(1.0, 2.0, 0.0, float(q), replays) for q in qs]
+    exp_cols = [np.array([e[k] for e in expected]) for k in range(3)]
+
+    def chains_hold():
+        return all(int(batch.mismatch_count(tgt, k, exp_cols[k]).sum()) == 0 for k in range(3))
+
+    valid = chains_hold()
     # triad alone: one launch over all instances
-    t_ms = timed(lambda: batch.op(tgt, "triad"), triad_reps)
+    t_ms = timed_launches(ts, tgt, lambda: batch.op(tgt, "triad"), triad_reps)
     # comparison: one plain launch per instance (4096 launches per map)
-    p_ms = timed(lambda: batch.op_plain(tgt, "triad"), 5)
+    p_ms = timed_launches(ts, tgt, lambda: batch.op_plain(tgt, "triad"), 5)
     tb = 3 * total * es
+    # the triad-only launches recompute a from the same b and c: unchanged
+    valid_after = chains_hold()
     info = batch.info()
     out = {
         "instances": count, "total_elems": total, "device_bytes": 3 * total * es, "tiles": info["tiles"],
-        "tile_elems": info["tile_elems"], "valid_after_graph_replays": valid, "graph_replays": replays,
+        "tile_elems": info["tile_elems"], "valid_after_graph_replays": valid,
+        "valid_after_triad_launches": valid_after, "graph_replays": replays,
         "graph_iteration_ms": round(graph_ms, 4),
         "graph_iteration_GBps": round(10 * total * es / graph_ms / 1e6, 1),  # 2+2+3+3 arrays per element
         "triad_best_GBps": round(tb / min(t_ms) / 1e6, 1), "triad_avg_GBps": round(tb / (sum(t_ms) / len(t_ms)) / 1e6, 1),
@@ -277,12 +350,28 @@ def reduced_leg(ts, torch, tgt, n=1 << 28, reps=10, samples=1 << 14):
     return out
 
 
-def sweep_leg(ts, tgt, lo=16, hi=29):
-    """Size and alignment sweep: GB/s of back-to-back launches (about 2 ms of
-    work per measurement, so launch-bound sizes report throughput) for f64
-    and f32 arrays of 2^p elements, aligned and as 2^p + 7 elements one
-    element past an aligned base.  Regime by working set (3 arrays): L2
-    (<= 32 MiB over 8 XCDs), MALL (<= 256 MiB Infinity Cache), else HBM."""
+def timed_launches(ts, tgt, launch, reps):
+    """Milliseconds of each of `reps` launches enqueued back to back with a
+    timing-only event between consecutive ones (after one untimed launch),
+    so the device never waits for the host inside a measurement."""
+    ev = [ts.Event(timing=True) for _ in range(reps + 1)]
+    launch()
+    ev[0].record(tgt)
+    for i in range(reps):
+        launch()
+        ev[i + 1].record(tgt)
+    ev[-1].synchronize()
+    return [ev[i].elapsed_ms(ev[i + 1]) for i in range(reps)]
+
+
+def sweep_leg(ts, tgt, lo=16, hi=29, reps=20, b2b_below=22, b2b_reps=100):
+    """Size and alignment sweep for f64 and f32 arrays of 2^p elements,
+    aligned and as 2^p + 7 elements one element past an aligned base, seeded
+    inputs: per map, best and average GB/s over `reps` event-timed launches
+    after one warm-up; below 2^b2b_below elements also the rate of
+    `b2b_reps` launches between two events (launch-bound sizes).  Regime by
+    working set (3 arrays): L2 (<= 32 MiB over 8 XCDs), MALL (<= 256 MiB
+    Infinity Cache), else HBM."""
     out = {}
     for dtype in ("f64", "f32"):
         es = ts.ELEM_SIZE[dtype]
@@ -296,12 +385,15 @@ def sweep_leg(ts, tgt, lo=16, hi=29):
                 ws = 3 * n * es
                 row = {"working_set_MiB": round(ws / 2 ** 20, 2),
                        "regime": "L2" if ws <= 32 << 20 else ("MALL" if ws <= 256 << 20 else "HBM")}
-                for op, (x, y, d) in (("copy", (A, None, C)), ("triad", (B, C, A))):
+                for op, (x, y, d) in (("copy", (A, None, C)), ("scale", (C, None, B)), ("add", (A, B, C)),
+                                      ("triad", (B, C, A))):
                     b = ts.stream_bytes(op, n, dtype)
-                    reps = int(max(3, min(400, 2e-3 / (b / 6e12 + 4e-6))))
-                    ts.time_op(tgt, op, x, y, d, 3.0, reps=2)
-                    ms = ts.time_op(tgt, op, x, y, d, 3.0, reps=reps) / reps
-                    row[op + "_GBps"] = round(b / ms / 1e6, 1)
+                    ms = timed_launches(ts, tgt, lambda: ts.run_op(tgt, op, x, y, d, 3.0), reps)
+                    row[op + "_GBps"] = round(b / (sum(ms) / len(ms)) / 1e6, 1)
+                    row[op + "_best_GBps"] = round(b / min(ms) / 1e6, 1)
+                    if p < b2b_below:
+                        t = ts.time_op(tgt, op, x, y, d, 3.0, reps=b2b_reps) / b2b_reps
+                        row[op + "_b2b_GBps"] = round(b / t / 1e6, 1)
                 rows[f"2^{p}"] = row
                 for arr in (A, B, C):
                     arr.free()
@@ -365,14 +457,7 @@ def transform_leg(ts, tgt, n, reps=20):
     out = {}
     for name, fn in (("transform_fma_expression", lambda: tr(tgt, B, D, C, 3.0)),
                      ("tuned_triad_kernel", lambda: ts.triad(tgt, B, C, A, 3.0))):
-        ev = [ts.Event(timing=True) for _ in range(reps + 1)]
-        fn()
-        ev[0].record(tgt)
-        for i in range(reps):
-            fn()
-            ev[i + 1].record(tgt)
-        ev[-1].synchronize()
-        ms = [ev[i].elapsed_ms(ev[i + 1]) for i in range(reps)]
+        ms = timed_launches(ts, tgt, fn, reps)
         b = ts.stream_bytes("triad", n)
         out[name] = {"best_GBps": round(b / min(ms) / 1e6, 1), "avg_GBps": round(b / (sum(ms) / len(ms)) / 1e6, 1)}
     out["same_bits"] = ts.mismatch_count(tgt, A, D) == 0
@@ -437,7 +522,8 @@ def comparator_leg(ts, torch, n, reps=20):
 
 
 def host_cpu_info() -> dict:
-    """The host's CPU model, sockets, NUMA nodes and the CPUs this process may use."""
+    """The host's CPU model, sockets and NUMA nodes, and the CPUs this process
+    may use, with the physical cores they belong to (SMT siblings share one)."""
     info = {}
     try:
         model, sockets = None, set()
@@ -458,50 +544,80 @@ def host_cpu_info() -> dict:
                                   if d.startswith("node") and d[4:].isdigit()])
     except OSError:
         pass
-    try:
-        info["cpus_allowed"] = len(os.sched_getaffinity(0))
-    except AttributeError:
-        info["cpus_allowed"] = os.cpu_count()
+    allowed = allowed_cpus()
+    info["cpus_allowed"] = len(allowed)
     info["cpus_online"] = os.cpu_count()
+    cores = set()
+    for cpu in allowed:
+        topo = f"/sys/devices/system/cpu/cpu{cpu}/topology/"
+        try:
+            with open(topo + "physical_package_id") as f:
+                pkg = f.read().strip()
+            with open(topo + "core_id") as f:
+                core = f.read().strip()
+            cores.add((pkg, core))
+        except OSError:
+            cores = set()
+            break
+    if cores:
+        info["physical_cores_allowed"] = len(cores)
+        info["smt_threads_per_core"] = round(len(allowed) / len(cores), 2)
     return info
 
 
-def _oracle_timed(oracle, n, threads, target_seconds, max_iters):
+def allowed_cpus() -> list:
+    try:
+        return sorted(os.sched_getaffinity(0))
+    except AttributeError:
+        return list(range(os.cpu_count() or 1))
+
+
+def _oracle_timed(oracle, n, threads, target_seconds, max_iters, min_iters=2):
     """Iterations of the oracle's timed mode sized to about target_seconds;
-    returns (per-op seconds, final values, iterations, wall seconds)."""
+    returns (per-op seconds, final values, iterations, threads used, wall s)."""
     t0 = time.perf_counter()
     secs, _, _ = oracle.stream_timed_f64(n, 1, threads)
     one = float(secs.sum())
-    iters = int(max(2, min(max_iters, target_seconds / max(one, 1e-3))))
-    secs, fin, _ = oracle.stream_timed_f64(n, iters, threads)
-    return secs, fin, iters, time.perf_counter() - t0
+    iters = int(max(min_iters, min(max_iters, target_seconds / max(one, 1e-3))))
+    secs, fin, used = oracle.stream_timed_f64(n, iters, threads)
+    return secs, fin, iters, used, time.perf_counter() - t0
 
 
-def cpu_baseline_leg(n, target_seconds=10.0, single_seconds=3.0):
-    """The oracle's timed mode on the host (pinned threads, first touch), on
-    up to 16 threads and on one thread."""
-    import oracle
-    try:
-        cpus = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cpus = os.cpu_count() or 1
-    threads = max(1, min(16, cpus))
-    secs, fin, iters, spent = _oracle_timed(oracle, n, threads, target_seconds, 300)
-    exp = oracle.stream_scalar_f64(1.0, 2.0, 0.0, 3.0, iters)
-    ok = tuple(fin[:3]) == exp
-    per_iter = secs.sum(axis=1)  # seconds per iteration (4 maps)
+def _rates(secs, n):
+    """Aggregate GB/s over the iterations and best GB/s per map (STREAM bytes)."""
+    per_iter = secs.sum(axis=1)
     agg = 80 * n / per_iter.mean() / 1e9
-    best = {op: round(ts_bytes / secs[:, k].min() / 1e9, 2)
-            for k, (op, ts_bytes) in enumerate(zip(OPS, (16 * n, 16 * n, 24 * n, 24 * n)))}
-    s1, f1, it1, spent1 = _oracle_timed(oracle, n, 1, single_seconds, 50)
-    ok = ok and tuple(f1[:3]) == oracle.stream_scalar_f64(1.0, 2.0, 0.0, 3.0, it1)
-    return {"value": round(agg, 2), "unit": "GB/s", "cores": threads, "kind": "oracle",
+    best = {op: round(nb / secs[:, k].min() / 1e9, 2)
+            for k, (op, nb) in enumerate(zip(OPS, (16 * n, 16 * n, 24 * n, 24 * n)))}
+    return agg, best
+
+
+def cpu_baseline_leg(n, target_seconds=10.0, single_seconds=3.0, small_n=1 << 20, small_iters=10):
+    """The oracle's timed mode on the host (one pinned thread per CPU this
+    process may use, first touch): the headline size, the small plain
+    configuration (2^20 elements, 10 iterations, checked against STREAM's
+    closed form) and one thread at the headline size.  Every run's final
+    values must equal the exactly rounded chain."""
+    import oracle
+    threads = len(allowed_cpus())
+    secs, fin, iters, used, spent = _oracle_timed(oracle, n, threads, target_seconds, 300)
+    ok = tuple(fin[:3]) == exact_chain(1.0, 2.0, 0.0, 3.0, iters) and tuple(fin[3:]) == tuple(fin[:3])
+    agg, best = _rates(secs, n)
+    s_secs, s_fin, s_used = oracle.stream_timed_f64(small_n, small_iters, threads)
+    s_ok = tuple(s_fin[:3]) == (576650390625.0, 115330078125.0, 153773437500.0) == tuple(s_fin[3:])
+    s_agg, s_best = _rates(s_secs, small_n)
+    s1, f1, it1, _, spent1 = _oracle_timed(oracle, n, 1, single_seconds, 50)
+    ok = ok and tuple(f1[:3]) == exact_chain(1.0, 2.0, 0.0, 3.0, it1)
+    return {"value": round(agg, 2), "unit": "GB/s", "cores": used, "kind": "oracle",
             "sample": f"N=2^{n.bit_length()-1} f64 x3 arrays, {iters} iterations of copy/scale/add/triad, "
-                      f"{threads} pinned threads, first-touch blocks; {spent:.1f} s wall",
+                      f"{used} pinned threads (one per allowed CPU), first-touch blocks; {spent:.1f} s wall",
             "best_GBps_per_kernel": best,
+            "small_n2p20_k10": {"value": round(s_agg, 2), "unit": "GB/s", "threads": s_used,
+                                "best_GBps_per_kernel": s_best, "closed_form_exact": bool(s_ok),
+                                "regime": "24 MiB working set: host caches"},
             "one_thread": {"value": round(80 * n / s1.sum(axis=1).mean() / 1e9, 2), "unit": "GB/s",
                            "iterations": it1, "wall_s": round(spent1, 1)},
-            "host": host_cpu_info(), "valid": bool(ok)}
+            "host": host_cpu_info(), "valid": bool(ok and s_ok)}
 
 
 def host_target_leg(ts, n, threads, target_seconds=10.0):
@@ -526,8 +642,10 @@ def host_target_leg(ts, n, threads, target_seconds=10.0):
             ms = ts.time_op(tgt, op, x, y, d, 3.0, reps=1)
             best[op] = min(best[op], ms)
             total += ms
-    # every element followed the same chain; then STREAM's closed form
-    valid = uniform_arrays(ts, tgt, (A, B, C)) and closed_form_check(ts, tgt, A, B, C)
+    # the warm-up and the timed iterations follow the exactly rounded chain;
+    # then the 50-iteration fused-triad run
+    valid = (chain_check(ts, tgt, (A, B, C), exact_chain(1.0, 2.0, 0.0, 3.0, iters + 1))
+             and fused_chain_check(ts, tgt, A, B, C, 50))
     for arr in (A, B, C):
         arr.free()
     tgt.close()
@@ -560,11 +678,12 @@ def metric_records(result: dict) -> list[dict]:
             if not isinstance(row, dict):
                 continue
             p = int(size.split("^")[1])
-            for op in ("copy", "triad"):
+            for op in OPS:
                 if f"{op}_GBps" in row:
                     recs.append({"config": "C3", "op": op, "dtype": dtype, "n": (1 << p) + (0 if align == "aligned" else 7),
-                                 "offset": 0 if align == "aligned" else 1, "GBps_best": row[f"{op}_GBps"],
-                                 "regime": row.get("regime"), "host": host, "ndev": 1})
+                                 "offset": 0 if align == "aligned" else 1, "GBps_avg": row[f"{op}_GBps"],
+                                 "GBps_best": row.get(f"{op}_best_GBps"), "regime": row.get("regime"),
+                                 "host": host, "ndev": 1})
     for dtype, ops in result.get("reduced_precision", {}).items():
         if not isinstance(ops, dict):
             continue
@@ -623,7 +742,8 @@ def main():
     log(f"main leg: f64 N={a.n}, warmup={a.warmup}, steps={a.steps}")
     m = main_leg(ts, torch, tgt, a.n, a.steps, a.warmup, a.order)
     if not m["valid"]:
-        print("validation failed: arrays not uniform, or the closed-form run differs", file=sys.stderr)
+        print("validation failed: the timed arrays or the 50-iteration run differ from the exactly rounded chain",
+              file=sys.stderr)
         sys.exit(1)
     k = m["kernels"]
     step_bytes = sum(k[op]["bytes"] for op in OPS)
@@ -649,23 +769,21 @@ def main():
                    "init": "a=1,b=2,c=0 (device fill)",
                    "order": "copy c=a,scale,add,triad" if a.order == "listing" else "copy a=b,scale,add,triad",
                    "bytes_per_step": step_bytes},
-        "triad_best_GBps": tri["best_GBps"],
-        "triad_pct_peak_best": tri["pct_peak_best"],
-        "copy_best_GBps": k["copy"]["best_GBps"],
-        "copy_pct_peak_best": k["copy"]["pct_peak_best"],
-        "per_kernel": k,
         "host_wall_ms_per_step": round(1e3 * m["wall_s"] / a.steps, 5),
-        "validated": "all elements of a, b, c equal element 0 bit for bit; a 10-iteration run matches "
-                     "STREAM's closed form exactly",
+        "validated": (f"every element of a, b, c after the {a.warmup} + {a.steps} steps equals the exactly rounded "
+                      "chain; a 50-iteration run from (1, 2, 0) in the same launch shapes equals the chain with a "
+                      "fused triad (an unfused one differs)"),
+        "kernel_source_digest": kernel_source_digest(),
+        "device": {"arch": info["arch"], "compute_units": info["compute_units"], "hbm_bytes": info["hbm_bytes"]},
+        "per_kernel": k,
         "roofline": {"bound": "hbm", "kernel": "triad f64", "achieved": round(achieved, 1), "peak": PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_GBPS, 4),
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": tri["bytes"]},
-        "kernel_source_digest": kernel_source_digest(),
-        "device": {"arch": info["arch"], "compute_units": info["compute_units"], "hbm_bytes": info["hbm_bytes"]},
     }
     if not a.quick:
-        for name, fn in (("batched", lambda: batched_leg(ts, torch, tgt)),
+        for name, fn in (("ceiling", lambda: ceiling_leg(ts, tgt, a.n)),
+                         ("batched", lambda: batched_leg(ts, torch, tgt)),
                          ("reduced_precision", lambda: reduced_leg(ts, torch, tgt)),
                          ("sweep", lambda: sweep_leg(ts, tgt)),
                          ("launch_overhead", lambda: overhead_leg(ts, torch, tgt)),
@@ -696,11 +814,73 @@ def main():
             except Exception as e:
                 result["host_target"] = {"error": f"{type(e).__name__}: {e}"}
     tgt.close()
+    result["valid"] = {"timed_arrays": m["valid_timed_arrays"], "k50_fused_chain": m["valid_k50_fused_chain"]}
+    result = order_for_output(result)
     if a.jsonl:
         with open(a.jsonl, "a") as f:
             for rec in metric_records(result):
                 f.write(json.dumps(rec) + "\n")
+    log(summary_text(result["summary"]))
     print(json.dumps(result))
+
+
+TAIL_KEYS = ("per_kernel", "roofline", "cpu_baseline")
+
+
+def summary(result: dict) -> dict:
+    """The metric's figures in one small object: per-map best and average
+    GB/s with % of peak, the ceilings the maps run against, the batched
+    triad against the plain one, the graph iteration, the checks and the CPU
+    baseline."""
+    k = result["per_kernel"]
+    s = {op: {"best_GBps": k[op]["best_GBps"], "avg_GBps": k[op]["avg_GBps"], "pct_best": k[op]["pct_peak_best"],
+              "pct_avg": k[op]["pct_peak_avg"]} for op in OPS}
+    ceil = result.get("ceiling", {})
+    if "triad_2r1w" in ceil:
+        s["ceiling_avg_GBps"] = {name: ceil[name]["avg_GBps"] for name, _, _ in PROBE_KINDS if name in ceil}
+        s["triad_avg_vs_2r1w_ceiling"] = round(k["triad"]["avg_GBps"] / ceil["triad_2r1w"]["avg_GBps"], 4)
+        s["copy_avg_vs_1r1w_ceiling"] = round(k["copy"]["avg_GBps"] / ceil["copy_1r1w"]["avg_GBps"], 4)
+    b = result.get("batched", {})
+    if "triad_best_GBps" in b:
+        s["batched"] = {"triad_best_GBps": b["triad_best_GBps"], "triad_avg_GBps": b["triad_avg_GBps"],
+                        "triad_vs_plain_triad_best": b.get("triad_vs_plain_n2p27_triad"),
+                        "graph_iteration_GBps": b["graph_iteration_GBps"],
+                        "valid": bool(b["valid_after_graph_replays"] and b["valid_after_triad_launches"])}
+    s["valid"] = result["valid"]
+    cb = result.get("cpu_baseline", {})
+    if "value" in cb:
+        s["cpu_baseline"] = {"GBps": cb["value"], "threads": cb["cores"], "valid": cb["valid"]}
+    return s
+
+
+def order_for_output(result: dict) -> dict:
+    """The JSON line's keys in reading order: the contract's fields, the
+    extra legs, then per-kernel figures, roofline, CPU baseline and the
+    summary last (the end of the line survives truncation)."""
+    out = {key: v for key, v in result.items() if key not in TAIL_KEYS}
+    for key in TAIL_KEYS:
+        if key in result:
+            out[key] = result[key]
+    out["summary"] = summary(result)
+    return out
+
+
+def summary_text(s: dict) -> str:
+    parts = [f"{op} {s[op]['best_GBps']:.0f}/{s[op]['avg_GBps']:.0f} GB/s best/avg ({s[op]['pct_avg']:.1f}% avg)"
+             for op in OPS]
+    lines = ["summary: " + "; ".join(parts)]
+    if "ceiling_avg_GBps" in s:
+        lines.append("ceilings (avg GB/s): " + ", ".join(f"{k} {v:.0f}" for k, v in s["ceiling_avg_GBps"].items())
+                     + f"; triad/2r1w {s['triad_avg_vs_2r1w_ceiling']:.3f}, copy/1r1w {s['copy_avg_vs_1r1w_ceiling']:.3f}")
+    if "batched" in s:
+        b = s["batched"]
+        lines.append(f"batched triad {b['triad_best_GBps']:.0f}/{b['triad_avg_GBps']:.0f} GB/s "
+                     f"({b['triad_vs_plain_triad_best']}x plain), graph iteration {b['graph_iteration_GBps']:.0f} GB/s, "
+                     f"valid {b['valid']}")
+    lines.append(f"valid {s['valid']}")
+    if "cpu_baseline" in s:
+        lines.append(f"cpu baseline {s['cpu_baseline']['GBps']:.1f} GB/s on {s['cpu_baseline']['threads']} threads")
+    return "\n".join(lines)
 
 
 if __name__ == "__main__":

@@ -335,6 +335,44 @@ TS_API int ts_tune_cache_clear(void);
 TS_API int ts_time_op(ts_target exec, ts_op op, ts_array x, ts_array y,
                       ts_array dst, double q, int reps, float *ms_total);
 
+/* Memory-system probe (a measurement tool, not one of the paper's
+ * algorithms).  Section 5 reads STREAM as the memory bandwidth that the
+ * implementation attains; this launch measures what the memory system
+ * itself delivers for a given mix of traffic, so the maps can be judged
+ * against it: a straight-line kernel over 16-byte vectors that reads
+ * `reads` arrays (0, 1: x, or 2: x and y) and writes `writes` arrays
+ * (0 or 1: dst), with no arithmetic beyond a bitwise fold.
+ *   reads 1, writes 1: dst = x (bits);  reads 2, writes 1: dst = x XOR y;
+ *   reads 0, writes 1: every 32-bit word of dst = `mark`;
+ *   writes 0: each lane folds what it reads by XOR and stores the fold into
+ *   dst only when its first word equals `mark`, so the first bytes/unroll
+ *   bytes of dst are unspecified afterwards.
+ * The first `bytes` bytes of each operand take part: `bytes` must be a
+ * positive multiple of 16 * cfg->block * cfg->unroll (TS_E_SHAPE), every
+ * operand must start on a 16-byte boundary (TS_E_SHAPE), hold at least
+ * `bytes` bytes (TS_E_SHAPE) and lie on the executor's device
+ * (TS_E_PLACEMENT); operands of any storage type; dst must not overlap an
+ * input (TS_E_ALIAS); y is ignored unless reads == 2, x unless reads >= 1.
+ * One launch of bytes / (16 * block * unroll) workgroups, asynchronous on
+ * the executor's stream; GPU targets only (TS_E_UNSUPPORTED on a host
+ * target). */
+typedef struct {
+    int32_t reads;           /* 0, 1 or 2 (writes + reads >= 1)               */
+    int32_t writes;          /* 0 or 1 (reads 0 needs writes 1)               */
+    int32_t block;           /* lanes per workgroup: 64..1024, multiple of 64 */
+    int32_t unroll;          /* 16-byte vectors per lane: 1, 2 or 4           */
+    int32_t nt_load;         /* 1: nontemporal loads                          */
+    int32_t nt_store;        /* 1: nontemporal stores                         */
+    int32_t wave_contiguous; /* 1: each wave covers unroll*1 KiB in a row;
+                                0: a lane's vectors lie a workgroup apart    */
+    int32_t lds_bytes;       /* dynamic LDS per workgroup, 0..the device's
+                                LDS per CU: caps the workgroups resident on
+                                a CU (0: no cap)                             */
+} ts_probe_cfg;
+TS_API int ts_probe_bandwidth(ts_target exec, const ts_probe_cfg *cfg,
+                              ts_array x, ts_array y, ts_array dst,
+                              size_t bytes, uint32_t mark);
+
 /* ------------------------------------------------------------------------ */
 /* Batched ragged instances: one launch per map over all instances          */
 /* ------------------------------------------------------------------------ */

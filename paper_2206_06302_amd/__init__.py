@@ -24,7 +24,7 @@ import numpy as np
 import torch  # must load first: libtstream then binds to torch's HIP runtime
 
 from . import _lib
-from ._lib import BatchDescC, ChecksumOut, DeviceInfo, KernelCfg
+from ._lib import BatchDescC, ChecksumOut, DeviceInfo, KernelCfg, ProbeCfg
 
 lib = _lib.load()
 
@@ -355,6 +355,17 @@ def time_op(target: Target, op, x: Array, y: Array | None, dst: Array, q: float 
     _check(lib.ts_time_op(target.handle, _op(op), x.handle, y.handle if y is not None else None,
                           dst.handle, float(q), int(reps), ctypes.byref(ms)))
     return float(ms.value)
+
+
+def probe_bandwidth(target: Target, cfg: dict, x: Array | None, y: Array | None, dst: Array, nbytes: int,
+                    mark: int = 0x5A5A5A5A) -> None:
+    """One launch of the memory-system probe (ts_probe_bandwidth): cfg keys
+    reads, writes, block, unroll, nt_load, nt_store, wave_contiguous,
+    lds_bytes.  Asynchronous on the target's stream."""
+    c = ProbeCfg.from_dict(cfg)
+    _check(lib.ts_probe_bandwidth(target.handle, ctypes.byref(c), x.handle if x is not None else None,
+                                  y.handle if y is not None else None, dst.handle, int(nbytes),
+                                  int(mark) & 0xFFFFFFFF))
 
 
 # ---------------------------------------------------------------------------

@@ -41,6 +41,26 @@ class KernelCfg(ctypes.Structure):
         return c
 
 
+class ProbeCfg(ctypes.Structure):
+    _fields_ = [
+        ("reads", ctypes.c_int32),
+        ("writes", ctypes.c_int32),
+        ("block", ctypes.c_int32),
+        ("unroll", ctypes.c_int32),
+        ("nt_load", ctypes.c_int32),
+        ("nt_store", ctypes.c_int32),
+        ("wave_contiguous", ctypes.c_int32),
+        ("lds_bytes", ctypes.c_int32),
+    ]
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "ProbeCfg":
+        c = cls()
+        for f, _ in cls._fields_:
+            setattr(c, f, int(d.get(f, 0)))
+        return c
+
+
 class DeviceInfo(ctypes.Structure):
     _fields_ = [
         ("device", ctypes.c_int),
@@ -126,6 +146,7 @@ PROTOTYPES = {
     "ts_tune_cache_save": [ctypes.c_char_p],
     "ts_tune_cache_clear": [],
     "ts_time_op": [H, I, H, H, H, D, I, ctypes.POINTER(F)],
+    "ts_probe_bandwidth": [H, ctypes.POINTER(ProbeCfg), H, H, H, SZ, ctypes.c_uint32],
     "ts_batch_create": [H, I, ctypes.POINTER(BatchDescC), SZ, ctypes.POINTER(H)],
     "ts_batch_destroy": [H],
     "ts_batch_info": [H, ctypes.POINTER(SZ), ctypes.POINTER(U64), ctypes.POINTER(U64), ctypes.POINTER(I64)],

@@ -28,8 +28,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtstream.so")
 ARCH = os.environ.get("TS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["kern_f64.hip", "kern_f32.hip", "kern_bf16.hip", "kern_f16.hip", "kern_aux.hip",
-           "capi.cpp", "capi_tune.cpp", "capi_batch.cpp", "capi_async.cpp", "tune.cpp", "host_target.cpp",
+SOURCES = ["kern_f64.hip", "kern_f32.hip", "kern_bf16.hip", "kern_f16.hip", "kern_aux.hip", "kern_probe.hip",
+           "capi.cpp", "capi_probe.cpp", "capi_tune.cpp", "capi_batch.cpp", "capi_async.cpp", "tune.cpp", "host_target.cpp",
            "transform.cpp", "host_transform.cpp"]
 
 COMMON = [

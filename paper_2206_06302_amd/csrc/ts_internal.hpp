@@ -32,6 +32,18 @@ struct BatchLaunch {
   hipStream_t stream;
 };
 
+// Arguments of one memory-system probe launch (kern_probe.hip): grid * block
+// * unroll 16-byte vectors of each array involved.
+struct ProbeLaunch {
+  const void* x;
+  const void* y;
+  void* d;
+  uint32_t grid, block, lds_bytes, mark;
+  int reads, writes, unroll, ntl, nts, wave_contiguous;
+  hipStream_t stream;
+};
+hipError_t launch_probe(const ProbeLaunch& L);
+
 // Per-format dispatch of the STREAM kernels (kern_<fmt>.hip).
 hipError_t plain_launch_f64(const PlainLaunch& L);
 hipError_t plain_launch_f32(const PlainLaunch& L);

@@ -1,6 +1,7 @@
 """Host logic of bench.py that needs no GPU: argument checks, the exact
 integer closed forms it validates against, and the metric records."""
 import os
+import struct
 import subprocess
 import sys
 
@@ -12,13 +13,66 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-def test_closed_forms_are_the_integer_recurrences():
-    # listing order: a = 15^k, b = 3*15^(k-1), c = 4*15^(k-1)
+def _bits(x: float) -> int:
+    return struct.unpack("<Q", struct.pack("<d", x))[0]
+
+
+def test_exact_chain_closed_forms():
+    # listing order: a = 15^k, b = 3*15^(k-1), c = 4*15^(k-1), exact below 2^53
     for k in range(1, 14):
-        assert bench.expected_integers("listing", k) == (15.0 ** k, 3.0 * 15 ** (k - 1), 4.0 * 15 ** (k - 1))
-    assert bench.expected_integers("copy_b", 10) == (1015254.0, 211896.0, 267786.0)
-    with pytest.raises(AssertionError):  # beyond 2^53 the integers are not exact
-        bench.expected_integers("listing", 14)
+        assert bench.exact_chain(1.0, 2.0, 0.0, 3.0, k) == (15.0 ** k, 3.0 * 15 ** (k - 1), 4.0 * 15 ** (k - 1))
+    assert bench.exact_chain(1.0, 2.0, 0.0, 3.0, 10, "copy_b") == (1015254.0, 211896.0, 267786.0)
+    assert bench.exact_chain(1.0, 2.0, 0.0, 3.0, 21, "copy_b") == (2361723449706.0, 492920384850.0, 622934354952.0)
+
+
+def test_exact_chain_tells_a_fused_triad_from_an_unfused_one():
+    """The 50-iteration check of the benchmark: the chain's bits with one
+    rounding in the triad, and the unfused chain differs in a."""
+    a, b, c = bench.exact_chain(1.0, 2.0, 0.0, 3.0, 50)
+    assert (_bits(a), _bits(b), _bits(c)) == (0x4C2450D7D0D568D7, 0x4C0040ACA71120AC, 0x4C05AB90DEC180E5)
+    au, bu, cu = bench.exact_chain(1.0, 2.0, 0.0, 3.0, 50, fused=False)
+    assert (_bits(au), _bits(bu), _bits(cu)) == (0x4C2450D7D0D568D6, 0x4C0040ACA71120AB, 0x4C05AB90DEC180E4)
+    # at 21 iterations (one warm-up plus 20 timed) both agree: 21 alone could not tell
+    assert bench.exact_chain(1.0, 2.0, 0.0, 3.0, 21) == bench.exact_chain(1.0, 2.0, 0.0, 3.0, 21, fused=False)
+
+
+def test_exact_chain_equals_the_oracle(oracle_lib):
+    """Per-instance q of the batched workload and K up to 80: the helper
+    reproduces the oracle's chain (std fma) bit for bit; past binary64's range
+    every value is infinite."""
+    import numpy as np
+
+    import tsgen
+    qs = list(tsgen.batched_scalars(5, 64)) + [3.0, 0.5, 4.0]
+    for q in qs:
+        for k in (1, 7, 21, 50, 80):
+            assert bench.exact_chain(1.0, 2.0, 0.0, float(q), k) == oracle_lib.stream_scalar_f64(1.0, 2.0, 0.0, float(q), k)
+    assert bench.exact_chain(1.0, 2.0, 0.0, 3.0, 300) == (float("inf"),) * 3
+    assert oracle_lib.stream_scalar_f64(1.0, 2.0, 0.0, 3.0, 300) == (float("inf"),) * 3
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(4000) * np.exp2(rng.integers(-60, 60, 4000))
+    y = rng.standard_normal(4000) * np.exp2(rng.integers(-60, 60, 4000))
+    d = np.zeros_like(x)
+    oracle_lib.op(oracle_lib.F64, oracle_lib.TRIAD, x, y, d, 3.0)
+    assert all(bench._fma(3.0, float(yv), float(xv)) == dv for xv, yv, dv in zip(x, y, d))
+
+
+def test_summary_is_the_last_key():
+    kernel = {"best_GBps": 6500.0, "avg_GBps": 6400.0, "pct_peak_best": 81.25, "pct_peak_avg": 80.0, "bytes": 1,
+              "best_ms": 1.0, "avg_ms": 1.0, "cfg": {}}
+    result = {"metric": "m", "value": 1.0, "per_kernel": {op: dict(kernel) for op in bench.OPS},
+              "roofline": {"frac": 0.8}, "valid": {"timed_arrays": True, "k50_fused_chain": True},
+              "ceiling": {name: {"avg_GBps": 6600.0} for name, _, _ in bench.PROBE_KINDS},
+              "batched": {"triad_best_GBps": 6300.0, "triad_avg_GBps": 6290.0, "triad_vs_plain_n2p27_triad": 0.97,
+                          "graph_iteration_GBps": 6200.0, "valid_after_graph_replays": True,
+                          "valid_after_triad_launches": True},
+              "cpu_baseline": {"value": 250.0, "cores": 16, "valid": True}, "sweep": {}}
+    out = bench.order_for_output(result)
+    keys = list(out)
+    assert keys[-4:] == ["per_kernel", "roofline", "cpu_baseline", "summary"] and keys[:2] == ["metric", "value"]
+    s = out["summary"]
+    assert s["triad_avg_vs_2r1w_ceiling"] == round(6400 / 6600, 4) and s["batched"]["valid"] is True
+    assert "triad 6500/6400" in bench.summary_text(s)
 
 
 @pytest.mark.parametrize("args,code,text", [(["--gpus", "2"], 2, "exactly one GPU"),
