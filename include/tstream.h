@@ -264,6 +264,29 @@ typedef struct {
  * Blocking.  The sums differ from a sequential sum only by rounding order. */
 TS_API int ts_checksum(ts_target exec, ts_array x, double expected,
                        ts_checksum_out *out);
+/* Allocation-free form of ts_checksum, for callers that cannot allocate
+ * device or pinned memory while they run (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same two kernels
+ * and the same reduction tree as ts_checksum, so the four results are
+ * bitwise identical to ts_checksum's for the same array.
+ *   dev_out: device memory of the target's GPU (caller-owned, 8-byte
+ *            aligned, room for one ts_checksum_out, not overlapping x); the
+ *            result is written there in stream order on the target's
+ *            stream.  The call does not wait: synchronise the target (or
+ *            order later work on its stream) before reading dev_out.
+ * The partial sums live in a fixed device array of 8192 parts of 32 bytes
+ * (256 KiB) per GPU, loaded with the library and held until the process
+ * ends; its address is resolved when a target is created on that GPU.  A
+ * reduction of any length uses at most 8192 parts, so no n is refused for
+ * scratch size (the check stays, TS_E_SHAPE).  The call makes no hipMalloc,
+ * hipHostMalloc, hipFree or hipMemset and does not synchronise.  Every call on
+ * one GPU shares that array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.
+ * GPU targets only (TS_E_UNSUPPORTED on a host target); TS_E_PLACEMENT if
+ * dev_out is not device memory of the target's GPU; TS_E_ALIAS if it
+ * overlaps x.  An empty array stores {0, 0, 0, 0}. */
+TS_API int ts_checksum_noalloc(ts_target exec, ts_array x, double expected,
+                               ts_checksum_out *dev_out);
 /* Number of j < n(x) with stored bits of x[j] != ref[j] (NaN matches NaN).
  * ref must hold n(x) elements of the same type.  Blocking. */
 TS_API int ts_mismatch_count(ts_target exec, ts_array x, ts_array ref,

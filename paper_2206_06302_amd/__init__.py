@@ -342,6 +342,13 @@ def checksum(target: Target, x: Array, expected: float) -> dict:
             "mismatches": int(out.mismatches)}
 
 
+def checksum_noalloc(target: Target, x: Array, expected: float, dev_out: int) -> None:
+    """ts_checksum_noalloc: enqueue the checksum of x with its result stored
+    at the device address dev_out (32 bytes: sum, abs_dev_sum, max_abs_dev as
+    binary64, then mismatches as uint64).  Does not wait."""
+    _check(lib.ts_checksum_noalloc(target.handle, x.handle, float(expected), ctypes.c_void_p(int(dev_out))))
+
+
 def mismatch_count(target: Target, x: Array, ref: Array) -> int:
     out = ctypes.c_uint64()
     _check(lib.ts_mismatch_count(target.handle, x.handle, ref.handle, ctypes.byref(out)))

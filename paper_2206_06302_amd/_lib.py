@@ -136,6 +136,7 @@ PROTOTYPES = {
     "ts_triad": [H, H, H, H, D],
     "ts_stream_iteration": [H, H, H, H, D],
     "ts_checksum": [H, H, D, ctypes.POINTER(ChecksumOut)],
+    "ts_checksum_noalloc": [H, H, D, ctypes.c_void_p],
     "ts_mismatch_count": [H, H, H, ctypes.POINTER(U64)],
     "ts_get_kernel_cfg": [I, I, SZ, I, I, ctypes.POINTER(KernelCfg)],
     "ts_set_kernel_cfg": [I, I, I, ctypes.POINTER(KernelCfg)],

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -319,7 +320,11 @@ int create_target(int device, void* hip_stream, bool owned, ts_target* out) {
     }
     t->owns_stream = true;
   }
-  hipError_t e = hipMalloc(&t->scratch, kReduceScratchBytes);
+  // Set-up of the allocation-free checksum on this device (current here):
+  // resolve its fixed array's address once, so later calls only look it up.
+  CsPart* fixed_parts = nullptr;
+  hipError_t e = noalloc_parts(device, &fixed_parts);
+  if (e == hipSuccess) e = hipMalloc(&t->scratch, kReduceScratchBytes);
   if (e == hipSuccess) e = hipHostMalloc(&t->host_result, sizeof(CsPart), hipHostMallocDefault);
   if (e != hipSuccess) {
     if (t->scratch) (void)hipFree(t->scratch);
@@ -750,6 +755,42 @@ int ts_checksum(ts_target t, ts_array x, double expected, ts_checksum_out* out) 
   TS_HIP(hipStreamSynchronize(t->stream));
   const CsPart* h = static_cast<const CsPart*>(t->host_result);
   *out = ts_checksum_out{h->sum, h->absdev, h->maxdev, h->mism};
+  return TS_OK;
+  TS_GUARD_END
+}
+
+static_assert(sizeof(ts_checksum_out) == sizeof(CsPart) && offsetof(ts_checksum_out, sum) == offsetof(CsPart, sum) &&
+                  offsetof(ts_checksum_out, abs_dev_sum) == offsetof(CsPart, absdev) &&
+                  offsetof(ts_checksum_out, max_abs_dev) == offsetof(CsPart, maxdev) &&
+                  offsetof(ts_checksum_out, mismatches) == offsetof(CsPart, mism),
+              "the reduction kernel stores its result straight into a ts_checksum_out");
+
+int ts_checksum_noalloc(ts_target t, ts_array x, double expected, ts_checksum_out* dev_out) {
+  TS_GUARD_BEGIN
+  if (!ok_target(t) || !ok_array(x) || !dev_out) return fail(TS_E_INVALID, "invalid handle or NULL dev_out");
+  if (t->host) return host_only_gpu("ts_checksum_noalloc");
+  if (!map_dtype(x->dtype)) return fail(TS_E_UNSUPPORTED, "checksums take floating-point storage");
+  if (x->device != t->device) return fail(TS_E_PLACEMENT, "array is not on the executor's device");
+  if (reinterpret_cast<uintptr_t>(dev_out) % alignof(ts_checksum_out))
+    return fail(TS_E_INVALID, "dev_out must be aligned to %zu bytes", alignof(ts_checksum_out));
+  int st = use_device(t->device);
+  if (st != TS_OK) return st;
+  // Pointer queries only: nothing here allocates.
+  if ((st = check_device_range(t->device, dev_out, 1, sizeof(ts_checksum_out), "dev_out")) != TS_OK) return st;
+  const uintptr_t xo = reinterpret_cast<uintptr_t>(x->ptr), o = reinterpret_cast<uintptr_t>(dev_out);
+  const uint64_t xbytes = x->n * dtype_size(x->dtype);
+  if (o < xo + xbytes && xo < o + sizeof(ts_checksum_out))
+    return fail(TS_E_ALIAS, "dev_out overlaps the array being reduced");
+  const uint32_t np = reduce_parts(x->n);
+  if (np > kNoallocParts)
+    return fail(TS_E_SHAPE, "the reduction needs %u parts; the fixed array holds %u", np, kNoallocParts);
+  CsPart* parts = nullptr;
+  hipError_t e = noalloc_parts(t->device, &parts);
+  if (e != hipSuccess) return hip_fail(e, "address of the fixed checksum array");
+  CsPart* res = reinterpret_cast<CsPart*>(dev_out);
+  e = x->n == 0 ? launch_store_part(res, CsPart{0.0, 0.0, 0.0, 0ull}, t->stream)
+                : launch_checksum_to(x->dtype, x->ptr, x->n, expected, parts, res, t->stream);
+  if (e != hipSuccess) return hip_fail(e, "checksum kernel launch");
   return TS_OK;
   TS_GUARD_END
 }

@@ -5,10 +5,19 @@
 // (Section 3.2, Listing 1's bulk_construct; Section 4.2).  The uniform fill
 // is SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) evaluated at a counter,
 // so any element can be regenerated alone.
+#include <mutex>
+
 #include "ts_device.hpp"
 #include "ts_internal.hpp"
 
 namespace ts {
+
+// Reduction parts of the allocation-free checksum (ts_checksum_noalloc): one
+// fixed array per GPU, loaded with the library's code object and held until
+// the process ends.  Host code never passes this name to a kernel (on the
+// host it is only a stand-in for the symbol); it resolves the array's
+// device address once per device (noalloc_parts) and passes that.
+static __device__ __align__(256) CsPart noalloc_scratch[kNoallocParts];
 
 namespace {
 
@@ -363,6 +372,10 @@ __global__ __launch_bounds__(256) void zero_u64_kernel(unsigned long long* p, ui
     p[j] = 0ull;
 }
 
+__global__ void store_part_kernel(CsPart* out, CsPart v) {
+  if (threadIdx.x == 0) *out = v;
+}
+
 uint32_t fill_grid(uint64_t n) {
   const uint64_t g = (n + 255) / 256;
   return static_cast<uint32_t>(g < 1 ? 1 : (g > 65536 ? 65536 : g));
@@ -425,9 +438,8 @@ hipError_t launch_fill_uniform(int dt, void* p, uint64_t n, uint64_t seed, uint6
                first_index, lo, w, head, nvec)
 }
 
-hipError_t launch_checksum(int dt, const void* x, uint64_t n, double expected, void* scratch,
-                           hipStream_t s) {
-  CsPart* parts = static_cast<CsPart*>(scratch);
+hipError_t launch_checksum_to(int dt, const void* x, uint64_t n, double expected, CsPart* parts, CsPart* out,
+                              hipStream_t s) {
   const uint32_t np = reduce_parts(n);
   switch (dt) {
     case DT_F64: hipLaunchKernelGGL(checksum_pass1<DT_F64>, dim3(np), dim3(kReduceBlock), 0, s, x, n, expected, parts, np); break;
@@ -438,8 +450,39 @@ hipError_t launch_checksum(int dt, const void* x, uint64_t n, double expected, v
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(reduce_pass2, dim3(1), dim3(kReduceBlock), 0, s, parts, np, parts + kReduceMaxParts);
+  hipLaunchKernelGGL(reduce_pass2, dim3(1), dim3(kReduceBlock), 0, s, parts, np, out);
   return hipGetLastError();
+}
+
+hipError_t launch_checksum(int dt, const void* x, uint64_t n, double expected, void* scratch,
+                           hipStream_t s) {
+  CsPart* parts = static_cast<CsPart*>(scratch);
+  return launch_checksum_to(dt, x, n, expected, parts, parts + kReduceMaxParts, s);
+}
+
+hipError_t launch_store_part(CsPart* out, const CsPart& v, hipStream_t s) {
+  hipLaunchKernelGGL(store_part_kernel, dim3(1), dim3(64), 0, s, out, v);
+  return hipGetLastError();
+}
+
+hipError_t noalloc_parts(int device, CsPart** out) {
+  static std::mutex mu;
+  static CsPart* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = static_cast<CsPart*>(p);
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_mismatch(int dt, const void* x, const void* ref, uint64_t n, void* scratch,

@@ -70,6 +70,12 @@ uint32_t reduce_parts(uint64_t n);
 // Device scratch a target needs for one reduction: parts plus the result.
 constexpr size_t kReduceScratchBytes = (kReduceMaxParts + 1) * sizeof(CsPart);
 
+// Parts held by the fixed per-GPU array of the allocation-free checksum: as
+// many as a reduction of any length uses, so it never limits n.
+constexpr uint32_t kNoallocParts = kReduceMaxParts;
+// Devices whose fixed array's address is cached.
+constexpr int kMaxDevices = 64;
+
 hipError_t launch_fill_const(int dt, void* p, uint64_t n, double value, hipStream_t s);
 // Element j: lo + w * u01(first_index + j + 1), narrowed to the storage type.
 hipError_t launch_fill_uniform(int dt, void* p, uint64_t n, uint64_t seed, uint64_t stream_id,
@@ -77,6 +83,15 @@ hipError_t launch_fill_uniform(int dt, void* p, uint64_t n, uint64_t seed, uint6
 // Leaves the reduced CsPart at scratch + kReduceMaxParts parts.
 hipError_t launch_checksum(int dt, const void* x, uint64_t n, double expected, void* scratch,
                            hipStream_t s);
+// The same two passes with the parts and the result wherever the caller says.
+hipError_t launch_checksum_to(int dt, const void* x, uint64_t n, double expected, CsPart* parts, CsPart* out,
+                              hipStream_t s);
+// One kernel that stores v at *out (the result of an empty reduction).
+hipError_t launch_store_part(CsPart* out, const CsPart& v, hipStream_t s);
+// Device address, on `device`, of the allocation-free checksum's fixed array
+// of kNoallocParts parts.  Resolved once per device; `device` must be the
+// calling thread's current device on that first call.  Allocates nothing.
+hipError_t noalloc_parts(int device, CsPart** out);
 // Leaves the count in the `mism` field of the part after kReduceMaxParts.
 hipError_t launch_mismatch(int dt, const void* x, const void* ref, uint64_t n, void* scratch,
                            hipStream_t s);
