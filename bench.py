@@ -46,8 +46,9 @@ if ROOT not in sys.path:
 METRIC = "STREAM Triad/Copy GB/s and % of HBM peak, FP64 N=2^27; batched vs plain"
 PEAK_GBPS = 8000.0
 OPS = ("copy", "scale", "add", "triad")
-EXTRA_LEGS = ("ceiling", "batched", "reduced_precision", "sweep", "launch_overhead", "comparators", "transform")
-PROFILE_PMC = os.path.join(ROOT, "profiles", "triad_f64_n2p27_pmc.md")
+EXTRA_LEGS = ("calibration", "ceiling", "batched", "reduced_precision", "sweep", "launch_overhead", "comparators",
+              "transform")
+PROFILE_PMC = os.path.join(ROOT, "profiles", "stream_f64_n2p27_pmc.md")
 
 
 def kernel_source_digest() -> str:
@@ -233,8 +234,36 @@ def ceiling_leg(ts, tgt, n, reps=20):
     return out
 
 
-def batched_leg(ts, torch, tgt, count=4096, seed=5, replays=50, triad_reps=20):
-    """Batched ragged triad and the graph-captured iteration vs plain launches."""
+CALIBRATION_SHAPE = {"block": 512, "unroll": 1, "wave_contiguous": 0, "nt_load": 1, "nt_store": 1, "lds_bytes": 0}
+
+
+def calibration_leg(ts, tgt, n, reps=3):
+    """Probe launches of exactly known traffic, for reading the hardware
+    counters: over n binary64 elements per array, the straight-line probe
+    reads one array (read_1r), writes one (write_1w), or reads one and writes
+    another (copy_1r1w), in one fixed shape.  The read-only probe stores
+    nothing unless a lane's fold of its vectors equals a 32-bit mark, which
+    seeded uniform data practically never gives.  A profiler run of this leg
+    sees these kernels beside the STREAM maps, whose counters they check."""
+    nbytes = 8 * n
+    A, B, C = (ts.Array.alloc(tgt, "f64", n) for _ in range(3))
+    for k, arr in enumerate((A, B, C)):
+        arr.fill_uniform(6, k)
+    out = {}
+    for name, reads, writes in (("read_1r", 1, 0), ("write_1w", 0, 1), ("copy_1r1w", 1, 1)):
+        cfg = dict(CALIBRATION_SHAPE, reads=reads, writes=writes)
+        ms = timed_launches(ts, tgt, lambda: ts.probe_bandwidth(tgt, cfg, A, B, C, nbytes), reps)
+        out[name] = {"bytes_read": reads * nbytes, "bytes_written": writes * nbytes, "launches": reps + 1,
+                     "avg_GBps": round((reads + writes) * nbytes / (sum(ms) / len(ms)) / 1e6, 1)}
+    out["shape"] = CALIBRATION_SHAPE
+    for arr in (A, B, C):
+        arr.free()
+    return out
+
+
+def batched_leg(ts, torch, tgt, count=4096, seed=5, replays=50, triad_reps=20, map_reps=10, per_instance=True):
+    """Batched ragged STREAM: the graph-captured iteration, each map alone, and
+    the triad as one plain launch per instance."""
     import numpy as np
 
     import tsgen
@@ -271,22 +300,34 @@ def batched_leg(ts, torch, tgt, count=4096, seed=5, replays=50, triad_reps=20):
         return all(int(batch.mismatch_count(tgt, k, exp_cols[k]).sum()) == 0 for k in range(3))
 
     valid = chains_hold()
-    # triad alone: one launch over all instances
-    t_ms = timed_launches(ts, tgt, lambda: batch.op(tgt, "triad"), triad_reps)
+    # each map alone, one launch over all instances, in listing order: a
+    # repeated map recomputes the same result, so the four together make one
+    # more iteration of the chain
+    maps = {}
+    for op, arrays in (("copy", 2), ("scale", 2), ("add", 3), ("triad", 3)):
+        ms = timed_launches(ts, tgt, lambda: batch.op(tgt, op), triad_reps if op == "triad" else map_reps)
+        mb = arrays * total * es
+        maps[op] = {"best_GBps": round(mb / min(ms) / 1e6, 1), "avg_GBps": round(mb / (sum(ms) / len(ms)) / 1e6, 1),
+                    "launches": len(ms) + 1, "cfg": ts.get_kernel_cfg(op, "f64", total, batched=True)}
+        if op == "triad":
+            t_ms = ms
     # comparison: one plain launch per instance (4096 launches per map)
-    p_ms = timed_launches(ts, tgt, lambda: batch.op_plain(tgt, "triad"), 5)
+    p_ms = timed_launches(ts, tgt, lambda: batch.op_plain(tgt, "triad"), 5) if per_instance else None
     tb = 3 * total * es
-    # the triad-only launches recompute a from the same b and c: unchanged
+    # the plain triads recompute a from the same b and c: still one iteration past the graph's
+    expected = [exact_chain(1.0, 2.0, 0.0, float(q), replays + 1) for q in qs]
+    exp_cols = [np.array([e[k] for e in expected]) for k in range(3)]
     valid_after = chains_hold()
     info = batch.info()
     out = {
         "instances": count, "total_elems": total, "device_bytes": 3 * total * es, "tiles": info["tiles"],
         "tile_elems": info["tile_elems"], "valid_after_graph_replays": valid,
-        "valid_after_triad_launches": valid_after, "graph_replays": replays,
+        "valid_after_map_launches": valid_after, "graph_replays": replays,
         "graph_iteration_ms": round(graph_ms, 4),
         "graph_iteration_GBps": round(10 * total * es / graph_ms / 1e6, 1),  # 2+2+3+3 arrays per element
         "triad_best_GBps": round(tb / min(t_ms) / 1e6, 1), "triad_avg_GBps": round(tb / (sum(t_ms) / len(t_ms)) / 1e6, 1),
-        "plain_per_instance_triad_best_GBps": round(tb / min(p_ms) / 1e6, 1),
+        "plain_per_instance_triad_best_GBps": round(tb / min(p_ms) / 1e6, 1) if p_ms else None,
+        "maps": maps,
         "cfg": ts.get_kernel_cfg("triad", "f64", total, batched=True),
     }
     g.close()
@@ -714,6 +755,9 @@ def main():
                          + ", ".join(EXTRA_LEGS))
     ap.add_argument("--jsonl", default=None,
                     help="also append one JSON record per measurement to this file")
+    ap.add_argument("--no-per-instance", action="store_true",
+                    help="batched leg: skip the comparison with one plain launch per instance (keeps "
+                         "profiler counter runs small)")
     ap.add_argument("--order", choices=("listing", "copy_b"), default="listing",
                     help="listing: copy c = a (Listing 4); copy_b: the variant with copy a = b")
     a = ap.parse_args()
@@ -782,8 +826,9 @@ def main():
                      "algorithmic_bytes_per_launch": tri["bytes"]},
     }
     if not a.quick:
-        for name, fn in (("ceiling", lambda: ceiling_leg(ts, tgt, a.n)),
-                         ("batched", lambda: batched_leg(ts, torch, tgt)),
+        for name, fn in (("calibration", lambda: calibration_leg(ts, tgt, a.n)),
+                         ("ceiling", lambda: ceiling_leg(ts, tgt, a.n)),
+                         ("batched", lambda: batched_leg(ts, torch, tgt, per_instance=not a.no_per_instance)),
                          ("reduced_precision", lambda: reduced_leg(ts, torch, tgt)),
                          ("sweep", lambda: sweep_leg(ts, tgt)),
                          ("launch_overhead", lambda: overhead_leg(ts, torch, tgt)),
@@ -797,8 +842,11 @@ def main():
             except Exception as e:  # an extra leg must not hide the headline
                 result[name] = {"error": f"{type(e).__name__}: {e}"}
         if "triad_best_GBps" in result.get("batched", {}):
-            result["batched"]["triad_vs_plain_n2p27_triad"] = round(
-                result["batched"]["triad_best_GBps"] / tri["best_GBps"], 3)
+            bt = result["batched"]
+            bt["triad_vs_plain_n2p27_triad"] = round(bt["triad_best_GBps"] / tri["best_GBps"], 3)
+            # each batched map against the same map's plain 2^27 launches of this run (averages)
+            bt["maps_avg_vs_plain_avg"] = {op: round(v["avg_GBps"] / k[op]["avg_GBps"], 3)
+                                           for op, v in bt["maps"].items()}
     if not a.no_cpu:
         log("cpu baseline leg (oracle)")
         try:
@@ -845,7 +893,9 @@ def summary(result: dict) -> dict:
         s["batched"] = {"triad_best_GBps": b["triad_best_GBps"], "triad_avg_GBps": b["triad_avg_GBps"],
                         "triad_vs_plain_triad_best": b.get("triad_vs_plain_n2p27_triad"),
                         "graph_iteration_GBps": b["graph_iteration_GBps"],
-                        "valid": bool(b["valid_after_graph_replays"] and b["valid_after_triad_launches"])}
+                        "maps_avg_GBps": {op: v["avg_GBps"] for op, v in b.get("maps", {}).items()},
+                        "maps_avg_vs_plain_avg": b.get("maps_avg_vs_plain_avg"),
+                        "valid": bool(b["valid_after_graph_replays"] and b["valid_after_map_launches"])}
     s["valid"] = result["valid"]
     cb = result.get("cpu_baseline", {})
     if "value" in cb:
@@ -877,6 +927,9 @@ def summary_text(s: dict) -> str:
         lines.append(f"batched triad {b['triad_best_GBps']:.0f}/{b['triad_avg_GBps']:.0f} GB/s "
                      f"({b['triad_vs_plain_triad_best']}x plain), graph iteration {b['graph_iteration_GBps']:.0f} GB/s, "
                      f"valid {b['valid']}")
+        if b.get("maps_avg_vs_plain_avg"):
+            lines.append("batched maps avg GB/s (x plain avg): " + ", ".join(
+                f"{op} {b['maps_avg_GBps'][op]:.0f} ({r:.3f})" for op, r in b["maps_avg_vs_plain_avg"].items()))
     lines.append(f"valid {s['valid']}")
     if "cpu_baseline" in s:
         lines.append(f"cpu baseline {s['cpu_baseline']['GBps']:.1f} GB/s on {s['cpu_baseline']['threads']} threads")

@@ -56,7 +56,7 @@ extern "C" {
 #define TS_API
 #endif
 
-#define TS_VERSION_MAJOR 1
+#define TS_VERSION_MAJOR 2
 #define TS_VERSION_MINOR 0
 
 typedef enum {
@@ -308,6 +308,10 @@ typedef struct {
                             once (batched: one workgroup per tile)          */
     int64_t tile_elems;  /* batched: elements per tile, a multiple of 8;
                             0 = default.  Ignored by plain kernels          */
+    int32_t tiles_per_wg; /* batched: consecutive tiles per workgroup, 1, 2,
+                            4 or 8 (0 = 1); more than 1 needs unroll <= 2.
+                            Plain kernels: 0 or 1                          */
+    int32_t reserved;    /* 0                                               */
 } ts_kernel_cfg;
 
 /* Operand alignment classes (keys of the tuning table). */

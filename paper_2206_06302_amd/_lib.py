@@ -23,10 +23,12 @@ class KernelCfg(ctypes.Structure):
         ("nt_store", ctypes.c_int32),
         ("grid_per_cu", ctypes.c_int32),
         ("tile_elems", ctypes.c_int64),
+        ("tiles_per_wg", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
-        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
 
     @classmethod
     def from_dict(cls, d: dict) -> "KernelCfg":
@@ -38,6 +40,8 @@ class KernelCfg(ctypes.Structure):
         c.nt_store = int(d.get("nt_store", 1))
         c.grid_per_cu = int(d.get("grid_per_cu", 0))
         c.tile_elems = int(d.get("tile_elems", 0))
+        c.tiles_per_wg = int(d.get("tiles_per_wg", 0))
+        c.reserved = int(d.get("reserved", 0))
         return c
 
 

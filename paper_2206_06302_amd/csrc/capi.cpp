@@ -236,9 +236,10 @@ void log_choice(int op, int dtype, uint64_t n, int align, int batched, const ts_
   static const char* const kTypes[] = {"f64", "f32", "bf16", "f16", "u8"};
   std::fprintf(stderr,
                "tstream: %s %s %s n=2^%d align=%d -> block %d, unroll %d, vec %d B, nt load %d, nt store %d, "
-               "grid/CU %d, tile %lld\n",
+               "grid/CU %d, tile %lld x %d per workgroup\n",
                batched ? "batched" : "plain", kOps[op & 3], kTypes[dtype < 5 ? dtype : 0], bucket, align, c.block,
-               c.unroll, c.vec_bytes, c.nt_load, c.nt_store, c.grid_per_cu, static_cast<long long>(c.tile_elems));
+               c.unroll, c.vec_bytes, c.nt_load, c.nt_store, c.grid_per_cu, static_cast<long long>(c.tile_elems),
+               c.tiles_per_wg < 1 ? 1 : c.tiles_per_wg);
 }
 
 }  // namespace tsapi

@@ -125,12 +125,14 @@ int launch_batch(ts_target_s* t, ts_batch_s* b, int op, const ts_kernel_cfg& cfg
         L.ntiles = p.ntiles;
       }
   }
-  // grid_per_cu 0: one workgroup per tile; otherwise a persistent grid that
-  // strides over the tiles.
+  // grid_per_cu 0: one workgroup per group of tiles_per_wg consecutive
+  // tiles; otherwise a persistent grid that strides over the groups.
+  const uint64_t per_wg = cfg.tiles_per_wg > 1 ? static_cast<uint64_t>(cfg.tiles_per_wg) : 1;
+  const uint64_t groups = (L.ntiles + per_wg - 1) / per_wg;
   uint64_t grid = cfg.grid_per_cu > 0
                       ? static_cast<uint64_t>(cfg.grid_per_cu) * static_cast<uint64_t>(t->info.compute_units)
-                      : L.ntiles;
-  if (grid > L.ntiles) grid = L.ntiles;
+                      : groups;
+  if (grid > groups) grid = groups;
   if (grid > kMaxGridX) grid = kMaxGridX;
   if (grid < 1) grid = 1;
   L.grid = static_cast<uint32_t>(grid);
@@ -139,6 +141,7 @@ int launch_batch(ts_target_s* t, ts_batch_s* b, int op, const ts_kernel_cfg& cfg
   L.unroll = cfg.unroll;
   L.ntl = cfg.nt_load;
   L.nts = cfg.nt_store;
+  L.tiles_per_wg = static_cast<int>(per_wg);
   L.stream = t->stream;
   const hipError_t e = batch_launch(b->dtype, L);
   if (e != hipSuccess) return hip_fail(e, "batched STREAM kernel launch");

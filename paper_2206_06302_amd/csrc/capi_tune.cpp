@@ -177,7 +177,15 @@ int ts_autotune_batch(ts_target t, ts_batch b, ts_op op, int reps, ts_kernel_cfg
   b->tile_pinned = true;  // candidates run on the primary plan, re-planned to their tile
   ts_kernel_cfg best_cfg = default_cfg(1, b->dtype);
   double best_s = 0;
-  for (const ts_kernel_cfg& c : candidates(1)) {
+  // Candidates grouped by tile size (one re-plan per size); shapes whose last
+  // unrolled vector lies past every full tile are skipped for this storage
+  // type (they repeat the shape with a smaller unroll).
+  std::vector<ts_kernel_cfg> cands = candidates(1);
+  std::stable_sort(cands.begin(), cands.end(),
+                   [](const ts_kernel_cfg& x, const ts_kernel_cfg& y) { return x.tile_elems < y.tile_elems; });
+  const int64_t per_vec = static_cast<int64_t>(16 / dtype_size(b->dtype));
+  for (const ts_kernel_cfg& c : cands) {
+    if (static_cast<int64_t>(c.unroll - 1) * c.block * per_vec >= c.tile_elems) continue;
     if (c.tile_elems != b->tile_elems && (st = batch_replan(b, c.tile_elems)) != TS_OK) break;
     double s = 0;
     st = time_candidate(t, reps, 1, [&]() { return launch_batch(t, b, op, c); }, &s);

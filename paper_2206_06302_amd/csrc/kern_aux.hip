@@ -309,7 +309,8 @@ __global__ __launch_bounds__(256) void batch_fill_kernel(const BatchTile* __rest
   constexpr uint64_t V = 16 / sizeof(T);
   TS_FOR_TILES(t) {
     const BatchTile tl = tiles[t];
-    T* d = static_cast<T*>(const_cast<void*>(which == 0 ? tl.a : which == 1 ? tl.b : tl.c));
+    T* dp = static_cast<T*>(const_cast<void*>(which == 0 ? tl.a : which == 1 ? tl.b : tl.c));
+    Global<T>* d = global_ptr(dp);  // global_load/store, not flat (see ts_device.hpp)
     const uint64_t state0 = seed ^ ((16ull + 3ull * tl.inst + static_cast<uint64_t>(which)) << 48);
     const T cv = from_f64<DT>(value);
     auto at = [&](uint64_t j) {
@@ -318,10 +319,10 @@ __global__ __launch_bounds__(256) void batch_fill_kernel(const BatchTile* __rest
     };
     const uint64_t end = tl.start + tl.count;
     uint64_t vs, ve;
-    tile_vectors(tl.start, end, head_of(d), V, vs, ve);
+    tile_vectors(tl.start, end, head_of(dp), V, vs, ve);
     for (uint64_t j = tl.start + threadIdx.x; j < vs; j += blockDim.x) d[j] = at(j);
     for (uint64_t j = ve + threadIdx.x; j < end; j += blockDim.x) d[j] = at(j);
-    R* dv = reinterpret_cast<R*>(d + vs);
+    Global<R>* dv = reinterpret_cast<Global<R>*>(d + vs);
     const uint64_t nvec = (ve - vs) / V;
     for (uint64_t k = threadIdx.x; k < nvec; k += blockDim.x) {
       Splat<T> v;
@@ -347,15 +348,16 @@ __global__ __launch_bounds__(256) void batch_mismatch_kernel(const BatchTile* __
   constexpr uint64_t V = 16 / sizeof(T);
   TS_FOR_TILES(t) {
     const BatchTile tl = tiles[t];
-    const T* x = static_cast<const T*>(which == 0 ? tl.a : which == 1 ? tl.b : tl.c);
+    const T* xp = static_cast<const T*>(which == 0 ? tl.a : which == 1 ? tl.b : tl.c);
+    const Global<T>* x = global_ptr(xp);
     const double e = expected[tl.inst];
     const uint64_t end = tl.start + tl.count;
     uint64_t vs, ve;
-    tile_vectors(tl.start, end, head_of(x), V, vs, ve);
+    tile_vectors(tl.start, end, head_of(xp), V, vs, ve);
     unsigned long long c = 0;
     for (uint64_t j = tl.start + threadIdx.x; j < vs; j += blockDim.x) c += differs(to_f64<DT>(x[j]), e) ? 1 : 0;
     for (uint64_t j = ve + threadIdx.x; j < end; j += blockDim.x) c += differs(to_f64<DT>(x[j]), e) ? 1 : 0;
-    const R* xv = reinterpret_cast<const R*>(x + vs);
+    const Global<R>* xv = reinterpret_cast<const Global<R>*>(x + vs);
     const uint64_t nvec = (ve - vs) / V;
     for (uint64_t k = threadIdx.x; k < nvec; k += blockDim.x) {
       const Splat<T> v = __builtin_bit_cast(Splat<T>, __builtin_nontemporal_load(xv + k));

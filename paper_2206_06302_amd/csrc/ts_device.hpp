@@ -88,18 +88,38 @@ template <> struct Raw<8> { typedef uint32_t type __attribute__((ext_vector_type
 template <> struct Raw<4> { typedef uint32_t type; };
 template <> struct Raw<2> { typedef uint16_t type; };
 
+// Every operand of these kernels is device (global) memory.  Accesses go
+// through global-address-space pointers, so they compile to global_load /
+// global_store even when the pointer was read from memory (a batch's tile
+// records) rather than passed as a kernel argument: the flat forms the
+// compiler would otherwise emit also count against the scalar-memory wait
+// counter, which ties every store to outstanding scalar loads.
+template <class T> using Global = __attribute__((address_space(1))) T;
+
+template <class T>
+__device__ __forceinline__ const Global<T>* global_ptr(const T* p) {
+  return (const Global<T>*)p;
+}
+
+template <class T>
+__device__ __forceinline__ Global<T>* global_ptr(T* p) {
+  return (Global<T>*)p;
+}
+
 template <int VB, bool NT>
 __device__ __forceinline__ typename Raw<VB>::type load(const void* p) {
   using R = typename Raw<VB>::type;
-  if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const R*>(p));
-  else return *reinterpret_cast<const R*>(p);
+  const Global<R>* g = global_ptr(static_cast<const R*>(p));
+  if constexpr (NT) return __builtin_nontemporal_load(g);
+  else return *g;
 }
 
 template <int VB, bool NT>
 __device__ __forceinline__ void store(void* p, typename Raw<VB>::type v) {
   using R = typename Raw<VB>::type;
-  if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<R*>(p));
-  else *reinterpret_cast<R*>(p) = v;
+  Global<R>* g = global_ptr(static_cast<R*>(p));
+  if constexpr (NT) __builtin_nontemporal_store(v, g);
+  else *g = v;
 }
 
 template <typename T, int VB> union Pack {
@@ -132,11 +152,11 @@ template <int DT, int OP>
 __device__ __forceinline__ void map_elem(const typename Fmt<DT>::T* x, const typename Fmt<DT>::T* y,
                                          typename Fmt<DT>::T* d, typename Fmt<DT>::C q, uint64_t j) {
   if constexpr (OP == OP_COPY) {
-    d[j] = x[j];
+    global_ptr(d)[j] = global_ptr(x)[j];
   } else {
     typename Fmt<DT>::C yv = 0;
-    if constexpr (uses_y<OP>()) yv = widen<DT>(y[j]);
-    d[j] = narrow<DT>(apply<OP>(widen<DT>(x[j]), yv, q));
+    if constexpr (uses_y<OP>()) yv = widen<DT>(global_ptr(y)[j]);
+    global_ptr(d)[j] = narrow<DT>(apply<OP>(widen<DT>(global_ptr(x)[j]), yv, q));
   }
 }
 
@@ -219,51 +239,160 @@ __device__ __forceinline__ void roles(const BatchTile& tl, const void*& x, const
   else { x = tl.b; y = tl.c; d = const_cast<void*>(tl.a); }
 }
 
-// One launch over every instance: workgroup w takes tiles w, w + G, w + 2G,
-// ... (G = grid size).  With one workgroup per tile (G = number of tiles,
-// the tuned shape) each workgroup takes one tile; with a smaller grid the
-// workgroups persist and stride.  Each tile record is self-contained, and the
-// next one is fetched while the current tile streams; inside a tile the lanes
-// stream 16-byte vectors like the plain kernel.
-template <int DT, int OP, int U, bool NTL, bool NTS>
+// The part of one tile a workgroup streams: element-wise ranges [start, vs)
+// and [ve, end) around the 16-byte vectors [vs, ve) (only the first tile of
+// an instance has a head, only its last a ragged tail).
+template <int DT>
+struct TileSpan {
+  const typename Fmt<DT>::T* x;
+  const typename Fmt<DT>::T* y;
+  typename Fmt<DT>::T* d;
+  typename Fmt<DT>::C q;
+  uint64_t start, vs, ve, end;
+};
+
+template <int DT, int OP>
+__device__ __forceinline__ TileSpan<DT> tile_span(const BatchTile& tl) {
+  using T = typename Fmt<DT>::T;
+  constexpr uint64_t V = 16 / sizeof(T);
+  const void *xv, *yv;
+  void* dv;
+  roles<OP>(tl, xv, yv, dv);
+  TileSpan<DT> s;
+  s.x = static_cast<const T*>(xv);
+  s.y = static_cast<const T*>(yv);
+  s.d = static_cast<T*>(dv);
+  s.q = pick_q<DT>(tl.q, tl.qf);
+  s.start = tl.start;
+  s.end = tl.start + tl.count;
+  s.vs = s.end;
+  s.ve = s.end;
+  if (tl.vec_ok) {
+    const uint64_t h = tl.head;
+    s.vs = s.start < h ? h : h + (s.start - h + V - 1) / V * V;
+    if (s.vs > s.end) s.vs = s.end;
+    s.ve = s.end < h ? s.vs : h + (s.end - h) / V * V;
+    if (s.ve < s.vs) s.ve = s.vs;
+  }
+  return s;
+}
+
+template <int DT, int OP>
+__device__ __forceinline__ void tile_edges(const TileSpan<DT>& s, uint64_t lane, uint64_t width) {
+  for (uint64_t j = s.start + lane; j < s.vs; j += width) map_elem<DT, OP>(s.x, s.y, s.d, s.q, j);
+  for (uint64_t j = s.ve + lane; j < s.end; j += width) map_elem<DT, OP>(s.x, s.y, s.d, s.q, j);
+}
+
+// Tiles between a workgroup and the one whose record it reads ahead (one
+// workgroup per tile): a multiple of the 8 XCDs, about one round of the
+// workgroups resident on an XCD (32 CUs x 8 workgroups of 256 lanes).
+constexpr uint64_t kRecordAhead = 2048;
+
+// One launch over every instance.
+//
+// K = 1: workgroup w takes tiles w, w + G, w + 2G, ... (G = grid size).
+// With one workgroup per tile (G = number of tiles) each workgroup takes one
+// tile; with a smaller grid the workgroups persist and stride, fetching the
+// next tile record while the current tile streams.
+//
+// K > 1: workgroup w takes the K consecutive tiles Kw .. Kw + K - 1 (then
+// Kw + KG, ... on a persistent grid).  It reads the K records together and
+// issues the first U vectors per lane of every one of its tiles before it
+// stores any, so K*U loads (or 2*K*U) are in flight per lane and one record
+// latency serves K tiles; the tiles may belong to different instances.
+// Vectors beyond the first U*width of a tile, and the element-wise head and
+// tail, follow.
+//
+// Inside a tile the lanes stream 16-byte vectors like the plain kernel, and
+// element ownership is disjoint, so results do not depend on K, U or G.
+template <int DT, int OP, int U, int K, bool NTL, bool NTS>
 __global__ __launch_bounds__(1024) void batch_kernel(const BatchTile* __restrict__ tiles,
                                                      uint64_t ntiles) {
   using T = typename Fmt<DT>::T;
   constexpr int VB = 16;
   constexpr uint64_t V = VB / sizeof(T);
   const uint64_t width = blockDim.x;
-  uint64_t t = blockIdx.x;
-  if (t >= ntiles) return;
-  BatchTile cur = tiles[t];
-  for (; t < ntiles; t += gridDim.x) {
-    BatchTile nxt = cur;
-    if (t + gridDim.x < ntiles) nxt = tiles[t + gridDim.x];
-    const void *xv, *yv;
-    void* dv;
-    roles<OP>(cur, xv, yv, dv);
-    const T* x = static_cast<const T*>(xv);
-    const T* y = static_cast<const T*>(yv);
-    T* d = static_cast<T*>(dv);
-    const typename Fmt<DT>::C qc = pick_q<DT>(cur.q, cur.qf);
-    const uint64_t start = cur.start, end = cur.start + cur.count;
-    uint64_t vs = end, ve = end;  // vector range [vs, ve)
-    if (cur.vec_ok) {
-      const uint64_t h = cur.head;
-      vs = start < h ? h : h + (start - h + V - 1) / V * V;
-      if (vs > end) vs = end;
-      ve = end < h ? vs : h + (end - h) / V * V;
-      if (ve < vs) ve = vs;
+  const uint64_t lane = threadIdx.x;
+  if constexpr (K == 1) {
+    uint64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    BatchTile cur = tiles[t];
+    uint64_t ahead = 0;
+    for (; t < ntiles; t += gridDim.x) {
+      BatchTile nxt = cur;
+      if (t + gridDim.x < ntiles) nxt = tiles[t + gridDim.x];
+      const TileSpan<DT> s = tile_span<DT, OP>(cur);
+      // One workgroup per tile, maps of one input (copy, scale): read the
+      // record of the tile that a workgroup kRecordAhead later takes.
+      // Workgroups are handed to the XCDs in turn and kRecordAhead is a
+      // multiple of their count, so the record lands in the L2 of the XCD
+      // that will run that workgroup, which then finds it there instead of
+      // waiting on memory before its first data load.  The read depends on
+      // this tile's record (a tile is never empty), so it is issued after
+      // that record has arrived, and is waited for only at the end: it costs
+      // this workgroup no latency.  Maps of two inputs stream longer per
+      // tile, and measured no faster with it.
+      if constexpr (!uses_y<OP>()) {
+        if (gridDim.x >= ntiles && s.end > s.start && t + kRecordAhead < ntiles) ahead = tiles[t + kRecordAhead].count;
+      }
+      const uint64_t nvec = (s.ve - s.vs) / V;
+      if (nvec) {
+        vec_body<DT, OP, VB, U, NTL, NTS>(reinterpret_cast<const char*>(s.x + s.vs),
+                                          reinterpret_cast<const char*>(s.y + s.vs),
+                                          reinterpret_cast<char*>(s.d + s.vs), s.q, nvec, lane, width,
+                                          width * U);
+      }
+      tile_edges<DT, OP>(s, lane, width);
+      cur = nxt;
     }
-    for (uint64_t j = start + threadIdx.x; j < vs; j += width) map_elem<DT, OP>(x, y, d, qc, j);
-    for (uint64_t j = ve + threadIdx.x; j < end; j += width) map_elem<DT, OP>(x, y, d, qc, j);
-    const uint64_t nvec = (ve - vs) / V;
-    if (nvec) {
-      vec_body<DT, OP, VB, U, NTL, NTS>(reinterpret_cast<const char*>(x + vs),
-                                        reinterpret_cast<const char*>(y + vs),
-                                        reinterpret_cast<char*>(d + vs), qc, nvec, threadIdx.x,
-                                        width, width * U);
+    asm volatile("" ::"s"(ahead));  // the read above completes before the workgroup ends
+  } else {
+    using R = typename Raw<VB>::type;
+    for (uint64_t t0 = static_cast<uint64_t>(blockIdx.x) * K; t0 < ntiles;
+         t0 += static_cast<uint64_t>(gridDim.x) * K) {
+      TileSpan<DT> s[K];
+      uint64_t nvec[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        nvec[k] = 0;
+        if (t0 + k < ntiles) {
+          s[k] = tile_span<DT, OP>(tiles[t0 + k]);
+          nvec[k] = (s[k].ve - s[k].vs) / V;
+        }
+      }
+      R rx[K][U], ry[K][U];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint64_t v = lane + u * width;
+          if (v < nvec[k]) {
+            rx[k][u] = load<VB, NTL>(s[k].x + s[k].vs + v * V);
+            if constexpr (uses_y<OP>()) ry[k][u] = load<VB, NTL>(s[k].y + s[k].vs + v * V);
+            else ry[k][u] = rx[k][u];
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint64_t v = lane + u * width;
+          if (v < nvec[k])
+            store<VB, NTS>(s[k].d + s[k].vs + v * V, map_vec<DT, OP, VB>(rx[k][u], ry[k][u], s[k].q));
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (nvec[k] > U * width) {
+          vec_body<DT, OP, VB, U, NTL, NTS>(reinterpret_cast<const char*>(s[k].x + s[k].vs),
+                                            reinterpret_cast<const char*>(s[k].y + s[k].vs),
+                                            reinterpret_cast<char*>(s[k].d + s[k].vs), s[k].q, nvec[k],
+                                            U * width + lane, width, width * U);
+        }
+        if (t0 + k < ntiles) tile_edges<DT, OP>(s[k], lane, width);
+      }
     }
-    cur = nxt;
   }
 }
 
@@ -318,30 +447,46 @@ hipError_t plain_dispatch(const PlainLaunch& L) {
   }
 }
 
-template <int DT, int OP, int U, bool NTL, bool NTS>
+template <int DT, int OP, int U, int K, bool NTL, bool NTS>
 hipError_t launch_batch_inst(const BatchLaunch& L) {
-  hipLaunchKernelGGL((batch_kernel<DT, OP, U, NTL, NTS>), dim3(L.grid), dim3(L.block), 0, L.stream,
+  hipLaunchKernelGGL((batch_kernel<DT, OP, U, K, NTL, NTS>), dim3(L.grid), dim3(L.block), 0, L.stream,
                      L.tiles, L.ntiles);
   return hipGetLastError();
 }
 
-template <int DT, int OP, int U>
+template <int DT, int OP, int U, int K>
 hipError_t batch_nt(const BatchLaunch& L) {
   if (L.ntl) {
-    return L.nts ? launch_batch_inst<DT, OP, U, true, true>(L)
-                 : launch_batch_inst<DT, OP, U, true, false>(L);
+    return L.nts ? launch_batch_inst<DT, OP, U, K, true, true>(L)
+                 : launch_batch_inst<DT, OP, U, K, true, false>(L);
   }
-  return L.nts ? launch_batch_inst<DT, OP, U, false, true>(L)
-               : launch_batch_inst<DT, OP, U, false, false>(L);
+  return L.nts ? launch_batch_inst<DT, OP, U, K, false, true>(L)
+               : launch_batch_inst<DT, OP, U, K, false, false>(L);
+}
+
+// Several tiles per workgroup come with at most two vectors per lane each
+// (the candidate set and the configuration check hold to this).
+template <int DT, int OP, int U>
+hipError_t batch_k(const BatchLaunch& L) {
+  if constexpr (U <= 2) {
+    switch (L.tiles_per_wg) {
+      case 2: return batch_nt<DT, OP, U, 2>(L);
+      case 4: return batch_nt<DT, OP, U, 4>(L);
+      case 8: return batch_nt<DT, OP, U, 8>(L);
+      default: break;
+    }
+  }
+  if (L.tiles_per_wg != 1) return hipErrorInvalidValue;
+  return batch_nt<DT, OP, U, 1>(L);
 }
 
 template <int DT, int OP>
 hipError_t batch_u(const BatchLaunch& L) {
   switch (L.unroll) {
-    case 1: return batch_nt<DT, OP, 1>(L);
-    case 2: return batch_nt<DT, OP, 2>(L);
-    case 4: return batch_nt<DT, OP, 4>(L);
-    case 8: return batch_nt<DT, OP, 8>(L);
+    case 1: return batch_k<DT, OP, 1>(L);
+    case 2: return batch_k<DT, OP, 2>(L);
+    case 4: return batch_k<DT, OP, 4>(L);
+    case 8: return batch_k<DT, OP, 8>(L);
     default: return hipErrorInvalidValue;
   }
 }

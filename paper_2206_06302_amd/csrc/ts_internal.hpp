@@ -29,6 +29,7 @@ struct BatchLaunch {
   uint64_t ntiles;
   uint32_t grid, block;
   int op, unroll, ntl, nts;
+  int tiles_per_wg;  // consecutive tiles per workgroup: 1, 2, 4 or 8
   hipStream_t stream;
 };
 

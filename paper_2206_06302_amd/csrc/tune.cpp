@@ -45,12 +45,14 @@ ts_kernel_cfg default_cfg(int batched, int dtype) {
     c.nt_load = 1;
     c.grid_per_cu = 0;
     c.tile_elems = 4096 / es;
+    c.tiles_per_wg = 1;
   } else {
     c.block = 256;
     c.unroll = 4;
     c.nt_load = 0;
     c.grid_per_cu = 0;
     c.tile_elems = 0;
+    c.tiles_per_wg = 1;
   }
   return c;
 }
@@ -62,11 +64,17 @@ std::string cfg_problem(const ts_kernel_cfg& c, int batched) {
     if (c.vec_bytes != 16) return "batched kernels use 16-byte vectors";
     if (c.grid_per_cu < 0 || c.grid_per_cu > 64) return "batched grid_per_cu must be 0..64";
     if (c.tile_elems < 0 || c.tile_elems % 8) return "tile_elems must be a multiple of 8";
+    if (c.tiles_per_wg != 0 && c.tiles_per_wg != 1 && c.tiles_per_wg != 2 && c.tiles_per_wg != 4 &&
+        c.tiles_per_wg != 8)
+      return "tiles_per_wg must be 1, 2, 4 or 8 (0 = 1)";
+    if (c.tiles_per_wg > 1 && c.unroll > 2) return "several tiles per workgroup take unroll 1 or 2";
   } else {
     if (c.vec_bytes != 16 && c.vec_bytes != 8 && c.vec_bytes != 4 && c.vec_bytes != 2)
       return "vec_bytes must be 16, 8, 4 or 2";
     if (c.grid_per_cu < 0 || c.grid_per_cu > 64) return "grid_per_cu must be 0..64";
+    if (c.tiles_per_wg != 0 && c.tiles_per_wg != 1) return "plain kernels take tiles_per_wg 0 or 1";
   }
+  if (c.reserved != 0) return "reserved must be 0";
   if ((c.nt_load != 0 && c.nt_load != 1) || (c.nt_store != 0 && c.nt_store != 1))
     return "nt flags must be 0 or 1";
   return "";
@@ -82,7 +90,7 @@ std::vector<ts_kernel_cfg> candidates(int batched) {
             for (int nts : {0, 1})
               for (int g : {0, 2, 4, 8}) {
                 if (vb == 8 && (u == 1 || g == 2)) continue;  // keep the 8-byte set small
-                out.push_back(ts_kernel_cfg{block, u, vb, ntl, nts, g, 0});
+                out.push_back(ts_kernel_cfg{block, u, vb, ntl, nts, g, 0, 1, 0});
               }
   } else {
     // One workgroup per tile (grid_per_cu 0) with small tiles ...
@@ -90,14 +98,22 @@ std::vector<ts_kernel_cfg> candidates(int batched) {
       for (int u : {1, 2})
         for (int ntl : {0, 1})
           for (int64_t tile : {512, 1024, 2048, 4096, 8192})
-            out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, 0, tile});
+            out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, 0, tile, 1, 0});
+    // ... several consecutive small tiles per workgroup, all their first
+    // loads in flight together ...
+    for (int block : {256, 512})
+      for (int u : {1, 2})
+        for (int ntl : {0, 1})
+          for (int k : {2, 4, 8})
+            for (int64_t tile : {512, 1024, 2048})
+              out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, 0, tile, k, 0});
     // ... and persistent grids that stride over larger tiles.
     for (int block : {512, 1024})
       for (int u : {4, 8})
         for (int ntl : {0, 1})
           for (int g : {4, 8})
             for (int64_t tile : {16384, 65536})
-              out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, g, tile});
+              out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, g, tile, 1, 0});
   }
   return out;
 }
@@ -157,10 +173,11 @@ std::string TuneTable::to_json() const {
                   "%s\n    {\"op\": \"%s\", \"dtype\": \"%s\", \"bucket\": %d, \"align\": %d, "
                   "\"batched\": %d, \"block\": %d, \"unroll\": %d, \"vec_bytes\": %d, "
                   "\"nt_load\": %d, \"nt_store\": %d, \"grid_per_cu\": %d, \"tile_elems\": %lld, "
-                  "\"bytes_per_s\": %.6e}",
+                  "\"tiles_per_wg\": %d, \"bytes_per_s\": %.6e}",
                   first ? "" : ",", kOpNames[k.op], kTypeNames[k.dtype], k.bucket, k.align,
                   k.batched, c.block, c.unroll, c.vec_bytes, c.nt_load, c.nt_store, c.grid_per_cu,
-                  static_cast<long long>(c.tile_elems), kv.second.bytes_per_s);
+                  static_cast<long long>(c.tile_elems), c.tiles_per_wg,
+                  kv.second.bytes_per_s);
     os << buf;
     first = false;
   }
@@ -268,6 +285,9 @@ bool parse_entry(Reader& r, TuneKey& k, TuneEntry& e) {
   e.cfg.nt_store = static_cast<int32_t>(nums["nt_store"]);
   e.cfg.grid_per_cu = static_cast<int32_t>(nums["grid_per_cu"]);
   e.cfg.tile_elems = static_cast<int64_t>(nums["tile_elems"]);
+  // Tables written before the field existed hold one tile per workgroup.
+  e.cfg.tiles_per_wg = nums.count("tiles_per_wg") ? static_cast<int32_t>(nums["tiles_per_wg"]) : 1;
+  e.cfg.reserved = 0;
   e.bytes_per_s = nums.count("bytes_per_s") ? nums["bytes_per_s"] : 0.0;
   const std::string why = cfg_problem(e.cfg, k.batched);
   if (!why.empty()) return r.fail("invalid configuration: " + why);

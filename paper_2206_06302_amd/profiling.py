@@ -3,22 +3,33 @@
     python paper_2206_06302_amd/profiling.py run --raw DIR        # on a machine with the GPU
     python paper_2206_06302_amd/profiling.py summarize --raw DIR  # anywhere: rewrites profiles/*.md
 
-`run` starts four rocprofv3 runs, each a process of its own with the program
+`run` starts six rocprofv3 runs, each a process of its own with the program
 directly after `--`, from /tmp with TMPDIR=/tmp:
 
   headline trace   --kernel-trace --stats of bench.py --quick --no-cpu --warmup 1 --steps 20
   batched trace    --kernel-trace --stats of bench.py --no-cpu --legs batched --warmup 1 --steps 20
-  fetch counters   --pmc FETCH_SIZE of bench.py --no-cpu --legs batched --warmup 1 --steps 3
-  write counters   --pmc WRITE_SIZE of the same command
+  fetch counters   --pmc FETCH_SIZE       of bench.py --no-cpu --legs calibration,batched --no-per-instance
+                                          --warmup 1 --steps 3
+  write counters   --pmc WRITE_SIZE       of the same command
+  read requests    --pmc TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_BUBBLE_sum TCC_EA0_RDREQ_DRAM_sum
+  write requests   --pmc TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum TCC_EA0_WRREQ_DRAM_sum
 
-`summarize` turns the raw CSV files into four short markdown summaries: the
+`summarize` turns the raw CSV files into short markdown summaries: the
 per-kernel trace of the headline and of the batched leg (with the bench's own
 event timings from the same runs beside rocprof's), and the HBM traffic per
-launch of the headline triad and the batched triad.  Counter KiB are scaled
-by what the same counters read for the headline copy kernel, which moves
-exactly 2^27 x 8 bytes each way.  Each summary records the source digest of
-the headline kernels, so the benchmark reports counter traffic only while
-the kernels are unchanged.
+launch of the four headline maps and the four batched maps.
+
+HBM bytes come from the L2-to-memory request counts: on gfx950 every read
+request that is not a 32-byte one moves 128 bytes, and write requests move
+64 or 32 bytes.  The memory-system probe kernels of bench.py's calibration
+leg, which move exactly known bytes and are not themselves reported, check
+this: the read-only probe's 2^30 bytes arrive in 2^23 requests.  They also
+show why FETCH_SIZE alone reads half: its expression prices 128-byte reads
+through TCC_BUBBLE, which stays 0 on this part, so each read request counts
+64 bytes.  FETCH_SIZE and WRITE_SIZE are reported beside the request-count
+bytes, scaled by what they read for the probe's copy of known size.  Each
+summary records the source digest of the headline kernels, so the benchmark
+reports counter traffic only while the kernels are unchanged.
 
 This file is loaded by path (bench.py does so for source_digest) and needs
 neither torch nor the library.
@@ -69,9 +80,15 @@ def _bench(*args):
     return [sys.executable, os.path.join(ROOT, "bench.py"), *args]
 
 
+READ_REQUESTS = ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_BUBBLE_sum", "TCC_EA0_RDREQ_DRAM_sum")
+WRITE_REQUESTS = ("TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum", "TCC_EA0_WRREQ_DRAM_sum")
+PMC_RUNS = (("fetch counters", "pmc_fetch", ("FETCH_SIZE",)), ("write counters", "pmc_write", ("WRITE_SIZE",)),
+            ("read requests", "pmc_rdreq", READ_REQUESTS), ("write requests", "pmc_wrreq", WRITE_REQUESTS))
+
+
 def runs(raw: str) -> list[tuple[str, list[str], str]]:
-    """(name, command, stdout file) of the four profiler runs."""
-    return [
+    """(name, command, stdout file) of the profiler runs."""
+    out = [
         ("headline trace", ["rocprofv3", "--kernel-trace", "--stats", "--output-format", "csv", "-d",
                             os.path.join(raw, "trace_headline"), "-o", "run", "--",
                             *_bench("--quick", "--no-cpu", "--warmup", "1", "--steps", "20")],
@@ -80,15 +97,14 @@ def runs(raw: str) -> list[tuple[str, list[str], str]]:
                            os.path.join(raw, "trace_batched"), "-o", "run", "--",
                            *_bench("--no-cpu", "--legs", "batched", "--warmup", "1", "--steps", "20")],
          os.path.join(raw, "trace_batched.json")),
-        ("fetch counters", ["rocprofv3", "--pmc", "FETCH_SIZE", "--output-format", "csv", "-d",
-                            os.path.join(raw, "pmc_fetch"), "-o", "run", "--",
-                            *_bench("--no-cpu", "--legs", "batched", "--warmup", "1", "--steps", "3")],
-         os.path.join(raw, "pmc_fetch.json")),
-        ("write counters", ["rocprofv3", "--pmc", "WRITE_SIZE", "--output-format", "csv", "-d",
-                            os.path.join(raw, "pmc_write"), "-o", "run", "--",
-                            *_bench("--no-cpu", "--legs", "batched", "--warmup", "1", "--steps", "3")],
-         os.path.join(raw, "pmc_write.json")),
     ]
+    for name, sub, counters in PMC_RUNS:
+        out.append((name, ["rocprofv3", "--pmc", *counters, "--output-format", "csv", "-d", os.path.join(raw, sub),
+                           "-o", "run", "--",
+                           *_bench("--no-cpu", "--legs", "calibration,batched", "--no-per-instance", "--warmup", "1",
+                                   "--steps", "3")],
+                    os.path.join(raw, sub + ".json")))
+    return out
 
 
 def run(raw: str, timeout: int) -> int:
@@ -117,6 +133,7 @@ def _stats(path):
 
 
 def _counters(dirpath, counter):
+    """{(kernel name, grid size): [value per dispatch]} of one counter."""
     vals = {}
     for f in glob.glob(os.path.join(dirpath, "**", "*counter_collection.csv"), recursive=True):
         for r in csv.DictReader(open(f)):
@@ -165,36 +182,96 @@ def _command(cmd, raw):
     return " ".join(out)
 
 
-def _calibration(fetch, write):
-    """Counter scale factors from the headline copy kernel (the largest copy
-    grid): it reads and writes exactly 2^27 x 8 bytes."""
-    grids = sorted({g for (name, g) in fetch if re.search(r"stream_kernel<0, 0,", name)})
-    cf = _pick(fetch, r"stream_kernel<0, 0,", grids[-1])
-    cw = _pick(write, r"stream_kernel<0, 0,", grids[-1])
-    ff = N27 * 8 / (sum(cf) / len(cf) * 1024)
-    fw = N27 * 8 / (sum(cw) / len(cw) * 1024)
-    return ff, fw, len(cf), len(cw)
+class Counters:
+    """Every counter of the four counter runs, averaged per dispatch of one kernel."""
+
+    def __init__(self, raw: str):
+        self.vals = {}
+        for _, sub, counters in PMC_RUNS:
+            for c in counters:
+                self.vals[c] = _counters(os.path.join(raw, sub), c)
+
+    def mean(self, counter, pattern, grid=None):
+        v = _pick(self.vals[counter], pattern, grid)
+        return (sum(v) / len(v), len(v)) if v else (float("nan"), 0)
+
+    def launch(self, pattern, grid=None) -> dict:
+        """Per-dispatch means of every counter for kernels matching `pattern`
+        (and grid size), plus the bytes the request counts give."""
+        d = {c: self.mean(c, pattern, grid)[0] for c in self.vals}
+        d["dispatches"] = "/".join(str(self.mean(c, pattern, grid)[1]) for c in ("FETCH_SIZE", "WRITE_SIZE",
+                                                                               READ_REQUESTS[0], WRITE_REQUESTS[0]))
+        rd, rd32 = d["TCC_EA0_RDREQ_sum"], d["TCC_EA0_RDREQ_32B_sum"]
+        wr, wr64 = d["TCC_EA0_WRREQ_sum"], d["TCC_EA0_WRREQ_64B_sum"]
+        d["read_bytes"] = 128.0 * (rd - rd32) + 32.0 * rd32
+        d["write_bytes"] = 64.0 * wr64 + 32.0 * (wr - wr64)
+        return d
 
 
-def summarize(raw: str) -> None:
+PROBE = {"read_1r": r"probe_kernel<1, 0,", "write_1w": r"probe_kernel<0, 1,", "copy_1r1w": r"probe_kernel<1, 1,"}
+PROBE_BYTES = N27 * 8  # the calibration leg's probes move 2^27 binary64 elements per array
+
+
+def _calibration(cn: Counters):
+    """Lines on the probe kernels of known traffic, and the FETCH_SIZE /
+    WRITE_SIZE scale factors from the probe's copy."""
+    r, w, c = (cn.launch(PROBE[k]) for k in ("read_1r", "write_1w", "copy_1r1w"))
+    # FETCH_SIZE prices a read request at 64 bytes when TCC_BUBBLE is 0; a
+    # request moves 128.  WRITE_SIZE prices write requests at their size.
+    ff, fw = 128.0 / 64.0, 1.0
+    lines = [
+        "Calibration on the memory-system probe of bench.py's calibration leg (straight-line 16-byte",
+        "loads and stores over 2^27 binary64 elements per array, 2^30 bytes; not a reported kernel):", "",
+        "| probe | reads / writes (bytes) | read requests (all / 32 B / TCC_BUBBLE) | write requests (all / 64 B) "
+        "| bytes per read request | bytes per write request | FETCH_SIZE KiB | WRITE_SIZE KiB |",
+        "|---|---|---|---|---|---|---|---|"]
+    for name, d, rb, wb in (("read_1r", r, PROBE_BYTES, 0), ("write_1w", w, 0, PROBE_BYTES),
+                            ("copy_1r1w", c, PROBE_BYTES, PROBE_BYTES)):
+        bpr = f"{rb / d['TCC_EA0_RDREQ_sum']:.2f}" if rb else "–"
+        bpw = f"{wb / d['TCC_EA0_WRREQ_sum']:.2f}" if wb else "–"
+        lines.append(f"| {name} | {rb:.4e} / {wb:.4e} | {d['TCC_EA0_RDREQ_sum']:.0f} / {d['TCC_EA0_RDREQ_32B_sum']:.0f} / "
+                     f"{d['TCC_BUBBLE_sum']:.0f} | {d['TCC_EA0_WRREQ_sum']:.0f} / {d['TCC_EA0_WRREQ_64B_sum']:.0f} | "
+                     f"{bpr} | {bpw} | {d['FETCH_SIZE']:.0f} | {d['WRITE_SIZE']:.0f} |")
+    extra = w["TCC_EA0_WRREQ_sum"] - PROBE_BYTES / 64
+    lines += ["", f"Every read request carries 128 bytes and every write request 64, while TCC_BUBBLE, the counter "
+              f"FETCH_SIZE's expression prices at 128 bytes, reads {r['TCC_BUBBLE_sum']:.0f}: FETCH_SIZE counts each "
+              f"read request as 64 bytes.  The bytes below are therefore 128 x (read requests - 32-byte ones) + 32 x "
+              f"the 32-byte ones, and 64 or 32 per write request.  FETCH_SIZE and WRITE_SIZE are listed beside them, "
+              f"scaled by what that gives: fetch x{ff:.1f} (128-byte requests priced at 64), write x{fw:.1f}.  The "
+              f"write-only probe's {extra:.0f} write requests beyond 2^30 / 64 ({extra * 64 / PROBE_BYTES * 100:.2f} %) "
+              f"are dirty lines of the kernel before it, written back while it runs."]
+    return lines, ff, fw
+
+
+def _traffic_table(rows, ff, fw):
+    """Markdown rows: (label, counters, algorithmic read bytes, algorithmic write bytes)."""
+    out = ["| map | dispatches (fetch/write/read req/write req) | FETCH_SIZE KiB | WRITE_SIZE KiB | read requests | "
+           "write requests | read bytes | write bytes | FETCH/WRITE scaled | algorithmic read / write | "
+           "traffic / algorithmic |", "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for label, d, ar, aw in rows:
+        scaled = d["FETCH_SIZE"] * 1024 * ff + d["WRITE_SIZE"] * 1024 * fw
+        out.append(f"| {label} | {d['dispatches']} | {d['FETCH_SIZE']:.0f} | {d['WRITE_SIZE']:.0f} | "
+                   f"{d['TCC_EA0_RDREQ_sum']:.0f} | {d['TCC_EA0_WRREQ_sum']:.0f} | {d['read_bytes']:.4e} | "
+                   f"{d['write_bytes']:.4e} | {scaled:.4e} | {ar:.4e} / {aw:.4e} | "
+                   f"{(d['read_bytes'] + d['write_bytes']) / (ar + aw):.4f} |")
+    return out
+
+
+def summarize(raw: str, out: str = PROFILES) -> None:
     raw = os.path.abspath(raw)
+    os.makedirs(out, exist_ok=True)
     digest = source_digest()
     cmds = {name: cmd for name, cmd, _ in runs(raw)}
-    fetch = _counters(os.path.join(raw, "pmc_fetch"), "FETCH_SIZE")
-    write = _counters(os.path.join(raw, "pmc_write"), "WRITE_SIZE")
-    ff, fw, ncf, ncw = _calibration(fetch, write)
-    calib = (f"Counter values are KiB per dispatch.  Calibration: the headline copy kernel ({ncf}/{ncw} "
-             f"dispatches) reads and writes exactly 2^27 x 8 B, giving the factors fetch x{ff:.4f} and write "
-             f"x{fw:.4f}.")
-    pmc_cmds = ["```", "export TMPDIR=/tmp; cd /tmp", _command(cmds["fetch counters"], raw),
-                _command(cmds["write counters"], raw), "```"]
+    cn = Counters(raw)
+    calib, ff, fw = _calibration(cn)
+    pmc_cmds = ["```", "export TMPDIR=/tmp; cd /tmp", *(_command(cmds[name], raw) for name, _, _ in PMC_RUNS), "```"]
 
     # headline trace
     bj = _bench_json(os.path.join(raw, "trace_headline.json"))
     L = ["# Kernel trace: STREAM f64, N = 2^27 per array (bench headline)", "",
          "Made by `python paper_2206_06302_amd/profiling.py run` (then `summarize`); the run:", "",
          "```", "export TMPDIR=/tmp; cd /tmp", _command(cmds["headline trace"], raw), "```", "",
-         "31 launches per map (1 warm-up, 20 timed steps, 10 of the closed-form check).  GB/s = STREAM bytes",
+         "71 launches per map (1 warm-up, 20 timed steps, 50 of the fused-chain check).  GB/s = STREAM bytes",
          "of the launch / its average duration (copy and scale move 2 arrays of 1 GiB, add and triad 3).", "",
          "| kernel | map | calls | avg µs | min µs | max µs | GB/s (avg) | GB/s (min time) |",
          "|---|---|---|---|---|---|---|---|"]
@@ -214,34 +291,31 @@ def summarize(raw: str) -> None:
         k = bj["per_kernel"][op]
         L.append(f"| {op} | {k['avg_ms']*1e3:.1f} | {k['avg_GBps']} | {k['best_ms']*1e3:.1f} |")
     L += ["", f"kernel_source_digest: {digest}", ""]
-    open(os.path.join(PROFILES, "stream_f64_n2p27_kernel_trace.md"), "w").write("\n".join(L))
+    open(os.path.join(out, "stream_f64_n2p27_kernel_trace.md"), "w").write("\n".join(L))
 
     # headline counters
     grid_of = {}
-    for (name, g) in fetch:
+    for (name, g) in cn.vals["FETCH_SIZE"]:
         p = _plain_name(name)
         if p and p[0] == 0:
             grid_of.setdefault(p[1], set()).add(g)
-    L = ["# HBM traffic counters: STREAM f64, N = 2^27 per array", "",
-         "Two counter runs (FETCH_SIZE, then WRITE_SIZE; each a run of its own), made by",
-         "`python paper_2206_06302_amd/profiling.py run`:", "", *pmc_cmds, "", calib, "",
-         "| map | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | fetched bytes (scaled) | written bytes (scaled) | "
-         "algorithmic read / write bytes | traffic / algorithmic |", "|---|---|---|---|---|---|---|---|"]
-    traffic = None
+    rows, traffic = [], None
     for op in range(4):
         g = max(grid_of[op])  # the 2^27 launches have the largest grid of their map
-        f = _pick(fetch, rf"stream_kernel<0, {op},", g)
-        w = _pick(write, rf"stream_kernel<0, {op},", g)
-        fk, wk = sum(f) / len(f), sum(w) / len(w)
-        fb, wb = fk * 1024 * ff, wk * 1024 * fw
+        d = cn.launch(rf"stream_kernel<0, {op},", g)
         reads = (ARRAYS[op] - 1) * N27 * 8
-        alg = reads + N27 * 8
-        L.append(f"| {OPS[op]} | {len(f)}/{len(w)} | {fk:.0f} | {wk:.0f} | {fb:.4e} | {wb:.4e} | "
-                 f"{reads:.4e} / {N27*8:.4e} | {(fb+wb)/alg:.4f} |")
+        rows.append((OPS[op], d, reads, N27 * 8))
         if op == 3:
-            traffic = fb + wb
-    L += ["", f"traffic_bytes_per_launch: {traffic:.6e}", f"kernel_source_digest: {digest}", ""]
-    open(os.path.join(PROFILES, "triad_f64_n2p27_pmc.md"), "w").write("\n".join(L))
+            traffic = d["read_bytes"] + d["write_bytes"]
+    L = ["# HBM traffic counters: STREAM f64, N = 2^27 per array", "",
+         "Four counter runs (each a run of its own), made by `python paper_2206_06302_amd/profiling.py run`:", "",
+         *pmc_cmds, "", *calib, "",
+         "Per launch of the headline maps (the 2^27 launches of the headline and of the closed-form checks):", "",
+         *_traffic_table(rows, ff, fw), "",
+         "Read and write requests all reach DRAM (TCC_EA0_RDREQ_DRAM_sum and TCC_EA0_WRREQ_DRAM_sum equal the",
+         "totals).  Copy's few extra writes are dirty lines of the preceding triad written back while it runs.",
+         "", f"traffic_bytes_per_launch: {traffic:.6e}", f"kernel_source_digest: {digest}", ""]
+    open(os.path.join(out, "stream_f64_n2p27_pmc.md"), "w").write("\n".join(L))
 
     # batched trace
     bb = _bench_json(os.path.join(raw, "trace_batched.json"))["batched"]
@@ -252,51 +326,49 @@ def summarize(raw: str) -> None:
          "```", "export TMPDIR=/tmp; cd /tmp", _command(cmds["batched trace"], raw), "```", "",
          f"Batch: 4096 instances, log-uniform lengths in [1e3, 1e7) (seed 5), {total} elements in total,",
          f"{3*total*8/1e9:.1f} GB on the device.  Each map is one launch over all instances, one workgroup",
-         f"per tile when grid/CU is 0: {tiles} tiles of {tile} elements (64-byte tile records).  Triad",
-         f"configuration: block {cfg['block']}, U{cfg['unroll']}, grid/CU {cfg['grid_per_cu']}, nontemporal "
-         f"loads {cfg['nt_load']} and stores {cfg['nt_store']}.",
-         "The four-map iteration runs 50 times from a captured graph plus 1 warm-up; the triad also runs",
-         "alone (1 + 20 launches).  GB/s = STREAM bytes of one launch / its average duration.", "",
+         f"per group of K consecutive tiles when grid/CU is 0 (the triad's plan: {tiles} tiles of {tile}",
+         f"elements, 64-byte tile records).  Triad configuration: block {cfg['block']}, U{cfg['unroll']}, K "
+         f"{cfg.get('tiles_per_wg', 1)}, grid/CU {cfg['grid_per_cu']}, nontemporal loads {cfg['nt_load']} and "
+         f"stores {cfg['nt_store']}.",
+         "The four-map iteration runs 50 times from a captured graph plus 1 warm-up; then each map runs",
+         "alone (1 + 10 launches; the triad 1 + 20).  GB/s = STREAM bytes of one launch / its average duration.", "",
          "| kernel | map | calls | avg ms | min ms | max ms | GB/s (avg) | GB/s (min time) |",
          "|---|---|---|---|---|---|---|---|"]
     for r in _stats(os.path.join(raw, "trace_batched", "run_kernel_stats.csv")):
-        m = re.search(r"batch_kernel<(\d+), (\d+), (\d+), (\w+), (\w+)>", r["Name"])
+        m = re.search(r"batch_kernel<(\d+), (\d+), (\d+), (\d+), (\w+), (\w+)>", r["Name"])
         if not m or m.group(1) != "0":
             continue
         op = int(m.group(2))
         b = ARRAYS[op] * total * 8
         avg, mn, mx = float(r["AverageNs"]), float(r["MinNs"]), float(r["MaxNs"])
-        L.append(f"| `batch_kernel<f64,{OPS[op]},U{m.group(3)},nt_load={int(m.group(4) == 'true')},"
-                 f"nt_store={int(m.group(5) == 'true')}>` | {OPS[op]} | {r['Calls']} | {avg/1e6:.3f} | "
+        L.append(f"| `batch_kernel<f64,{OPS[op]},U{m.group(3)},K{m.group(4)},nt_load={int(m.group(5) == 'true')},"
+                 f"nt_store={int(m.group(6) == 'true')}>` | {OPS[op]} | {r['Calls']} | {avg/1e6:.3f} | "
                  f"{mn/1e6:.3f} | {mx/1e6:.3f} | {b/avg:.1f} | {b/mn:.1f} |")
     L += ["", "From the same run (events on the target's stream, profiler attached):", "",
           f"* graph-replayed four-map iteration: {bb['graph_iteration_ms']} ms ({bb['graph_iteration_GBps']} GB/s)",
           f"* batched triad best {bb['triad_best_GBps']} GB/s, average {bb['triad_avg_GBps']} GB/s; one plain "
           f"launch per instance {bb['plain_per_instance_triad_best_GBps']} GB/s",
+          "* each map alone, average GB/s: " + ", ".join(f"{op} {v['avg_GBps']}" for op, v in bb["maps"].items()),
           f"* every element of every instance validated after the replays: {bb['valid_after_graph_replays']}", ""]
-    open(os.path.join(PROFILES, "batched_f64_4096_kernel_trace.md"), "w").write("\n".join(L))
+    open(os.path.join(out, "batched_f64_4096_kernel_trace.md"), "w").write("\n".join(L))
 
     # batched counters
-    bf, bw = _pick(fetch, r"batch_kernel<0, 3,"), _pick(write, r"batch_kernel<0, 3,")
-    fk, wk = sum(bf) / len(bf), sum(bw) / len(bw)
-    fetched, written = fk * 1024 * ff, wk * 1024 * fw
-    alg_r, alg_w, meta = 2 * total * 8, total * 8, tiles * 64
-    L = ["# HBM traffic counters: batched triad, 4096 FP64 instances", "",
-         "Two counter runs (FETCH_SIZE, then WRITE_SIZE; each a run of its own), made by",
-         "`python paper_2206_06302_amd/profiling.py run`:", "", *pmc_cmds, "", calib, "",
-         f"Batched triad (`batch_kernel<f64,triad,...>`, {len(bf)}/{len(bw)} dispatches), {tiles} tiles of "
-         f"{tile} elements:", "",
-         "| | counter KiB | scaled bytes | algorithmic bytes | ratio |", "|---|---|---|---|---|",
-         f"| fetched | {fk:.0f} | {fetched:.4e} | {alg_r:.4e} (b and c) + {meta:.3e} (tile records) | "
-         f"{fetched/(alg_r+meta):.4f} |",
-         f"| written | {wk:.0f} | {written:.4e} | {alg_w:.4e} (a) | {written/alg_w:.4f} |",
-         f"| total | | {fetched+written:.4e} | {alg_r+alg_w:.4e} STREAM bytes | {(fetched+written)/(alg_r+alg_w):.4f} |",
-         "", f"The tile records add {meta/(alg_r+alg_w)*100:.2f} % to the STREAM bytes.  Fetches run "
-         f"{(fetched/(alg_r+meta)-1)*100:.2f} % above b, c and the",
-         f"records together.  In all, HBM traffic per launch is {(fetched+written)/(alg_r+alg_w):.3f}x the STREAM bytes.",
-         "", f"traffic_bytes_per_launch: {fetched+written:.6e}", ""]
-    open(os.path.join(PROFILES, "batched_triad_f64_4096_pmc.md"), "w").write("\n".join(L))
-    print("wrote", ", ".join(sorted(os.listdir(PROFILES))))
+    bj = _bench_json(os.path.join(raw, "pmc_rdreq.json"))["batched"]
+    total, tiles = bj["total_elems"], bj["tiles"]
+    rows = []
+    for op in range(4):
+        d = cn.launch(rf"batch_kernel<0, {op},")
+        rows.append((OPS[op], d, (ARRAYS[op] - 1) * total * 8, total * 8))
+    L = ["# HBM traffic counters: batched ragged STREAM, 4096 FP64 instances", "",
+         "Four counter runs (each a run of its own), made by `python paper_2206_06302_amd/profiling.py run`:", "",
+         *pmc_cmds, "", *calib, "",
+         f"Per launch of each batched map over all {total} elements (dispatches of the captured iteration and",
+         "of the maps timed alone).  Each map also reads its tile table: 64 bytes per tile, "
+         f"{tiles} tiles of the triad's size ({tiles * 64:.3e} bytes).", "",
+         *_traffic_table(rows, ff, fw), "",
+         f"traffic_bytes_per_launch (triad): {rows[3][1]['read_bytes'] + rows[3][1]['write_bytes']:.6e}", ""]
+    open(os.path.join(out, "batched_f64_4096_pmc.md"), "w").write("\n".join(L))
+    print("wrote", ", ".join(sorted(os.listdir(out))))
 
 
 def main() -> int:
@@ -304,10 +376,11 @@ def main() -> int:
     ap.add_argument("action", choices=("run", "summarize"))
     ap.add_argument("--raw", required=True, help="directory of the raw profiler output")
     ap.add_argument("--timeout", type=int, default=300, help="seconds allowed per profiler run")
+    ap.add_argument("--out", default=PROFILES, help="directory for the summaries (default: profiles/)")
     a = ap.parse_args()
     if a.action == "run":
         return run(a.raw, a.timeout)
-    summarize(a.raw)
+    summarize(a.raw, a.out)
     return 0
 
 

@@ -57,7 +57,7 @@ def test_binding_covers_every_function(ts):
 
 
 def test_version_and_errors(ts):
-    assert ts.version() == (1, 0)
+    assert ts.version() == (2, 0)
     L = ts.lib
     assert L.ts_copy(None, None, None) == TS_E_INVALID
     assert "invalid" in ts.last_error()
@@ -117,13 +117,23 @@ def test_tune_table_roundtrip(ts, tmp_path):
     assert ts.get_kernel_cfg("triad", "f64", 4 << 30, batched=True)["tile_elems"] == 65536
     # mixed misalignment falls back to the element-wise width by default
     assert ts.get_kernel_cfg("add", "f32", 1000, align_class=2)["vec_bytes"] == 4
+    # an entry without tiles_per_wg (written before the field) holds one tile per workgroup
+    assert ts.get_kernel_cfg("triad", "f64", 4 << 30, batched=True)["tiles_per_wg"] == 1
+    doc["entries"].append({"op": "copy", "dtype": "f64", "bucket": 32, "align": 0, "batched": 1, "block": 256,
+                           "unroll": 1, "vec_bytes": 16, "nt_load": 1, "nt_store": 1, "grid_per_cu": 0,
+                           "tile_elems": 512, "tiles_per_wg": 4})
+    p.write_text(json.dumps(doc))
+    ts.tune_cache_load(str(p))
+    assert ts.get_kernel_cfg("copy", "f64", 4 << 30, batched=True)["tiles_per_wg"] == 4
     q = tmp_path / "u.json"
     ts.tune_cache_save(str(q))
     saved = json.loads(q.read_text())
-    assert saved["format"] == "tstream-tune" and len(saved["entries"]) == 3
+    assert saved["format"] == "tstream-tune" and len(saved["entries"]) == 4
+    assert {e["op"]: e["tiles_per_wg"] for e in saved["entries"] if e["batched"]} == {"triad": 1, "copy": 4}
     ts.tune_cache_clear()
     ts.tune_cache_load(str(q))
     assert ts.get_kernel_cfg("triad", "f64", 1 << 27)["block"] == 512
+    assert ts.get_kernel_cfg("copy", "f64", 4 << 30, batched=True)["tiles_per_wg"] == 4
     ts.tune_cache_clear()
 
 
@@ -177,6 +187,20 @@ def test_forced_configuration(ts):
         cfg.update(bad)
         with pytest.raises(ts.TSError):
             ts.set_kernel_cfg("copy", "f64", cfg, batched=True)
+    # several tiles per workgroup: 1, 2, 4 or 8, with unroll 1 or 2; plain kernels take 0 or 1
+    for bad in ({"tiles_per_wg": 3}, {"tiles_per_wg": 16}, {"tiles_per_wg": -1},
+                {"tiles_per_wg": 2, "unroll": 4}, {"reserved": 1}):
+        cfg = {"block": 256, "unroll": 1, "vec_bytes": 16, "nt_load": 1, "nt_store": 1, "grid_per_cu": 0,
+               "tile_elems": 512}
+        cfg.update(bad)
+        with pytest.raises(ts.TSError):
+            ts.set_kernel_cfg("copy", "f64", cfg, batched=True)
+    with pytest.raises(ts.TSError):
+        ts.set_kernel_cfg("copy", "f64", {"block": 256, "unroll": 1, "vec_bytes": 16, "tiles_per_wg": 2})
+    ts.set_kernel_cfg("add", "f64", {"block": 256, "unroll": 2, "vec_bytes": 16, "nt_load": 1, "nt_store": 1,
+                                     "grid_per_cu": 0, "tile_elems": 1024, "tiles_per_wg": 8}, batched=True)
+    assert ts.get_kernel_cfg("add", "f64", 1 << 30, batched=True)["tiles_per_wg"] == 8
+    ts.set_kernel_cfg("add", "f64", None, batched=True)
     # grid_per_cu 0 on the batched path: one workgroup per tile
     ts.set_kernel_cfg("copy", "f64", {"block": 1024, "unroll": 4, "vec_bytes": 16, "nt_load": 1, "nt_store": 1,
                                       "grid_per_cu": 0, "tile_elems": 4096}, batched=True)
@@ -195,6 +219,8 @@ def test_candidate_sets_are_valid(ts):
     for c in batched:
         ts.set_kernel_cfg("copy", "f64", c, batched=True)
         assert c["tile_elems"] % 8 == 0
+    assert {c["tiles_per_wg"] for c in batched} == {1, 2, 4, 8}
+    assert all(c["unroll"] <= 2 for c in batched if c["tiles_per_wg"] > 1)
     ts.set_kernel_cfg("copy", "f64", None)
     ts.set_kernel_cfg("copy", "f64", None, batched=True)
 

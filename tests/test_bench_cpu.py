@@ -65,7 +65,9 @@ def test_summary_is_the_last_key():
               "ceiling": {name: {"avg_GBps": 6600.0} for name, _, _ in bench.PROBE_KINDS},
               "batched": {"triad_best_GBps": 6300.0, "triad_avg_GBps": 6290.0, "triad_vs_plain_n2p27_triad": 0.97,
                           "graph_iteration_GBps": 6200.0, "valid_after_graph_replays": True,
-                          "valid_after_triad_launches": True},
+                          "valid_after_map_launches": True,
+                          "maps": {op: {"avg_GBps": 6208.0} for op in bench.OPS},
+                          "maps_avg_vs_plain_avg": {op: 0.97 for op in bench.OPS}},
               "cpu_baseline": {"value": 250.0, "cores": 16, "valid": True}, "sweep": {}}
     out = bench.order_for_output(result)
     keys = list(out)
@@ -73,6 +75,7 @@ def test_summary_is_the_last_key():
     s = out["summary"]
     assert s["triad_avg_vs_2r1w_ceiling"] == round(6400 / 6600, 4) and s["batched"]["valid"] is True
     assert "triad 6500/6400" in bench.summary_text(s)
+    assert s["batched"]["maps_avg_GBps"]["copy"] == 6208.0 and "copy 6208 (0.970)" in bench.summary_text(s)
 
 
 @pytest.mark.parametrize("args,code,text", [(["--gpus", "2"], 2, "exactly one GPU"),
@@ -120,6 +123,11 @@ def test_profiler_runs_follow_the_rules():
         after = cmd[cmd.index("--") + 1:]
         assert after[0] == sys.executable and after[1].endswith("bench.py")
         if "--pmc" in cmd:
-            assert len(cmd[cmd.index("--pmc") + 1].split()) == 1
+            counters = cmd[cmd.index("--pmc") + 1:cmd.index("--output-format")]
+            # within one pass: at most 4 TCC counters (FETCH_SIZE alone takes 3, WRITE_SIZE 2)
+            tcc = sum(3 if c == "FETCH_SIZE" else 2 if c == "WRITE_SIZE" else int(c.startswith("TCC_"))
+                      for c in counters)
+            assert 1 <= len(counters) and tcc <= 4, counters
             assert not {"--kernel-trace", "--sys-trace", "--runtime-trace", "-s", "-r"} & set(cmd[:cmd.index("--")])
-    assert names == ["headline trace", "batched trace", "fetch counters", "write counters"]
+    assert names == ["headline trace", "batched trace", "fetch counters", "write counters", "read requests",
+                     "write requests"]

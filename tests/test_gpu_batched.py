@@ -346,11 +346,13 @@ def test_batch_launch_shapes_do_not_change_results(env, dtype):
         ref.fill_uniform(tgt, k, 6)
     for op in OPS:
         ref.op_plain(tgt, op)
-    shapes = [(0, 256, 1, 24), (0, 1024, 4, 4096), (0, 512, 2, 2048), (1, 1024, 8, 16384), (64, 64, 1, 8)]
+    # (grid_per_cu, block, unroll, tile, tiles per workgroup)
+    shapes = [(0, 256, 1, 24, 1), (0, 1024, 4, 4096, 1), (0, 512, 2, 2048, 1), (1, 1024, 8, 16384, 1),
+              (64, 64, 1, 8, 1), (0, 256, 1, 24, 8), (0, 512, 2, 1024, 4), (2, 256, 2, 512, 2), (0, 64, 1, 8, 4)]
     try:
-        for grid, block, unroll, tile in shapes:
+        for grid, block, unroll, tile, per_wg in shapes:
             cfg = {"block": block, "unroll": unroll, "vec_bytes": 16, "nt_load": 1, "nt_store": 1,
-                   "grid_per_cu": grid, "tile_elems": tile}
+                   "grid_per_cu": grid, "tile_elems": tile, "tiles_per_wg": per_wg}
             for op in OPS:
                 ts.set_kernel_cfg(op, dtype, cfg, batched=True)
             pool = Pool(ts, torch, lens, dtype, mis)
@@ -358,7 +360,7 @@ def test_batch_launch_shapes_do_not_change_results(env, dtype):
             b.set_tile(tile)
             for k in range(3):
                 b.fill_uniform(tgt, k, 6)
-            say(f"[launch shape grid_per_cu={grid} block={block} U{unroll} tile={tile} {dtype}]")
+            say(f"[launch shape grid_per_cu={grid} block={block} U{unroll} tile={tile} x{per_wg} {dtype}]")
             for op in OPS:
                 b.op(tgt, op)
             tgt.synchronize()
