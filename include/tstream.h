@@ -117,11 +117,17 @@ typedef struct {
     char name[128];
 } ts_device_info;
 
-/* Create a target on `device` ordered on `hip_stream`, a hipStream_t of that
- * device (e.g. torch.cuda.Stream().cuda_stream) which the target borrows.
- * NULL is the device's default stream, as in HIP (graph capture is not
- * available on it).  Errors: TS_E_INVALID (out NULL, device out of range),
- * TS_E_DEVICE (no usable GPU / HIP failure), TS_E_OOM. */
+/* Create a target on `device` (Section 4.2: a GPU target is a device and a
+ * stream).  `hip_stream`:
+ *   NULL              a non-blocking stream the library creates and destroys
+ *                     with the target (as ts_target_create_owned);
+ *   hipStreamLegacy   ((void*)1) the device's legacy default stream, which
+ *                     orders with every blocking stream (graph capture is
+ *                     not available on it);
+ *   any other         a hipStream_t of that device (e.g.
+ *                     torch.cuda.Stream().cuda_stream), borrowed.
+ * Errors: TS_E_INVALID (out NULL, device out of range), TS_E_DEVICE (no
+ * usable GPU / HIP failure), TS_E_OOM. */
 TS_API int ts_target_create(int device, void *hip_stream, ts_target *out);
 /* Same, on a non-blocking stream the library creates and destroys with the
  * target. */

@@ -44,6 +44,7 @@ OPS = {"copy": 0, "scale": 1, "add": 2, "triad": 3}
 ALIGN_16, ALIGN_SHARED, ALIGN_MIXED = 0, 1, 2
 # STREAM bytes per element: copy/scale move two arrays, add/triad three.
 ARRAYS_MOVED = {"copy": 2, "scale": 2, "add": 3, "triad": 3}
+HIP_STREAM_LEGACY = 1  # HIP's handle of a device's legacy default stream (hipStreamLegacy)
 
 DEFAULT_TUNE_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune", "gfx950.json")
 
@@ -123,7 +124,10 @@ class Target:
                 raw = stream.cuda_stream
             else:
                 raw = int(stream)
-            _check(lib.ts_target_create(int(device), ctypes.c_void_p(raw) if raw else None, ctypes.byref(h)))
+            # torch's default stream is the legacy null stream: pass HIP's
+            # handle for it (NULL would ask for a stream of the library's own)
+            _check(lib.ts_target_create(int(device), ctypes.c_void_p(raw if raw else HIP_STREAM_LEGACY),
+                                        ctypes.byref(h)))
         self.handle = h
         self.device = int(device)
         self._callbacks = []

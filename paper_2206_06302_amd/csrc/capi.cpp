@@ -405,6 +405,10 @@ int ts_host_domain_cpus(int domain, int* cpus, int cap, int* count) {
 
 int ts_target_create(int device, void* hip_stream, ts_target* out) {
   TS_GUARD_BEGIN
+  // NULL: a non-blocking stream of the library's own.  hipStreamLegacy: the
+  // device's legacy default stream, kept as the null handle.
+  if (!hip_stream) return create_target(device, nullptr, true, out);
+  if (hip_stream == static_cast<void*>(hipStreamLegacy)) return create_target(device, nullptr, false, out);
   return create_target(device, hip_stream, false, out);
   TS_GUARD_END
 }

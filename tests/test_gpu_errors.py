@@ -110,6 +110,34 @@ def test_graph_capture_needs_a_stream(env):
     dflt.close()
 
 
+def test_target_stream_choices_through_the_abi(env):
+    """ts_target_create with NULL makes a non-blocking stream of the
+    library's own (graph capture works on it); hipStreamLegacy binds the
+    device's legacy default stream (the null handle; capture refused)."""
+    ts, torch, tgt = env
+    h = ctypes.c_void_p()
+    assert ts.lib.ts_target_create(0, None, ctypes.byref(h)) == 0, ts.last_error()
+    null_arg = ts.Target.__new__(ts.Target)
+    null_arg.handle, null_arg.device, null_arg._torch_stream, null_arg._callbacks = h, 0, None, []
+    assert null_arg.stream_handle() not in (0, ts.HIP_STREAM_LEGACY)
+    a, b, c = (ts.Array.alloc(null_arg, "f64", 1000) for _ in range(3))
+    for arr in (a, b, c):
+        arr.fill(1.0)
+    g = ts.Graph.capture_arrays_iteration(null_arg, a, b, c)
+    g.launch(null_arg, 2)
+    null_arg.synchronize()
+    assert ts.checksum(null_arg, a, 225.0)["mismatches"] == 0  # (1, 1, 1) -> (15, 3, 4) -> a = 225
+    g.close()
+    h2 = ctypes.c_void_p()
+    assert ts.lib.ts_target_create(0, ctypes.c_void_p(ts.HIP_STREAM_LEGACY), ctypes.byref(h2)) == 0
+    legacy = ts.Target.__new__(ts.Target)
+    legacy.handle, legacy.device, legacy._torch_stream, legacy._callbacks = h2, 0, None, []
+    assert legacy.stream_handle() == 0
+    assert status(ts, lambda: ts.Graph.capture_arrays_iteration(legacy, a, b, c)) == E_UNSUPPORTED
+    legacy.close()
+    null_arg.close()
+
+
 def test_graph_refuses_freed_arrays(env):
     """A graph over library-owned arrays refuses to launch once one of them
     has been freed, instead of touching freed memory."""
