@@ -54,6 +54,8 @@ int batch_replan(ts_batch_s* b, int64_t tile_elems) {
   if (!b->d_expected && !descs.empty()) {
     TS_HIP(hipMalloc(&b->d_expected, descs.size() * sizeof(double)));
     TS_HIP(hipMalloc(&b->d_counts, descs.size() * sizeof(unsigned long long)));
+    TS_HIP(hipHostMalloc(&b->h_expected, descs.size() * sizeof(double), hipHostMallocDefault));
+    TS_HIP(hipHostMalloc(&b->h_counts, descs.size() * sizeof(unsigned long long), hipHostMallocDefault));
   }
   BatchTile* d_new = nullptr;
   if ((st = upload_tiles(b->target, tiles, &d_new)) != TS_OK) return st;
@@ -205,6 +207,8 @@ int ts_batch_create(ts_target t, ts_dtype dtype, const ts_batch_desc* descs, siz
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     if (b->d_expected) (void)hipFree(b->d_expected);
     if (b->d_counts) (void)hipFree(b->d_counts);
+    if (b->h_expected) (void)hipHostFree(b->h_expected);
+    if (b->h_counts) (void)hipHostFree(b->h_counts);
     delete b;
     return status;
   };
@@ -251,6 +255,8 @@ int ts_batch_destroy(ts_batch b) {
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   if (b->d_expected) (void)hipFree(b->d_expected);
   if (b->d_counts) (void)hipFree(b->d_counts);
+  if (b->h_expected) (void)hipHostFree(b->h_expected);
+  if (b->h_counts) (void)hipHostFree(b->h_counts);
   *b->plan_epoch = kDeadEpoch;
   b->magic = kDead;
   delete b;
@@ -349,7 +355,10 @@ int ts_batch_mismatch_count(ts_target exec, ts_batch b, int which, const double*
   const size_t n = b->host.size();
   if (n == 0) return TS_OK;
   if (!expected || !counts) return fail(TS_E_INVALID, "NULL expected or counts");
-  TS_HIP(hipMemcpyAsync(b->d_expected, expected, n * sizeof(double), hipMemcpyHostToDevice, exec->stream));
+  // The staging buffers are free: every earlier call ended with a stream
+  // synchronisation after its last copy.
+  std::memcpy(b->h_expected, expected, n * sizeof(double));
+  TS_HIP(hipMemcpyAsync(b->d_expected, b->h_expected, n * sizeof(double), hipMemcpyHostToDevice, exec->stream));
   hipError_t e = launch_zero_u64(b->d_counts, n, exec->stream);
   if (e != hipSuccess) return hip_fail(e, "zero kernel launch");
   if (!b->tiles.empty()) {
@@ -357,8 +366,9 @@ int ts_batch_mismatch_count(ts_target exec, ts_batch b, int which, const double*
                               b->d_counts, aux_grid(b->tiles.size()), exec->stream);
     if (e != hipSuccess) return hip_fail(e, "batched mismatch launch");
   }
-  TS_HIP(hipMemcpyAsync(counts, b->d_counts, n * sizeof(uint64_t), hipMemcpyDeviceToHost, exec->stream));
+  TS_HIP(hipMemcpyAsync(b->h_counts, b->d_counts, n * sizeof(uint64_t), hipMemcpyDeviceToHost, exec->stream));
   TS_HIP(hipStreamSynchronize(exec->stream));
+  std::memcpy(counts, b->h_counts, n * sizeof(uint64_t));
   return TS_OK;
   TS_GUARD_END
 }

@@ -75,6 +75,11 @@ struct ts_batch_s {
   ts::BatchTile* d_tiles;
   double* d_expected;
   unsigned long long* d_counts;
+  // Pinned host staging for the mismatch count's expected values and
+  // counts: copies from pageable memory are staged by the runtime on every
+  // call, which cost more than the count itself.
+  double* h_expected;
+  unsigned long long* h_counts;
   uint64_t total;
   int64_t tile_elems;
   // Device plans for the other tile sizes that the maps' tuned configurations

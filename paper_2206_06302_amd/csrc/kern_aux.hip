@@ -289,7 +289,17 @@ __device__ __forceinline__ uint64_t head_of(const T* p) {
 
 // Tiles [c, c + per_wg) of the table go to workgroup c / per_wg (striding
 // by the grid over any beyond it): fewer, longer workgroups than one per
-// tile, which the hardware dispatches at a limited rate.
+// tile, which the hardware dispatches at a limited rate.  A workgroup reads
+// the records of its group together (scalar loads issued back to back), so
+// it waits on the table once per group, not once per tile.
+constexpr uint32_t kAuxMaxTilesPerWg = 4;
+
+#define TS_FOR_TILE_GROUPS(c0, cnt)                                                               \
+  for (uint64_t c0 = static_cast<uint64_t>(blockIdx.x) * per_wg, cnt = 0; c0 < ntiles;             \
+       c0 += static_cast<uint64_t>(gridDim.x) * per_wg)                                           \
+    if ((cnt = ntiles - c0 < per_wg ? ntiles - c0 : per_wg), true)
+
+// Tile by tile, for kernels that wait on each tile's data anyway.
 #define TS_FOR_TILES(t)                                                                           \
   for (uint64_t c_ = static_cast<uint64_t>(blockIdx.x) * per_wg; c_ < ntiles;                    \
        c_ += static_cast<uint64_t>(gridDim.x) * per_wg)                                           \
@@ -307,28 +317,35 @@ __global__ __launch_bounds__(256) void batch_fill_kernel(const BatchTile* __rest
   using T = typename Fmt<DT>::T;
   using R = typename Raw<16>::type;
   constexpr uint64_t V = 16 / sizeof(T);
-  TS_FOR_TILES(t) {
-    const BatchTile tl = tiles[t];
-    T* dp = static_cast<T*>(const_cast<void*>(which == 0 ? tl.a : which == 1 ? tl.b : tl.c));
-    Global<T>* d = global_ptr(dp);  // global_load/store, not flat (see ts_device.hpp)
-    const uint64_t state0 = seed ^ ((16ull + 3ull * tl.inst + static_cast<uint64_t>(which)) << 48);
-    const T cv = from_f64<DT>(value);
-    auto at = [&](uint64_t j) {
-      if constexpr (UNIFORM) return from_f64<DT>(uniform_pm1(state0, j + 1));
-      else return cv;
-    };
-    const uint64_t end = tl.start + tl.count;
-    uint64_t vs, ve;
-    tile_vectors(tl.start, end, head_of(dp), V, vs, ve);
-    for (uint64_t j = tl.start + threadIdx.x; j < vs; j += blockDim.x) d[j] = at(j);
-    for (uint64_t j = ve + threadIdx.x; j < end; j += blockDim.x) d[j] = at(j);
-    Global<R>* dv = reinterpret_cast<Global<R>*>(d + vs);
-    const uint64_t nvec = (ve - vs) / V;
-    for (uint64_t k = threadIdx.x; k < nvec; k += blockDim.x) {
-      Splat<T> v;
+  TS_FOR_TILE_GROUPS(c0, cnt) {
+    BatchTile group[kAuxMaxTilesPerWg];  // past the group's end: its last record again, unused
 #pragma unroll
-      for (uint64_t e = 0; e < V; ++e) v.e[e] = at(vs + k * V + e);
-      __builtin_nontemporal_store(__builtin_bit_cast(R, v), dv + k);
+    for (uint32_t g = 0; g < kAuxMaxTilesPerWg; ++g) group[g] = tiles[c0 + (g < cnt ? g : cnt - 1)];
+#pragma unroll
+    for (uint32_t g = 0; g < kAuxMaxTilesPerWg; ++g) {
+      if (g >= cnt) break;
+      const BatchTile& tl = group[g];
+      T* dp = static_cast<T*>(const_cast<void*>(which == 0 ? tl.a : which == 1 ? tl.b : tl.c));
+      Global<T>* d = global_ptr(dp);  // global_load/store, not flat (see ts_device.hpp)
+      const uint64_t state0 = seed ^ ((16ull + 3ull * tl.inst + static_cast<uint64_t>(which)) << 48);
+      const T cv = from_f64<DT>(value);
+      auto at = [&](uint64_t j) {
+        if constexpr (UNIFORM) return from_f64<DT>(uniform_pm1(state0, j + 1));
+        else return cv;
+      };
+      const uint64_t end = tl.start + tl.count;
+      uint64_t vs, ve;
+      tile_vectors(tl.start, end, head_of(dp), V, vs, ve);
+      Global<R>* dv = reinterpret_cast<Global<R>*>(d + vs);
+      const uint64_t nvec = (ve - vs) / V;
+      for (uint64_t k = threadIdx.x; k < nvec; k += blockDim.x) {
+        Splat<T> v;
+#pragma unroll
+        for (uint64_t e = 0; e < V; ++e) v.e[e] = at(vs + k * V + e);
+        __builtin_nontemporal_store(__builtin_bit_cast(R, v), dv + k);
+      }
+      for (uint64_t j = tl.start + threadIdx.x; j < vs; j += blockDim.x) d[j] = at(j);
+      for (uint64_t j = ve + threadIdx.x; j < end; j += blockDim.x) d[j] = at(j);
     }
   }
 }
@@ -506,6 +523,7 @@ hipError_t launch_mismatch(int dt, const void* x, const void* ref, uint64_t n, v
 
 hipError_t launch_batch_fill(int dt, const BatchTile* tiles, uint64_t ntiles, uint32_t per_wg, int which,
                              int uniform, double value, uint64_t seed, uint32_t grid, hipStream_t s) {
+  if (per_wg < 1 || per_wg > kAuxMaxTilesPerWg) return hipErrorInvalidValue;
   if (uniform) {
     TS_BY_FORMAT_U(dt, true, dim3(grid), dim3(256), 0, s, tiles, ntiles, per_wg, which, value, seed)
   }

@@ -3,11 +3,12 @@
     python paper_2206_06302_amd/profiling.py run --raw DIR        # on a machine with the GPU
     python paper_2206_06302_amd/profiling.py summarize --raw DIR  # anywhere: rewrites profiles/*.md
 
-`run` starts six rocprofv3 runs, each a process of its own with the program
+`run` starts seven rocprofv3 runs, each a process of its own with the program
 directly after `--`, from /tmp with TMPDIR=/tmp:
 
   headline trace   --kernel-trace --stats of bench.py --quick --no-cpu --warmup 1 --steps 20
   batched trace    --kernel-trace --stats of bench.py --no-cpu --legs batched --warmup 1 --steps 20
+  reduced trace    --kernel-trace         of bench.py --no-cpu --legs reduced_precision --warmup 1 --steps 3
   fetch counters   --pmc FETCH_SIZE       of bench.py --no-cpu --legs calibration,batched --no-per-instance
                                           --warmup 1 --steps 3
   write counters   --pmc WRITE_SIZE       of the same command
@@ -15,9 +16,10 @@ directly after `--`, from /tmp with TMPDIR=/tmp:
   write requests   --pmc TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum TCC_EA0_WRREQ_DRAM_sum
 
 `summarize` turns the raw CSV files into short markdown summaries: the
-per-kernel trace of the headline and of the batched leg (with the bench's own
-event timings from the same runs beside rocprof's), and the HBM traffic per
-launch of the four headline maps and the four batched maps.
+per-kernel trace of the headline, of the batched leg (with the bench's own
+event timings from the same runs beside rocprof's) and of the maps on
+reduced-precision storage, and the HBM traffic per launch of the four
+headline maps and the four batched maps.
 
 HBM bytes come from the L2-to-memory request counts: on gfx950 every read
 request that is not a 32-byte one moves 128 bytes, and write requests move
@@ -97,6 +99,10 @@ def runs(raw: str) -> list[tuple[str, list[str], str]]:
                            os.path.join(raw, "trace_batched"), "-o", "run", "--",
                            *_bench("--no-cpu", "--legs", "batched", "--warmup", "1", "--steps", "20")],
          os.path.join(raw, "trace_batched.json")),
+        ("reduced trace", ["rocprofv3", "--kernel-trace", "--output-format", "csv", "-d",
+                           os.path.join(raw, "trace_reduced"), "-o", "run", "--",
+                           *_bench("--no-cpu", "--legs", "reduced_precision", "--warmup", "1", "--steps", "3")],
+         os.path.join(raw, "trace_reduced.json")),
     ]
     for name, sub, counters in PMC_RUNS:
         out.append((name, ["rocprofv3", "--pmc", *counters, "--output-format", "csv", "-d", os.path.join(raw, sub),
@@ -152,6 +158,53 @@ def _pick(vals, pattern, grid=None):
 
 def _bench_json(path):
     return json.loads(open(path).read().strip().splitlines()[-1])
+
+
+DT_NAMES = {0: "f64", 1: "f32", 2: "bf16", 3: "f16"}
+DT_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
+
+
+def _reduced_summary(raw, cmd):
+    """Per storage type and map, the average duration of the 2^28-element
+    launches (the largest grid of each kernel) from the per-dispatch trace."""
+    n = 1 << 28
+    rows = {}
+    for f in glob.glob(os.path.join(raw, "trace_reduced", "**", "*kernel_trace.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            m = re.search(r"stream_kernel<(\d+), (\d+), (\d+), (\d+), (\w+), (\w+)>", r["Kernel_Name"])
+            if not m:
+                continue
+            key = (int(m.group(1)), int(m.group(2)))
+            grid = int(r["Grid_Size_X"])
+            dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            shape = f"VB{m.group(3)},U{m.group(4)},nt_load={int(m.group(5) == 'true')},nt_store={int(m.group(6) == 'true')}"
+            rows.setdefault(key, {}).setdefault(grid, []).append((dur, shape))
+    bj = _bench_json(os.path.join(raw, "trace_reduced.json"))["reduced_precision"]
+    L = ["# Kernel trace: STREAM maps on reduced-precision storage, N = 2^28 per array (bench reduced leg)", "",
+         "Made by `python paper_2206_06302_amd/profiling.py run` (then `summarize`); the run:", "",
+         "```", "export TMPDIR=/tmp; cd /tmp", cmd, "```", "",
+         "Binary64 storage beside binary32, bfloat16 and binary16 storage (arithmetic in binary32 for the",
+         "16-bit types).  Per storage type and map: the launches over 2^28 elements (2 warm-up, 10 timed, 1",
+         "for the error figure), their average duration from the trace, STREAM bytes / that duration, and",
+         "elements per second against binary64's.", "",
+         "| storage | map | kernel shape | dispatches | avg µs | GB/s (avg) | Gelem/s | elements/s vs f64 | "
+         "bench events GB/s |", "|---|---|---|---|---|---|---|---|---|"]
+    rate64 = {}
+    for dt in range(4):
+        for op in range(4):
+            if (dt, op) not in rows:
+                continue
+            grid = max(rows[(dt, op)])
+            launches = rows[(dt, op)][grid]
+            avg = sum(d for d, _ in launches) / len(launches)
+            gb = ARRAYS[op] * n * DT_BYTES[dt] / avg
+            ge = n / avg
+            if dt == 0:
+                rate64[op] = ge
+            ev = bj.get(DT_NAMES[dt], {}).get(OPS[op], {}).get("GBps", "")
+            L.append(f"| {DT_NAMES[dt]} | {OPS[op]} | `{launches[0][1]}` | {len(launches)} | {avg / 1e3:.1f} | {gb:.1f} | "
+                     f"{ge:.2f} | {ge / rate64[op]:.2f} | {ev} |" if op in rate64 else "")
+    return L + [""]
 
 
 def _plain_name(name):
@@ -351,6 +404,10 @@ def summarize(raw: str, out: str = PROFILES) -> None:
           "* each map alone, average GB/s: " + ", ".join(f"{op} {v['avg_GBps']}" for op, v in bb["maps"].items()),
           f"* every element of every instance validated after the replays: {bb['valid_after_graph_replays']}", ""]
     open(os.path.join(out, "batched_f64_4096_kernel_trace.md"), "w").write("\n".join(L))
+
+    # reduced-precision trace
+    L = _reduced_summary(raw, _command(cmds["reduced trace"], raw))
+    open(os.path.join(out, "stream_reduced_n2p28_kernel_trace.md"), "w").write("\n".join(L))
 
     # batched counters
     bj = _bench_json(os.path.join(raw, "pmc_rdreq.json"))["batched"]
