@@ -337,9 +337,10 @@ def batched_leg(ts, torch, tgt, count=4096, seed=5, replays=50, triad_reps=20, m
     return out
 
 
-def reduced_leg(ts, torch, tgt, n=1 << 28, reps=10, samples=1 << 14):
+def reduced_leg(ts, torch, tgt, n=1 << 28, reps=10, samples=1 << 14, chain_steps=20):
     """Storage as f64/f32/bf16/f16 (arithmetic in binary32 for the narrow
-    types), N = 2^28 per array: GB/s and elements/s per map, and the maximum
+    types), N = 2^28 per array: per map, GB/s over a chain of 1 + 20
+    iterations and over standalone launches, elements/s, and the maximum
     relative error of each map against binary64 arithmetic on the same
     stored inputs (numpy, on sampled elements; normal results only)."""
     import numpy as np
@@ -359,12 +360,35 @@ def reduced_leg(ts, torch, tgt, n=1 << 28, reps=10, samples=1 << 14):
         roles = {"copy": (A, None, C, 0, None, 2), "scale": (C, None, B, 2, None, 1),
                  "add": (A, B, C, 0, 1, 2), "triad": (B, C, A, 1, 2, 0)}
         res = {}
+        # the chain: 1 warm-up and `chain_steps` timed iterations of the four
+        # maps in listing order, per-kernel events (values grow 15-fold per
+        # iteration and reach infinity in the 16-bit types; the traffic is
+        # the same)
+        ev = [[ts.Event(timing=True) for _ in range(5)] for _ in range(chain_steps)]
+        ts.stream_iteration(tgt, A, B, C, 3.0)
+        for st in range(chain_steps):
+            ev[st][0].record(tgt)
+            for k, op in enumerate(OPS):
+                x, y, d = roles[op][:3]
+                ts.run_op(tgt, op, x, y, d, 3.0)
+                ev[st][k + 1].record(tgt)
+        tgt.synchronize()
+        chain = {}
+        for k, op in enumerate(OPS):
+            ms_list = [ev[st][k].elapsed_ms(ev[st][k + 1]) for st in range(chain_steps)]
+            b = ts.stream_bytes(op, n, dtype)
+            chain[op] = {"avg_GBps": round(b / (sum(ms_list) / len(ms_list)) / 1e6, 1),
+                         "best_GBps": round(b / min(ms_list) / 1e6, 1)}
+        # standalone maps from the seeded inputs again
+        A.fill_uniform(4, 0), B.fill_uniform(4, 1), C.fill_uniform(4, 2)
+        tgt.synchronize()
         for op in OPS:
             x, y, d, ix, iy, idst = roles[op]
             ts.time_op(tgt, op, x, y, d, 3.0, reps=2)
             ms = ts.time_op(tgt, op, x, y, d, 3.0, reps=reps) / reps
             b = ts.stream_bytes(op, n, dtype)
-            res[op] = {"GBps": round(b / ms / 1e6, 1), "Gelem_per_s": round(n / ms / 1e6, 2)}
+            res[op] = {"GBps": round(b / ms / 1e6, 1), "Gelem_per_s": round(n / ms / 1e6, 2),
+                       "chain_avg_GBps": chain[op]["avg_GBps"], "chain_best_GBps": chain[op]["best_GBps"]}
             # one more standalone application from known inputs for the error figure
             for k in range(3):
                 tt[k][tidx] = torch.from_numpy(xs[k]).to(tt[k].dtype).cuda()

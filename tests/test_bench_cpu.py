@@ -129,5 +129,5 @@ def test_profiler_runs_follow_the_rules():
                       for c in counters)
             assert 1 <= len(counters) and tcc <= 4, counters
             assert not {"--kernel-trace", "--sys-trace", "--runtime-trace", "-s", "-r"} & set(cmd[:cmd.index("--")])
-    assert names == ["headline trace", "batched trace", "fetch counters", "write counters", "read requests",
-                     "write requests"]
+    assert names == ["headline trace", "batched trace", "reduced trace", "fetch counters", "write counters",
+                     "read requests", "write requests"]

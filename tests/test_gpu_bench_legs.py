@@ -40,3 +40,16 @@ def test_transform_and_overhead_legs(env):
     assert t["same_bits"] and t["avg_ratio"] > 0
     o = bench.overhead_leg(ts, torch, tgt, lo=12, hi=14, iters=32, per_graph=16)
     assert set(o) == {"2^12", "2^14"} and all(r["graph16_us_per_iteration"] > 0 for r in o.values())
+
+
+def test_reduced_and_calibration_legs(env):
+    bench, ts, torch, tgt = env
+    r = bench.reduced_leg(ts, torch, tgt, n=(1 << 20) + 5, reps=2, samples=512, chain_steps=3)
+    for dtype in ("f64", "f32", "bf16", "f16"):
+        for op in ("copy", "scale", "add", "triad"):
+            e = r[dtype][op]
+            assert e["GBps"] > 0 and e["chain_avg_GBps"] > 0 and e["chain_best_GBps"] >= e["chain_avg_GBps"]
+    assert r["f32"]["copy"]["max_rel_err_vs_f64"] == 0.0
+    c = bench.calibration_leg(ts, tgt, 1 << 20, reps=2)
+    assert c["read_1r"]["bytes_read"] == 8 << 20 and c["write_1w"]["bytes_written"] == 8 << 20
+    assert all(c[k]["avg_GBps"] > 0 for k in ("read_1r", "write_1w", "copy_1r1w"))
