@@ -205,7 +205,9 @@ def ceiling_leg(ts, tgt, n, reps=20):
     straight-line probe (ts_probe_bandwidth) reads one or two arrays and
     writes none or one, over a search of launch shapes; per mix, the shape
     with the best average over `reps` launches.  Bytes = arrays touched x
-    array bytes, as the STREAM convention counts them."""
+    array bytes, as the STREAM convention counts them.  Then the library's
+    four maps in their tuned shapes, each timed alone the same way on the
+    same arrays, against the ceiling of their mix."""
     nbytes = 8 * n
     A, B, C = (ts.Array.alloc(tgt, "f64", n) for _ in range(3))
     for k, arr in enumerate((A, B, C)):
@@ -229,6 +231,16 @@ def ceiling_leg(ts, tgt, n, reps=20):
                      "frac_avg": round(moved / avg / 1e6 / PEAK_GBPS, 4), "shape": shape,
                      "runner_up_avg_GBps": [round(moved / r[0] / 1e6, 1) for r in ranked[1:4]],
                      "shapes_tried": len(ranked)}
+    # The library's tuned maps timed the same way on the same arrays (each map
+    # alone, back to back), against the ceiling of their mix of traffic.
+    maps = {}
+    for op, x, y, d, ceil in (("copy", A, None, C, "copy_1r1w"), ("scale", A, None, C, "copy_1r1w"),
+                              ("add", A, B, C, "triad_2r1w"), ("triad", A, B, C, "triad_2r1w")):
+        ms = timed_launches(ts, tgt, lambda: ts.run_op(tgt, op, x, y, d, 3.0), reps)
+        moved = ts.stream_bytes(op, n)
+        gbps = moved / (sum(ms) / len(ms)) / 1e6
+        maps[op] = {"avg_GBps": round(gbps, 1), "vs_ceiling": round(gbps / out[ceil]["avg_GBps"], 4)}
+    out["maps_alone"] = maps
     for arr in (A, B, C):
         arr.free()
     return out
@@ -912,6 +924,8 @@ def summary(result: dict) -> dict:
         s["ceiling_avg_GBps"] = {name: ceil[name]["avg_GBps"] for name, _, _ in PROBE_KINDS if name in ceil}
         s["triad_avg_vs_2r1w_ceiling"] = round(k["triad"]["avg_GBps"] / ceil["triad_2r1w"]["avg_GBps"], 4)
         s["copy_avg_vs_1r1w_ceiling"] = round(k["copy"]["avg_GBps"] / ceil["copy_1r1w"]["avg_GBps"], 4)
+        if "maps_alone" in ceil:
+            s["maps_alone_vs_ceiling"] = {op: v["vs_ceiling"] for op, v in ceil["maps_alone"].items()}
     b = result.get("batched", {})
     if "triad_best_GBps" in b:
         s["batched"] = {"triad_best_GBps": b["triad_best_GBps"], "triad_avg_GBps": b["triad_avg_GBps"],
@@ -946,6 +960,9 @@ def summary_text(s: dict) -> str:
     if "ceiling_avg_GBps" in s:
         lines.append("ceilings (avg GB/s): " + ", ".join(f"{k} {v:.0f}" for k, v in s["ceiling_avg_GBps"].items())
                      + f"; triad/2r1w {s['triad_avg_vs_2r1w_ceiling']:.3f}, copy/1r1w {s['copy_avg_vs_1r1w_ceiling']:.3f}")
+        if "maps_alone_vs_ceiling" in s:
+            lines.append("maps alone back to back vs ceiling: " + ", ".join(
+                f"{op} {r:.3f}" for op, r in s["maps_alone_vs_ceiling"].items()))
     if "batched" in s:
         b = s["batched"]
         lines.append(f"batched triad {b['triad_best_GBps']:.0f}/{b['triad_avg_GBps']:.0f} GB/s "
