@@ -174,6 +174,23 @@ int main(int argc, char **argv)
         expect(total == 0, msg);
     }
 
+    /* The allocation-free checksum: the same reductions as ts_checksum, the
+     * result written in stream order to device memory the caller owns. */
+    {
+        ts_array out_arr;
+        void *out_ptr = NULL;
+        ts_checksum_out ref, got;
+        CHECK(ts_array_alloc(tgt, TS_F64, 4, 0, &out_arr)); /* 32 bytes: one ts_checksum_out */
+        CHECK(ts_array_info(out_arr, &out_ptr, NULL, NULL));
+        CHECK(ts_checksum(tgt, arr[1], 1.0, &ref));
+        CHECK(ts_checksum_noalloc(tgt, arr[1], 1.0, (ts_checksum_out *)out_ptr));
+        CHECK(ts_copy_to_host(&got, out_arr, 4));
+        CHECK(ts_target_synchronize(tgt));
+        expect(memcmp(&ref, &got, sizeof ref) == 0 && got.mismatches == n,
+               "allocation-free checksum equals ts_checksum bit for bit");
+        CHECK(ts_array_free(out_arr));
+    }
+
     /* Errors come back as status codes with a message, never as crashes. */
     ts_array short_arr;
     CHECK(ts_array_alloc(tgt, TS_F64, n - 1, 0, &short_arr));

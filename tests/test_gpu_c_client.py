@@ -22,7 +22,7 @@ def test_c_client(n):
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "all checks passed" in r.stdout
-    assert r.stdout.count("ok  ") == 8
+    assert r.stdout.count("ok  ") == 9
 
 
 def test_ts_log_reports_launch_choices():
