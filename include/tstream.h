@@ -317,7 +317,10 @@ typedef struct {
     int32_t tiles_per_wg; /* batched: consecutive tiles per workgroup, 1, 2,
                             4 or 8 (0 = 1); more than 1 needs unroll <= 2.
                             Plain kernels: 0 or 1                          */
-    int32_t reserved;    /* 0                                               */
+    int32_t record_ahead; /* batched, one workgroup per tile (grid_per_cu 0,
+                            tiles_per_wg 1): 1 = each workgroup also reads
+                            the tile record 2048 workgroups ahead into its
+                            XCD's L2; 0 = off.  Plain kernels: 0          */
 } ts_kernel_cfg;
 
 /* Operand alignment classes (keys of the tuning table). */

@@ -24,11 +24,11 @@ class KernelCfg(ctypes.Structure):
         ("grid_per_cu", ctypes.c_int32),
         ("tile_elems", ctypes.c_int64),
         ("tiles_per_wg", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("record_ahead", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
-        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
     @classmethod
     def from_dict(cls, d: dict) -> "KernelCfg":
@@ -41,7 +41,7 @@ class KernelCfg(ctypes.Structure):
         c.grid_per_cu = int(d.get("grid_per_cu", 0))
         c.tile_elems = int(d.get("tile_elems", 0))
         c.tiles_per_wg = int(d.get("tiles_per_wg", 0))
-        c.reserved = int(d.get("reserved", 0))
+        c.record_ahead = int(d.get("record_ahead", 0))
         return c
 
 

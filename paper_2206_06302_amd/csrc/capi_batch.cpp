@@ -144,6 +144,7 @@ int launch_batch(ts_target_s* t, ts_batch_s* b, int op, const ts_kernel_cfg& cfg
   L.ntl = cfg.nt_load;
   L.nts = cfg.nt_store;
   L.tiles_per_wg = static_cast<int>(per_wg);
+  L.record_ahead = cfg.record_ahead && per_wg == 1 && grid >= L.ntiles ? 1 : 0;
   L.stream = t->stream;
   const hipError_t e = batch_launch(b->dtype, L);
   if (e != hipSuccess) return hip_fail(e, "batched STREAM kernel launch");

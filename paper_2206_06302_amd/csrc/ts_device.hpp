@@ -292,8 +292,9 @@ constexpr uint64_t kRecordAhead = 2048;
 //
 // K = 1: workgroup w takes tiles w, w + G, w + 2G, ... (G = grid size).
 // With one workgroup per tile (G = number of tiles) each workgroup takes one
-// tile; with a smaller grid the workgroups persist and stride, fetching the
-// next tile record while the current tile streams.
+// tile, and with AHEAD it also reads a record further on (below); with a
+// smaller grid the workgroups persist and stride, fetching the next tile
+// record while the current tile streams.
 //
 // K > 1: workgroup w takes the K consecutive tiles Kw .. Kw + K - 1 (then
 // Kw + KG, ... on a persistent grid).  It reads the K records together and
@@ -305,7 +306,7 @@ constexpr uint64_t kRecordAhead = 2048;
 //
 // Inside a tile the lanes stream 16-byte vectors like the plain kernel, and
 // element ownership is disjoint, so results do not depend on K, U or G.
-template <int DT, int OP, int U, int K, bool NTL, bool NTS>
+template <int DT, int OP, int U, int K, bool NTL, bool NTS, bool AHEAD>
 __global__ __launch_bounds__(1024) void batch_kernel(const BatchTile* __restrict__ tiles,
                                                      uint64_t ntiles) {
   using T = typename Fmt<DT>::T;
@@ -322,17 +323,15 @@ __global__ __launch_bounds__(1024) void batch_kernel(const BatchTile* __restrict
       BatchTile nxt = cur;
       if (t + gridDim.x < ntiles) nxt = tiles[t + gridDim.x];
       const TileSpan<DT> s = tile_span<DT, OP>(cur);
-      // One workgroup per tile, maps of one input (copy, scale): read the
-      // record of the tile that a workgroup kRecordAhead later takes.
-      // Workgroups are handed to the XCDs in turn and kRecordAhead is a
-      // multiple of their count, so the record lands in the L2 of the XCD
-      // that will run that workgroup, which then finds it there instead of
-      // waiting on memory before its first data load.  The read depends on
-      // this tile's record (a tile is never empty), so it is issued after
-      // that record has arrived, and is waited for only at the end: it costs
-      // this workgroup no latency.  Maps of two inputs stream longer per
-      // tile, and measured no faster with it.
-      if constexpr (!uses_y<OP>()) {
+      // AHEAD (one workgroup per tile): read the record of the tile that a
+      // workgroup kRecordAhead later takes.  Workgroups are handed to the
+      // XCDs in turn and kRecordAhead is a multiple of their count, so the
+      // record lands in the L2 of the XCD that will run that workgroup,
+      // which then finds it there instead of waiting on memory before its
+      // first data load.  The read depends on this tile's record (a tile is
+      // never empty), so it is issued after that record has arrived, and is
+      // waited for only at the end: it costs this workgroup no latency.
+      if constexpr (AHEAD) {
         if (gridDim.x >= ntiles && s.end > s.start && t + kRecordAhead < ntiles) ahead = tiles[t + kRecordAhead].count;
       }
       const uint64_t nvec = (s.ve - s.vs) / V;
@@ -449,7 +448,14 @@ hipError_t plain_dispatch(const PlainLaunch& L) {
 
 template <int DT, int OP, int U, int K, bool NTL, bool NTS>
 hipError_t launch_batch_inst(const BatchLaunch& L) {
-  hipLaunchKernelGGL((batch_kernel<DT, OP, U, K, NTL, NTS>), dim3(L.grid), dim3(L.block), 0, L.stream,
+  if constexpr (K == 1) {
+    if (L.record_ahead) {
+      hipLaunchKernelGGL((batch_kernel<DT, OP, U, K, NTL, NTS, true>), dim3(L.grid), dim3(L.block), 0, L.stream,
+                         L.tiles, L.ntiles);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((batch_kernel<DT, OP, U, K, NTL, NTS, false>), dim3(L.grid), dim3(L.block), 0, L.stream,
                      L.tiles, L.ntiles);
   return hipGetLastError();
 }

@@ -30,6 +30,7 @@ struct BatchLaunch {
   uint32_t grid, block;
   int op, unroll, ntl, nts;
   int tiles_per_wg;  // consecutive tiles per workgroup: 1, 2, 4 or 8
+  int record_ahead;  // one workgroup per tile: read the record kRecordAhead ahead
   hipStream_t stream;
 };
 

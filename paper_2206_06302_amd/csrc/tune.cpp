@@ -68,13 +68,16 @@ std::string cfg_problem(const ts_kernel_cfg& c, int batched) {
         c.tiles_per_wg != 8)
       return "tiles_per_wg must be 1, 2, 4 or 8 (0 = 1)";
     if (c.tiles_per_wg > 1 && c.unroll > 2) return "several tiles per workgroup take unroll 1 or 2";
+    if (c.record_ahead != 0 && c.record_ahead != 1) return "record_ahead must be 0 or 1";
+    if (c.record_ahead && (c.grid_per_cu != 0 || c.tiles_per_wg > 1))
+      return "record_ahead needs one workgroup per tile (grid_per_cu 0, tiles_per_wg 1)";
   } else {
     if (c.vec_bytes != 16 && c.vec_bytes != 8 && c.vec_bytes != 4 && c.vec_bytes != 2)
       return "vec_bytes must be 16, 8, 4 or 2";
     if (c.grid_per_cu < 0 || c.grid_per_cu > 64) return "grid_per_cu must be 0..64";
     if (c.tiles_per_wg != 0 && c.tiles_per_wg != 1) return "plain kernels take tiles_per_wg 0 or 1";
+    if (c.record_ahead != 0) return "plain kernels take record_ahead 0";
   }
-  if (c.reserved != 0) return "reserved must be 0";
   if ((c.nt_load != 0 && c.nt_load != 1) || (c.nt_store != 0 && c.nt_store != 1))
     return "nt flags must be 0 or 1";
   return "";
@@ -98,7 +101,8 @@ std::vector<ts_kernel_cfg> candidates(int batched) {
       for (int u : {1, 2})
         for (int ntl : {0, 1})
           for (int64_t tile : {512, 1024, 2048, 4096, 8192})
-            out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, 0, tile, 1, 0});
+            for (int ahead : {0, 1})
+              out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, 0, tile, 1, ahead});
     // ... several consecutive small tiles per workgroup, all their first
     // loads in flight together ...
     for (int block : {256, 512})
@@ -173,10 +177,10 @@ std::string TuneTable::to_json() const {
                   "%s\n    {\"op\": \"%s\", \"dtype\": \"%s\", \"bucket\": %d, \"align\": %d, "
                   "\"batched\": %d, \"block\": %d, \"unroll\": %d, \"vec_bytes\": %d, "
                   "\"nt_load\": %d, \"nt_store\": %d, \"grid_per_cu\": %d, \"tile_elems\": %lld, "
-                  "\"tiles_per_wg\": %d, \"bytes_per_s\": %.6e}",
+                  "\"tiles_per_wg\": %d, \"record_ahead\": %d, \"bytes_per_s\": %.6e}",
                   first ? "" : ",", kOpNames[k.op], kTypeNames[k.dtype], k.bucket, k.align,
                   k.batched, c.block, c.unroll, c.vec_bytes, c.nt_load, c.nt_store, c.grid_per_cu,
-                  static_cast<long long>(c.tile_elems), c.tiles_per_wg,
+                  static_cast<long long>(c.tile_elems), c.tiles_per_wg, c.record_ahead,
                   kv.second.bytes_per_s);
     os << buf;
     first = false;
@@ -287,7 +291,7 @@ bool parse_entry(Reader& r, TuneKey& k, TuneEntry& e) {
   e.cfg.tile_elems = static_cast<int64_t>(nums["tile_elems"]);
   // Tables written before the field existed hold one tile per workgroup.
   e.cfg.tiles_per_wg = nums.count("tiles_per_wg") ? static_cast<int32_t>(nums["tiles_per_wg"]) : 1;
-  e.cfg.reserved = 0;
+  e.cfg.record_ahead = nums.count("record_ahead") ? static_cast<int32_t>(nums["record_ahead"]) : 0;
   e.bytes_per_s = nums.count("bytes_per_s") ? nums["bytes_per_s"] : 0.0;
   const std::string why = cfg_problem(e.cfg, k.batched);
   if (!why.empty()) return r.fail("invalid configuration: " + why);

@@ -130,6 +130,7 @@ def test_tune_table_roundtrip(ts, tmp_path):
     saved = json.loads(q.read_text())
     assert saved["format"] == "tstream-tune" and len(saved["entries"]) == 4
     assert {e["op"]: e["tiles_per_wg"] for e in saved["entries"] if e["batched"]} == {"triad": 1, "copy": 4}
+    assert all(e["record_ahead"] == 0 for e in saved["entries"])
     ts.tune_cache_clear()
     ts.tune_cache_load(str(q))
     assert ts.get_kernel_cfg("triad", "f64", 1 << 27)["block"] == 512
@@ -189,7 +190,8 @@ def test_forced_configuration(ts):
             ts.set_kernel_cfg("copy", "f64", cfg, batched=True)
     # several tiles per workgroup: 1, 2, 4 or 8, with unroll 1 or 2; plain kernels take 0 or 1
     for bad in ({"tiles_per_wg": 3}, {"tiles_per_wg": 16}, {"tiles_per_wg": -1},
-                {"tiles_per_wg": 2, "unroll": 4}, {"reserved": 1}):
+                {"tiles_per_wg": 2, "unroll": 4}, {"record_ahead": 2}, {"record_ahead": 1, "tiles_per_wg": 2},
+                {"record_ahead": 1, "grid_per_cu": 4}):
         cfg = {"block": 256, "unroll": 1, "vec_bytes": 16, "nt_load": 1, "nt_store": 1, "grid_per_cu": 0,
                "tile_elems": 512}
         cfg.update(bad)
@@ -197,6 +199,12 @@ def test_forced_configuration(ts):
             ts.set_kernel_cfg("copy", "f64", cfg, batched=True)
     with pytest.raises(ts.TSError):
         ts.set_kernel_cfg("copy", "f64", {"block": 256, "unroll": 1, "vec_bytes": 16, "tiles_per_wg": 2})
+    with pytest.raises(ts.TSError):
+        ts.set_kernel_cfg("copy", "f64", {"block": 256, "unroll": 1, "vec_bytes": 16, "record_ahead": 1})
+    ts.set_kernel_cfg("scale", "f64", {"block": 256, "unroll": 1, "vec_bytes": 16, "nt_load": 1, "nt_store": 1,
+                                       "grid_per_cu": 0, "tile_elems": 512, "record_ahead": 1}, batched=True)
+    assert ts.get_kernel_cfg("scale", "f64", 1 << 30, batched=True)["record_ahead"] == 1
+    ts.set_kernel_cfg("scale", "f64", None, batched=True)
     ts.set_kernel_cfg("add", "f64", {"block": 256, "unroll": 2, "vec_bytes": 16, "nt_load": 1, "nt_store": 1,
                                      "grid_per_cu": 0, "tile_elems": 1024, "tiles_per_wg": 8}, batched=True)
     assert ts.get_kernel_cfg("add", "f64", 1 << 30, batched=True)["tiles_per_wg"] == 8
@@ -221,6 +229,8 @@ def test_candidate_sets_are_valid(ts):
         assert c["tile_elems"] % 8 == 0
     assert {c["tiles_per_wg"] for c in batched} == {1, 2, 4, 8}
     assert all(c["unroll"] <= 2 for c in batched if c["tiles_per_wg"] > 1)
+    assert {c["record_ahead"] for c in batched} == {0, 1} and {c["record_ahead"] for c in plain} == {0}
+    assert all(c["grid_per_cu"] == 0 and c["tiles_per_wg"] == 1 for c in batched if c["record_ahead"])
     ts.set_kernel_cfg("copy", "f64", None)
     ts.set_kernel_cfg("copy", "f64", None, batched=True)
 

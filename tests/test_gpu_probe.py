@@ -43,6 +43,7 @@ def test_probe_results_every_shape(env, reads, writes):
     for shape in bench.probe_shapes():
         cfg = dict(shape, reads=reads, writes=writes)
         dev[2].copy_(host[2].cuda())
+        torch.cuda.synchronize()  # torch's stream is not ordered with the target's
         say(f"[probe {reads}r{writes}w {shape}]")
         ts.probe_bandwidth(tgt, cfg, X, Y, D, nbytes, MARK)
         tgt.synchronize()
