@@ -382,21 +382,21 @@ def summarize(raw: str, out: str = PROFILES) -> None:
          f"per group of K consecutive tiles when grid/CU is 0 (the triad's plan: {tiles} tiles of {tile}",
          f"elements, 64-byte tile records).  Triad configuration: block {cfg['block']}, U{cfg['unroll']}, K "
          f"{cfg.get('tiles_per_wg', 1)}, grid/CU {cfg['grid_per_cu']}, nontemporal loads {cfg['nt_load']} and "
-         f"stores {cfg['nt_store']}.",
+         f"stores {cfg['nt_store']}, record read-ahead {cfg.get('record_ahead', 0)}.",
          "The four-map iteration runs 50 times from a captured graph plus 1 warm-up; then each map runs",
          "alone (1 + 10 launches; the triad 1 + 20).  GB/s = STREAM bytes of one launch / its average duration.", "",
          "| kernel | map | calls | avg ms | min ms | max ms | GB/s (avg) | GB/s (min time) |",
          "|---|---|---|---|---|---|---|---|"]
     for r in _stats(os.path.join(raw, "trace_batched", "run_kernel_stats.csv")):
-        m = re.search(r"batch_kernel<(\d+), (\d+), (\d+), (\d+), (\w+), (\w+)>", r["Name"])
+        m = re.search(r"batch_kernel<(\d+), (\d+), (\d+), (\d+), (\w+), (\w+), (\w+)>", r["Name"])
         if not m or m.group(1) != "0":
             continue
         op = int(m.group(2))
         b = ARRAYS[op] * total * 8
         avg, mn, mx = float(r["AverageNs"]), float(r["MinNs"]), float(r["MaxNs"])
         L.append(f"| `batch_kernel<f64,{OPS[op]},U{m.group(3)},K{m.group(4)},nt_load={int(m.group(5) == 'true')},"
-                 f"nt_store={int(m.group(6) == 'true')}>` | {OPS[op]} | {r['Calls']} | {avg/1e6:.3f} | "
-                 f"{mn/1e6:.3f} | {mx/1e6:.3f} | {b/avg:.1f} | {b/mn:.1f} |")
+                 f"nt_store={int(m.group(6) == 'true')},record_ahead={int(m.group(7) == 'true')}>` | {OPS[op]} | "
+                 f"{r['Calls']} | {avg/1e6:.3f} | {mn/1e6:.3f} | {mx/1e6:.3f} | {b/avg:.1f} | {b/mn:.1f} |")
     L += ["", "From the same run (events on the target's stream, profiler attached):", "",
           f"* graph-replayed four-map iteration: {bb['graph_iteration_ms']} ms ({bb['graph_iteration_GBps']} GB/s)",
           f"* batched triad best {bb['triad_best_GBps']} GB/s, average {bb['triad_avg_GBps']} GB/s; one plain "
