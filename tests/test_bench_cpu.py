@@ -131,3 +131,148 @@ def test_profiler_runs_follow_the_rules():
             assert not {"--kernel-trace", "--sys-trace", "--runtime-trace", "-s", "-r"} & set(cmd[:cmd.index("--")])
     assert names == ["headline trace", "batched trace", "reduced trace", "fetch counters", "write counters",
                      "read requests", "write requests"]
+
+
+def _load_profiling():
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location("_prof", os.path.join(ROOT, "paper_2206_06302_amd", "profiling.py"))
+    prof = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(prof)
+    return prof
+
+
+def _write_csv(path, header, rows):
+    import csv
+
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f, quoting=csv.QUOTE_NONNUMERIC)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def _synthetic_raw(raw):
+    """A raw profiler directory whose figures have answers known by
+    construction: 2^30-byte arrays, read requests of 128 bytes (plus, for
+    copy, four of 32 bytes standing in for one 128-byte one), write requests
+    of 64 bytes, and a small-grid launch of every map that the summaries must
+    leave out."""
+    import json
+
+    gib = 1 << 30
+    plain = "void ts::stream_kernel<0, {op}, 16, 1, true, true>(void const*, void const*, void*, double, float)"
+    batch = "void ts::batch_kernel<0, {op}, 1, 1, true, true, true>(ts::BatchTile const*, unsigned long)"
+    probe = {"read_1r": "void ts::probe_kernel<1, 0, 1, true, true, false>(void const*)",
+             "write_1w": "void ts::probe_kernel<0, 1, 1, true, true, false>(void const*)",
+             "copy_1r1w": "void ts::probe_kernel<1, 1, 1, true, true, false>(void const*)"}
+    big, small = 1 << 24, 1 << 10
+
+    def req(reads, writes, copy=False):
+        rd32 = 4 if copy else 0
+        rd = reads // 128 - (1 if copy else 0) + rd32
+        wr = writes // 64
+        return {"FETCH_SIZE": rd * 64 / 1024, "WRITE_SIZE": wr * 64 / 1024, "TCC_EA0_RDREQ_sum": rd,
+                "TCC_EA0_RDREQ_32B_sum": rd32, "TCC_BUBBLE_sum": 0, "TCC_EA0_RDREQ_DRAM_sum": rd,
+                "TCC_EA0_WRREQ_sum": wr, "TCC_EA0_WRREQ_64B_sum": wr, "TCC_EA0_WRREQ_DRAM_sum": wr}
+
+    launches = []  # (kernel name, grid, counters) per dispatch
+    for op, arrays in ((0, 2), (1, 2), (2, 3), (3, 3)):
+        launches += [(plain.format(op=op), big, req((arrays - 1) * gib, gib, copy=op == 0))] * 2
+        launches.append((plain.format(op=op), small, req(4096, 4096)))
+        launches.append((batch.format(op=op), big, req((arrays - 1) * 3 * gib, 3 * gib)))
+    launches += [(probe["read_1r"], big, req(gib, 0)), (probe["write_1w"], big, req(0, gib)),
+                 (probe["copy_1r1w"], big, req(gib, gib))]
+    prof = _load_profiling()
+    header = ["Dispatch_Id", "Grid_Size", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    for _, sub, counters in prof.PMC_RUNS:
+        rows = [[i, g, name, c, vals[c]] for i, (name, g, vals) in enumerate(launches) for c in counters]
+        _write_csv(os.path.join(raw, sub, "run_counter_collection.csv"), header, rows)
+        with open(os.path.join(raw, sub + ".json"), "w") as f:
+            f.write(json.dumps({"batched": {"total_elems": 3 * (1 << 27), "tiles": 12345}}) + "\n")
+
+    stats = ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs", "StdDev"]
+    # 2 or 3 GiB of STREAM bytes in 400 or 600 µs: 5368.7 GB/s avg; minimum 1.25x faster
+    rows = [[plain.format(op=op), 71, 0, 200e3 * a, 0, 160e3 * a, 250e3 * a, 0]
+            for op, a in ((0, 2), (1, 2), (2, 3), (3, 3))]
+    rows.append(["void ts::(anonymous namespace)::fill_const_kernel<0>(void*, unsigned long)", 3, 0, 1e5, 0, 1e5,
+                 1e5, 0])
+    _write_csv(os.path.join(raw, "trace_headline", "run_kernel_stats.csv"), stats, rows)
+    per = {op: {"avg_ms": 0.5, "avg_GBps": 1.0, "best_ms": 0.4} for op in ("copy", "scale", "add", "triad")}
+    with open(os.path.join(raw, "trace_headline.json"), "w") as f:
+        f.write("log line\n" + json.dumps({"per_kernel": per}) + "\n")
+
+    rows = [[batch.format(op=op), 11, 0, 3 * 200e3 * a, 0, 3 * 160e3 * a, 3 * 250e3 * a, 0]
+            for op, a in ((0, 2), (1, 2), (2, 3), (3, 3))]
+    _write_csv(os.path.join(raw, "trace_batched", "run_kernel_stats.csv"), stats, rows)
+    bb = {"total_elems": 3 * (1 << 27), "tiles": 12345, "tile_elems": 1024,
+          "cfg": {"block": 1024, "unroll": 1, "tiles_per_wg": 1, "grid_per_cu": 0, "nt_load": 1, "nt_store": 1,
+                  "record_ahead": 1},
+          "graph_iteration_ms": 5.0, "graph_iteration_GBps": 5000.0, "triad_best_GBps": 6000.0,
+          "triad_avg_GBps": 5900.0, "plain_per_instance_triad_best_GBps": 4000.0,
+          "maps": {op: {"avg_GBps": 5800.0} for op in ("copy", "scale", "add", "triad")},
+          "valid_after_graph_replays": True}
+    with open(os.path.join(raw, "trace_batched.json"), "w") as f:
+        f.write(json.dumps({"batched": bb}) + "\n")
+
+    trace = ["Kernel_Name", "Grid_Size_X", "Start_Timestamp", "End_Timestamp"]
+    rows = []
+    for dt, nbytes in ((0, 8), (1, 4), (2, 2)):
+        name = f"void ts::stream_kernel<{dt}, 3, 16, 1, true, true>(void const*, void const*, void*)"
+        # 2^28 elements: 3 * 2^28 * nbytes bytes in (nbytes / 8) ms; a small launch that must be left out
+        rows += [[name, 1 << 22, 0, int(nbytes / 8 * 1e6)]] * 2 + [[name, 1 << 10, 0, 1]]
+    _write_csv(os.path.join(raw, "trace_reduced", "run_kernel_trace.csv"), trace, rows)
+    with open(os.path.join(raw, "trace_reduced.json"), "w") as f:
+        f.write(json.dumps({"reduced_precision": {"f32": {"triad": {"GBps": 1.5}}}}) + "\n")
+    return prof
+
+
+def test_profile_summaries_from_known_counts(tmp_path, monkeypatch):
+    """The summaries turn request counts into bytes, keep the 2^27 launches
+    apart from smaller ones of the same kernel, and leave the triad's bytes
+    and the kernel digest where bench.py reads them."""
+    raw, out = str(tmp_path / "raw"), str(tmp_path / "profiles")
+    prof = _synthetic_raw(raw)
+    prof.summarize(raw, out)
+    assert sorted(os.listdir(out)) == ["batched_f64_4096_kernel_trace.md", "batched_f64_4096_pmc.md",
+                                       "stream_f64_n2p27_kernel_trace.md", "stream_f64_n2p27_pmc.md",
+                                       "stream_reduced_n2p28_kernel_trace.md"]
+    read = lambda f: open(os.path.join(out, f)).read()  # noqa: E731
+
+    pmc = read("stream_f64_n2p27_pmc.md")
+    rows = {ln.split("|")[1].strip(): ln for ln in pmc.splitlines() if ln.startswith("| ")}
+    for op in ("copy", "scale", "add", "triad"):
+        assert rows[op].rstrip().endswith("| 1.0000 |"), rows[op]
+        assert rows[op].split("|")[2].strip() == "2/2/2/2"  # the small-grid launch is left out
+    # the probe's read requests carry 128 bytes each, its write requests 64
+    assert "| 128.00 | – |" in rows["read_1r"] and "| – | 64.00 |" in rows["write_1w"]
+    assert "traffic_bytes_per_launch: 3.221225e+09" in pmc
+    assert f"kernel_source_digest: {prof.source_digest()}" in pmc
+    assert "$RAW/pmc_fetch" in pmc and raw not in pmc
+
+    bpmc = read("batched_f64_4096_pmc.md")
+    assert "traffic_bytes_per_launch (triad): 9.663676e+09" in bpmc
+    assert all(r.rstrip().endswith("| 1.0000 |") for r in bpmc.splitlines() if r.startswith("| triad |"))
+
+    trace = read("stream_f64_n2p27_kernel_trace.md")
+    lines = [ln for ln in trace.splitlines() if ln.startswith("| `stream_kernel<f64,")]
+    assert len(lines) == 4 and all("| 5368.7 | 6710.9 |" in ln for ln in lines), lines
+    assert "| `fill_const_kernel<0>` | – | 3 |" in trace
+
+    btrace = read("batched_f64_4096_kernel_trace.md")
+    lines = [ln for ln in btrace.splitlines() if ln.startswith("| `batch_kernel<f64,")]
+    assert len(lines) == 4 and all("record_ahead=1>`" in ln and "| 5368.7 | 6710.9 |" in ln for ln in lines)
+
+    red = read("stream_reduced_n2p28_kernel_trace.md")
+    rows = {ln.split("|")[1].strip(): ln.split("|") for ln in red.splitlines()
+            if ln.split("|")[1:2] and ln.split("|")[1].strip() in ("f64", "f32", "bf16", "f16")}
+    assert rows["f64"][4].strip() == "2" and rows["f64"][6].strip() == "6442.5"
+    # elements per second against binary64: 2x for 4-byte storage, 4x for 2-byte storage
+    assert rows["f32"][8].strip() == "2.00" and rows["bf16"][8].strip() == "4.00"
+    assert rows["f32"][9].strip() == "1.5"
+
+    monkeypatch.setattr(bench, "PROFILE_PMC", os.path.join(out, "stream_f64_n2p27_pmc.md"))
+    assert bench.committed_traffic() == 3.221225e9
+    with open(bench.PROFILE_PMC, "w") as f:
+        f.write(pmc.replace(prof.source_digest(), "0" * 16))
+    assert bench.committed_traffic() is None
