@@ -182,20 +182,21 @@ LDS_PER_CU = 160 * 1024  # gfx950
 
 def probe_shapes():
     """Launch shapes the ceiling leg searches for every mix of traffic:
-    lanes per workgroup, 16-byte vectors per lane and their layout,
-    nontemporal loads, and a cap on the workgroups resident per CU (through
-    dynamic LDS)."""
+    lanes per workgroup, vectors per lane, their width (16 or 8 bytes, the
+    widths the maps use) and layout, nontemporal loads, and a cap on the
+    workgroups resident per CU (through dynamic LDS)."""
     shapes = []
-    for block in (256, 512, 1024):
-        for unroll in (1, 2, 4):
-            for wave in ((0,) if unroll == 1 else (0, 1)):
-                for ntl in (0, 1):
-                    for cap in (0, 2, 4):
-                        lds = 0 if cap == 0 else LDS_PER_CU // cap
-                        if cap and 1024 // block * 2 <= cap:
-                            continue  # the cap would not bind at this block size
-                        shapes.append({"block": block, "unroll": unroll, "wave_contiguous": wave, "nt_load": ntl,
-                                       "nt_store": 1, "lds_bytes": lds})
+    for vb in (16, 8):
+        for block in (256, 512, 1024):
+            for unroll in (1, 2, 4):
+                for wave in ((0,) if unroll == 1 else (0, 1)):
+                    for ntl in (0, 1):
+                        for cap in (0, 2, 4):
+                            lds = 0 if cap == 0 else LDS_PER_CU // cap
+                            if cap and 1024 // block * 2 <= cap:
+                                continue  # the cap would not bind at this block size
+                            shapes.append({"block": block, "unroll": unroll, "vec_bytes": vb, "wave_contiguous": wave,
+                                           "nt_load": ntl, "nt_store": 1, "lds_bytes": lds})
     return shapes
 
 
@@ -246,7 +247,8 @@ def ceiling_leg(ts, tgt, n, reps=20):
     return out
 
 
-CALIBRATION_SHAPE = {"block": 512, "unroll": 1, "wave_contiguous": 0, "nt_load": 1, "nt_store": 1, "lds_bytes": 0}
+CALIBRATION_SHAPE = {"block": 512, "unroll": 1, "vec_bytes": 16, "wave_contiguous": 0, "nt_load": 1, "nt_store": 1,
+                     "lds_bytes": 0}
 
 
 def calibration_leg(ts, tgt, n, reps=3):

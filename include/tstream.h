@@ -384,26 +384,28 @@ TS_API int ts_time_op(ts_target exec, ts_op op, ts_array x, ts_array y,
  *   dst only when its first word equals `mark`, so the first bytes/unroll
  *   bytes of dst are unspecified afterwards.
  * The first `bytes` bytes of each operand take part: `bytes` must be a
- * positive multiple of 16 * cfg->block * cfg->unroll (TS_E_SHAPE), every
+ * positive multiple of vec_bytes * cfg->block * cfg->unroll (TS_E_SHAPE), every
  * operand must start on a 16-byte boundary (TS_E_SHAPE), hold at least
  * `bytes` bytes (TS_E_SHAPE) and lie on the executor's device
  * (TS_E_PLACEMENT); operands of any storage type; dst must not overlap an
  * input (TS_E_ALIAS); y is ignored unless reads == 2, x unless reads >= 1.
- * One launch of bytes / (16 * block * unroll) workgroups, asynchronous on
+ * One launch of bytes / (vec_bytes * block * unroll) workgroups, asynchronous on
  * the executor's stream; GPU targets only (TS_E_UNSUPPORTED on a host
  * target). */
 typedef struct {
     int32_t reads;           /* 0, 1 or 2 (writes + reads >= 1)               */
     int32_t writes;          /* 0 or 1 (reads 0 needs writes 1)               */
     int32_t block;           /* lanes per workgroup: 64..1024, multiple of 64 */
-    int32_t unroll;          /* 16-byte vectors per lane: 1, 2 or 4           */
+    int32_t unroll;          /* vectors per lane: 1, 2 or 4                   */
     int32_t nt_load;         /* 1: nontemporal loads                          */
     int32_t nt_store;        /* 1: nontemporal stores                         */
-    int32_t wave_contiguous; /* 1: each wave covers unroll*1 KiB in a row;
-                                0: a lane's vectors lie a workgroup apart    */
+    int32_t wave_contiguous; /* 1: each wave covers unroll*64 vectors in a
+                                row; 0: a lane's vectors lie a workgroup
+                                apart                                        */
     int32_t lds_bytes;       /* dynamic LDS per workgroup, 0..the device's
                                 LDS per CU: caps the workgroups resident on
                                 a CU (0: no cap)                             */
+    int32_t vec_bytes;       /* bytes per lane access: 16 or 8 (0 means 16) */
 } ts_probe_cfg;
 TS_API int ts_probe_bandwidth(ts_target exec, const ts_probe_cfg *cfg,
                               ts_array x, ts_array y, ts_array dst,

@@ -55,6 +55,7 @@ class ProbeCfg(ctypes.Structure):
         ("nt_store", ctypes.c_int32),
         ("wave_contiguous", ctypes.c_int32),
         ("lds_bytes", ctypes.c_int32),
+        ("vec_bytes", ctypes.c_int32),
     ]
 
     @classmethod

@@ -1,5 +1,5 @@
 // capi_probe.cpp -- the memory-system probe of the C ABI: one launch of a
-// straight-line kernel with a chosen mix of 16-byte reads and writes
+// straight-line kernel with a chosen mix of 16- or 8-byte reads and writes
 // (kern_probe.hip), the ceiling the STREAM maps are measured against.
 #include <cstdint>
 
@@ -38,15 +38,18 @@ int ts_probe_bandwidth(ts_target t, const ts_probe_cfg* cfg, ts_array x, ts_arra
   if (c.unroll != 1 && c.unroll != 2 && c.unroll != 4) return fail(TS_E_INVALID, "probe: unroll must be 1, 2 or 4");
   if ((c.nt_load & ~1) || (c.nt_store & ~1) || (c.wave_contiguous & ~1))
     return fail(TS_E_INVALID, "probe: flags must be 0 or 1");
+  if (c.vec_bytes != 0 && c.vec_bytes != 8 && c.vec_bytes != 16)
+    return fail(TS_E_INVALID, "probe: vec_bytes must be 16 or 8 (0 means 16)");
+  const uint64_t vb = c.vec_bytes ? static_cast<uint64_t>(c.vec_bytes) : 16u;
   int st = use_device(t->device);
   if (st != TS_OK) return st;
   int lds_per_cu = 0;
   TS_HIP(hipDeviceGetAttribute(&lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, t->device));
   if (c.lds_bytes < 0 || c.lds_bytes > lds_per_cu)
     return fail(TS_E_INVALID, "probe: lds_bytes must be 0..%d", lds_per_cu);
-  const uint64_t per_wg = 16ull * static_cast<uint64_t>(c.block) * static_cast<uint64_t>(c.unroll);
+  const uint64_t per_wg = vb * static_cast<uint64_t>(c.block) * static_cast<uint64_t>(c.unroll);
   if (bytes == 0 || bytes % per_wg)
-    return fail(TS_E_SHAPE, "probe: bytes must be a positive multiple of 16 * block * unroll = %llu",
+    return fail(TS_E_SHAPE, "probe: bytes must be a positive multiple of vec_bytes * block * unroll = %llu",
                 static_cast<unsigned long long>(per_wg));
   const uint64_t grid = bytes / per_wg;
   if (grid > kMaxGridX) return fail(TS_E_SHAPE, "probe: more than 2^31 - 1 workgroups");
@@ -73,6 +76,7 @@ int ts_probe_bandwidth(ts_target t, const ts_probe_cfg* cfg, ts_array x, ts_arra
   L.reads = c.reads;
   L.writes = c.writes;
   L.unroll = c.unroll;
+  L.vb = static_cast<int>(vb);
   L.ntl = c.nt_load;
   L.nts = c.nt_store;
   L.wave_contiguous = c.wave_contiguous;

@@ -35,13 +35,13 @@ struct BatchLaunch {
 };
 
 // Arguments of one memory-system probe launch (kern_probe.hip): grid * block
-// * unroll 16-byte vectors of each array involved.
+// * unroll vectors of vb (16 or 8) bytes of each array involved.
 struct ProbeLaunch {
   const void* x;
   const void* y;
   void* d;
   uint32_t grid, block, lds_bytes, mark;
-  int reads, writes, unroll, ntl, nts, wave_contiguous;
+  int reads, writes, unroll, vb, ntl, nts, wave_contiguous;
   hipStream_t stream;
 };
 hipError_t launch_probe(const ProbeLaunch& L);

@@ -261,7 +261,9 @@ class Counters:
         return d
 
 
-PROBE = {"read_1r": r"probe_kernel<1, 0,", "write_1w": r"probe_kernel<0, 1,", "copy_1r1w": r"probe_kernel<1, 1,"}
+# probe_kernel<vector bytes, reads, writes, ...>: the calibration leg's 16-byte probes
+PROBE = {"read_1r": r"probe_kernel<16, 1, 0,", "write_1w": r"probe_kernel<16, 0, 1,",
+         "copy_1r1w": r"probe_kernel<16, 1, 1,"}
 PROBE_BYTES = N27 * 8  # the calibration leg's probes move 2^27 binary64 elements per array
 
 

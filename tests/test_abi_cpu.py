@@ -170,18 +170,20 @@ def test_tune_table_rejects_bad_files(ts, tmp_path, text):
 
 
 def test_forced_configuration(ts):
+    before = ts.get_kernel_cfg("scale", "f16", 5)
     ts.set_kernel_cfg("scale", "f16", {"block": 1024, "unroll": 8, "vec_bytes": 8, "nt_load": 1,
                                        "nt_store": 0, "grid_per_cu": 2})
     assert ts.get_kernel_cfg("scale", "f16", 5)["block"] == 1024
     ts.set_kernel_cfg("scale", "f16", None)
-    assert ts.get_kernel_cfg("scale", "f16", 5)["block"] == 256
+    assert ts.get_kernel_cfg("scale", "f16", 5) == before
     for bad in ({"block": 96}, {"unroll": 3}, {"vec_bytes": 32}, {"nt_load": 2}, {"grid_per_cu": -1}):
         cfg = {"block": 256, "unroll": 4, "vec_bytes": 16, "nt_load": 0, "nt_store": 0, "grid_per_cu": 0}
         cfg.update(bad)
         with pytest.raises(ts.TSError):
             ts.set_kernel_cfg("copy", "f64", cfg)
     with pytest.raises(ts.TSError):  # batched kernels require 16-byte vectors
-        ts.set_kernel_cfg("copy", "f64", {"vec_bytes": 8, "grid_per_cu": 4, "tile_elems": 8192}, batched=True)
+        ts.set_kernel_cfg("copy", "f64", {"block": 256, "unroll": 1, "vec_bytes": 8, "grid_per_cu": 4,
+                                          "tile_elems": 8192}, batched=True)
     for bad in ({"grid_per_cu": -1}, {"grid_per_cu": 65}, {"tile_elems": 12}):
         cfg = {"block": 1024, "unroll": 4, "vec_bytes": 16, "nt_load": 1, "nt_store": 1, "grid_per_cu": 0,
                "tile_elems": 4096}
@@ -231,6 +233,7 @@ def test_candidate_sets_are_valid(ts):
     assert all(c["unroll"] <= 2 for c in batched if c["tiles_per_wg"] > 1)
     assert {c["record_ahead"] for c in batched} == {0, 1} and {c["record_ahead"] for c in plain} == {0}
     assert all(c["grid_per_cu"] == 0 and c["tiles_per_wg"] == 1 for c in batched if c["record_ahead"])
+    assert {c["vec_bytes"] for c in batched} == {16}
     ts.set_kernel_cfg("copy", "f64", None)
     ts.set_kernel_cfg("copy", "f64", None, batched=True)
 

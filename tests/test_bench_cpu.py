@@ -163,9 +163,9 @@ def _synthetic_raw(raw):
     gib = 1 << 30
     plain = "void ts::stream_kernel<0, {op}, 16, 1, true, true>(void const*, void const*, void*, double, float)"
     batch = "void ts::batch_kernel<0, {op}, 1, 1, true, true, true>(ts::BatchTile const*, unsigned long)"
-    probe = {"read_1r": "void ts::probe_kernel<1, 0, 1, true, true, false>(void const*)",
-             "write_1w": "void ts::probe_kernel<0, 1, 1, true, true, false>(void const*)",
-             "copy_1r1w": "void ts::probe_kernel<1, 1, 1, true, true, false>(void const*)"}
+    probe = {"read_1r": "void ts::probe_kernel<16, 1, 0, 1, true, true, false>(void const*)",
+             "write_1w": "void ts::probe_kernel<16, 0, 1, 1, true, true, false>(void const*)",
+             "copy_1r1w": "void ts::probe_kernel<16, 1, 1, 1, true, true, false>(void const*)"}
     big, small = 1 << 24, 1 << 10
 
     def req(reads, writes, copy=False):

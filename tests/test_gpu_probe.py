@@ -38,7 +38,7 @@ def test_probe_results_every_shape(env, reads, writes):
     dst keeps its contents (a lane stores only when the first word of its
     fold equals the mark, which these seeded inputs never give)."""
     ts, torch, tgt = env
-    nbytes = 16 * 1024 * 4 * 6  # a multiple of every shape's 16 * block * unroll
+    nbytes = 16 * 1024 * 4 * 6  # a multiple of every shape's vec_bytes * block * unroll
     host, dev, (X, Y, D) = _arrays(ts, torch, tgt, nbytes, reads * 10 + writes)
     for shape in bench.probe_shapes():
         cfg = dict(shape, reads=reads, writes=writes)
@@ -59,13 +59,15 @@ def test_probe_results_every_shape(env, reads, writes):
         assert torch.equal(got, exp), (reads, writes, shape)
 
 
-def test_probe_leaves_bytes_beyond_its_range(env):
+@pytest.mark.parametrize("vb", [16, 8])
+def test_probe_leaves_bytes_beyond_its_range(env, vb):
     """Only the first `bytes` bytes of dst are written."""
     ts, torch, tgt = env
-    nbytes = 16 * 256
-    host, dev, (X, Y, D) = _arrays(ts, torch, tgt, 3 * nbytes, 3)
-    say("[probe range]")
-    ts.probe_bandwidth(tgt, {"reads": 2, "writes": 1, "block": 256, "unroll": 1, "nt_store": 1}, X, Y, D, nbytes)
+    nbytes = vb * 256
+    host, dev, (X, Y, D) = _arrays(ts, torch, tgt, 3 * 16 * 256, 3)
+    say(f"[probe range vb={vb}]")
+    ts.probe_bandwidth(tgt, {"reads": 2, "writes": 1, "block": 256, "unroll": 1, "nt_store": 1, "vec_bytes": vb},
+                       X, Y, D, nbytes)
     tgt.synchronize()
     got = dev[2].cpu()
     k = nbytes // 8
@@ -92,6 +94,8 @@ def test_probe_rules(env):
     assert st(dict(base, reads=3), X, Y, D, 4096) == E_INVALID
     assert st(dict(base, block=96), X, Y, D, 4096 * 6) == E_INVALID
     assert st(dict(base, unroll=8), X, Y, D, 4096) == E_INVALID
+    assert st(dict(base, vec_bytes=4), X, Y, D, 4096) == E_INVALID
+    assert st(dict(base, vec_bytes=8), X, Y, D, 2048 + 8) == E_SHAPE  # not a multiple of 8 * block * unroll
     assert st(dict(base, lds_bytes=1 << 30), X, Y, D, 4096) == E_INVALID
     assert st(base, X, Y, D, 4096 + 16) == E_SHAPE  # not a multiple of 16 * block * unroll
     assert st(base, X, Y, D, 0) == E_SHAPE
