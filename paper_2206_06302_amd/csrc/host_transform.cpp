@@ -25,6 +25,7 @@
 #include <sstream>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "../../include/tstream.h"
 #include "host_transform.hpp"
