@@ -4,9 +4,9 @@
 // The paper's GPU executor runs any device callable (Section 4.2), and its
 // hello-world example transforms a vector of chars with to_upper (Section
 // 3.4, Listing 3).  A C ABI cannot carry a callable, so the callable arrives
-// as the text of a C++ expression in x, y and q; the library wraps it in two
-// kernels (16-byte vectors for operands that share their alignment, and an
-// element-wise fallback), compiles them once per (expression, inputs,
+// as the text of a C++ expression in x, y and q; the library wraps it in
+// kernels (16- and 8-byte vectors for operands that share their alignment,
+// and an element-wise fallback), compiles them once per (expression, inputs,
 // storage type, architecture) and launches one on the executing target's
 // stream.
 // hipRTC is opened lazily (dlopen), so it is needed only when transforms
@@ -102,11 +102,13 @@ TypeText type_text(int dtype) {
   }
 }
 
-// The generated source holds two kernels around the expression:
+// The generated source holds three kernels around the expression:
 //   ts_transform_vec     one pass, 16-byte nontemporal vectors (16 / element
 //                        size elements per lane) plus an element-wise head and
 //                        tail, for operands that share their misalignment
 //                        modulo 16 bytes;
+//   ts_transform_vec8    the same with 8-byte vectors, for operands that share
+//                        their misalignment modulo 8 bytes;
 //   ts_transform_kernel  element-wise with a grid-stride loop, for any operands.
 std::string kernel_source(const std::string& expr, int n_inputs, int dtype) {
   const TypeText t = type_text(dtype);
@@ -115,8 +117,7 @@ std::string kernel_source(const std::string& expr, int n_inputs, int dtype) {
   s += "typedef " + std::string(t.storage) + " ts_store_t;\n";
   s += "typedef " + std::string(t.arith) + " ts_arith_t;\n";
   s += "typedef unsigned int ts_u4 __attribute__((ext_vector_type(4)));\n";
-  s += "#define TS_E (16 / sizeof(ts_store_t))\n";
-  s += "struct ts_vec_t { ts_store_t v[TS_E]; };\n";
+  s += "typedef unsigned int ts_u2 __attribute__((ext_vector_type(2)));\n";
   s += "__device__ inline float ts_keep(float v) { asm(\"\" : \"+v\"(v)); return v; }\n";
   s += "__device__ inline ts_arith_t ts_widen(ts_store_t v) { return " + std::string(t.widen) + "; }\n";
   s += "__device__ inline ts_store_t ts_narrow(ts_arith_t r) { return " + std::string(t.narrow) + "; }\n";
@@ -132,27 +133,36 @@ std::string kernel_source(const std::string& expr, int n_inputs, int dtype) {
        "  for (unsigned long long j = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; j < n;\n"
        "       j += stride)\n";
   s += two ? "    ds[j] = ts_apply(xs[j], ys[j], q);\n}\n" : "    ds[j] = ts_apply(xs[j], xs[j], q);\n}\n";
-  s += "extern \"C\" __global__ void ts_transform_vec(const ts_store_t* __restrict__ xs,\n"
-       "    const ts_store_t* __restrict__ ys, ts_store_t* ds, double qd, unsigned long long head,\n"
-       "    unsigned long long nvec, unsigned long long tail) {\n"
-       "  const ts_arith_t q = (ts_arith_t)qd;\n"
-       "  const unsigned long long g = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;\n"
-       "  const unsigned long long t0 = head + nvec * TS_E;\n";
-  s += two ? "  if (g < head) ds[g] = ts_apply(xs[g], ys[g], q);\n"
-             "  if (g < tail) ds[t0 + g] = ts_apply(xs[t0 + g], ys[t0 + g], q);\n"
-           : "  if (g < head) ds[g] = ts_apply(xs[g], xs[g], q);\n"
-             "  if (g < tail) ds[t0 + g] = ts_apply(xs[t0 + g], xs[t0 + g], q);\n";
-  s += "  if (g < nvec) {\n"
-       "    const ts_vec_t xv = __builtin_bit_cast(ts_vec_t,\n"
-       "        __builtin_nontemporal_load(reinterpret_cast<const ts_u4*>(xs + head) + g));\n";
-  s += two ? "    const ts_vec_t yv = __builtin_bit_cast(ts_vec_t,\n"
-             "        __builtin_nontemporal_load(reinterpret_cast<const ts_u4*>(ys + head) + g));\n"
-           : "    const ts_vec_t yv = xv;\n";
-  s += "    ts_vec_t dv;\n"
-       "#pragma unroll\n"
-       "    for (unsigned e = 0; e < TS_E; ++e) dv.v[e] = ts_apply(xv.v[e], yv.v[e], q);\n"
-       "    __builtin_nontemporal_store(__builtin_bit_cast(ts_u4, dv), reinterpret_cast<ts_u4*>(ds + head) + g);\n"
-       "  }\n}\n";
+  // One vector kernel per width W: name, W-byte raw vector type, elements per vector.
+  const struct { const char* name; const char* raw; const char* elems; } widths[] = {
+      {"ts_transform_vec", "ts_u4", "(16 / sizeof(ts_store_t))"},
+      {"ts_transform_vec8", "ts_u2", "(8 / sizeof(ts_store_t))"}};
+  for (const auto& w : widths) {
+    const std::string vt = std::string(w.name) + "_t";
+    s += "struct " + vt + " { ts_store_t v[" + w.elems + "]; };\n";
+    s += "extern \"C\" __global__ void " + std::string(w.name) + "(const ts_store_t* __restrict__ xs,\n"
+         "    const ts_store_t* __restrict__ ys, ts_store_t* ds, double qd, unsigned long long head,\n"
+         "    unsigned long long nvec, unsigned long long tail) {\n"
+         "  const ts_arith_t q = (ts_arith_t)qd;\n"
+         "  const unsigned long long g = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;\n"
+         "  const unsigned long long t0 = head + nvec * " + w.elems + ";\n";
+    s += two ? "  if (g < head) ds[g] = ts_apply(xs[g], ys[g], q);\n"
+               "  if (g < tail) ds[t0 + g] = ts_apply(xs[t0 + g], ys[t0 + g], q);\n"
+             : "  if (g < head) ds[g] = ts_apply(xs[g], xs[g], q);\n"
+               "  if (g < tail) ds[t0 + g] = ts_apply(xs[t0 + g], xs[t0 + g], q);\n";
+    s += "  if (g < nvec) {\n"
+         "    const " + vt + " xv = __builtin_bit_cast(" + vt + ",\n"
+         "        __builtin_nontemporal_load(reinterpret_cast<const " + w.raw + "*>(xs + head) + g));\n";
+    s += two ? "    const " + vt + " yv = __builtin_bit_cast(" + vt + ",\n"
+               "        __builtin_nontemporal_load(reinterpret_cast<const " + w.raw + "*>(ys + head) + g));\n"
+             : "    const " + vt + " yv = xv;\n";
+    s += "    " + vt + " dv;\n"
+         "#pragma unroll\n"
+         "    for (unsigned e = 0; e < " + w.elems + "; ++e) dv.v[e] = ts_apply(xv.v[e], yv.v[e], q);\n"
+         "    __builtin_nontemporal_store(__builtin_bit_cast(" + w.raw + ", dv), reinterpret_cast<" + w.raw +
+         "*>(ds + head) + g);\n"
+         "  }\n}\n";
+  }
   return s;
 }
 
@@ -169,7 +179,8 @@ struct ts_transform_s {
   int n_inputs;
   hipModule_t module;
   hipFunction_t fn;      // element-wise, grid-stride
-  hipFunction_t fn_vec;  // 16-byte vectors, one pass
+  hipFunction_t fn_vec;   // 16-byte vectors, one pass
+  hipFunction_t fn_vec8;  // 8-byte vectors, one pass
   HostTransformFn host_fn;  // host-CPU targets: the compiled block function
   std::string log;
 };
@@ -245,9 +256,10 @@ int ts_transform_create(ts_target t, const char* expr, int n_inputs, ts_dtype dt
     hipModule_t mod = nullptr;
     he = hipModuleLoadData(&mod, code->data());
     if (he != hipSuccess) return api_hip_fail(he, "hipModuleLoadData");
-    hipFunction_t fn = nullptr, fn_vec = nullptr;
+    hipFunction_t fn = nullptr, fn_vec = nullptr, fn_vec8 = nullptr;
     he = hipModuleGetFunction(&fn, mod, "ts_transform_kernel");
     if (he == hipSuccess) he = hipModuleGetFunction(&fn_vec, mod, "ts_transform_vec");
+    if (he == hipSuccess) he = hipModuleGetFunction(&fn_vec8, mod, "ts_transform_vec8");
     if (he != hipSuccess) {
       (void)hipModuleUnload(mod);
       return api_hip_fail(he, "hipModuleGetFunction");
@@ -259,6 +271,7 @@ int ts_transform_create(ts_target t, const char* expr, int n_inputs, ts_dtype dt
     x->module = mod;
     x->fn = fn;
     x->fn_vec = fn_vec;
+    x->fn_vec8 = fn_vec8;
     x->log = log;
     x->magic = kTransformMagic;
     *out = x;
@@ -305,14 +318,18 @@ int ts_transform_apply(ts_target t, ts_transform x, ts_array a, ts_array b, ts_a
     void* dp = d->ptr;
     const unsigned long long n = c.count;
     const unsigned long long es = dtype_size(a->dtype);
-    const unsigned long long per_vec = 16 / es;
     const uintptr_t xa = reinterpret_cast<uintptr_t>(xp), ya = reinterpret_cast<uintptr_t>(yp),
                     da = reinterpret_cast<uintptr_t>(dp);
-    const unsigned block = 256;
-    if ((xa - da) % 16 == 0 && (ya - da) % 16 == 0) {
-      // Shared misalignment: element-wise head up to the next 16-byte
+    // One wave per workgroup and one vector per lane, 8 bytes when two
+    // arrays are read and 16 when one is: the shapes that stream fastest at
+    // sizes beyond the caches, as for the tuned maps.
+    const unsigned long long vw = two ? 8 : 16;
+    const unsigned long long per_vec = vw / es;
+    if ((xa - da) % vw == 0 && (ya - da) % vw == 0) {
+      const unsigned block = 64;
+      // Shared misalignment: element-wise head up to the next vw-byte
       // boundary of every operand, vectors, element-wise tail.
-      unsigned long long head = ((16 - da % 16) % 16) / es;
+      unsigned long long head = ((vw - da % vw) % vw) / es;
       if (head > n) head = n;
       const unsigned long long nvec = (n - head) / per_vec;
       const unsigned long long tail = n - head - nvec * per_vec;
@@ -322,12 +339,13 @@ int ts_transform_apply(ts_target t, ts_transform x, ts_array a, ts_array b, ts_a
       if (grid <= 0x7fffffffull) {
         void* args[] = {&xp, &yp, &dp, &q, &head, const_cast<unsigned long long*>(&nvec),
                         const_cast<unsigned long long*>(&tail)};
-        he = hipModuleLaunchKernel(x->fn_vec, static_cast<unsigned>(grid), 1, 1, block, 1, 1, 0, t->stream,
-                                   args, nullptr);
+        he = hipModuleLaunchKernel(vw == 16 ? x->fn_vec : x->fn_vec8, static_cast<unsigned>(grid), 1, 1, block, 1,
+                                   1, 0, t->stream, args, nullptr);
         if (he != hipSuccess) return api_hip_fail(he, "hipModuleLaunchKernel");
         return TS_OK;
       }
     }
+    const unsigned block = 256;
     unsigned long long nn = n;
     void* args[] = {&xp, &yp, &dp, &q, &nn};
     unsigned long long grid = (n + block - 1) / block;

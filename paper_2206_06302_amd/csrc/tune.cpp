@@ -87,12 +87,15 @@ std::vector<ts_kernel_cfg> candidates(int batched) {
   std::vector<ts_kernel_cfg> out;
   if (!batched) {
     for (int vb : {16, 8})
-      for (int block : {256, 512, 1024})
+      for (int block : {64, 128, 256, 512, 1024})
         for (int u : {1, 2, 4, 8})
           for (int ntl : {0, 1})
             for (int nts : {0, 1})
               for (int g : {0, 2, 4, 8}) {
-                if (vb == 8 && (u == 1 || g == 2)) continue;  // keep the 8-byte set small
+                if (vb == 8 && g == 2) continue;  // keep the 8-byte set small
+                // Workgroups of one or two waves only as one pass over the
+                // array: a persistent grid of them leaves each CU a few waves.
+                if (block < 256 && g != 0) continue;
                 out.push_back(ts_kernel_cfg{block, u, vb, ntl, nts, g, 0, 1, 0});
               }
   } else {
