@@ -213,6 +213,7 @@ def ceiling_leg(ts, tgt, n, reps=20):
     A, B, C = (ts.Array.alloc(tgt, "f64", n) for _ in range(3))
     for k, arr in enumerate((A, B, C)):
         arr.fill_uniform(6, k)
+    settle(lambda: ts.run_op(tgt, "triad", A, B, C, 3.0))
     out = {}
     for name, reads, writes in PROBE_KINDS:
         moved = (reads + writes) * nbytes
@@ -353,7 +354,7 @@ def batched_leg(ts, torch, tgt, count=4096, seed=5, replays=50, triad_reps=20, m
 
 def reduced_leg(ts, torch, tgt, n=1 << 28, reps=10, samples=1 << 14, chain_steps=20):
     """Storage as f64/f32/bf16/f16 (arithmetic in binary32 for the narrow
-    types), N = 2^28 per array: per map, GB/s over a chain of 1 + 20
+    types), N = 2^28 per array: per map, GB/s over a chain of 10 + 20
     iterations and over standalone launches, elements/s, and the maximum
     relative error of each map against binary64 arithmetic on the same
     stored inputs (numpy, on sampled elements; normal results only)."""
@@ -374,12 +375,12 @@ def reduced_leg(ts, torch, tgt, n=1 << 28, reps=10, samples=1 << 14, chain_steps
         roles = {"copy": (A, None, C, 0, None, 2), "scale": (C, None, B, 2, None, 1),
                  "add": (A, B, C, 0, 1, 2), "triad": (B, C, A, 1, 2, 0)}
         res = {}
-        # the chain: 1 warm-up and `chain_steps` timed iterations of the four
-        # maps in listing order, per-kernel events (values grow 15-fold per
-        # iteration and reach infinity in the 16-bit types; the traffic is
-        # the same)
+        # the chain: 10 settling and `chain_steps` timed iterations of the
+        # four maps in listing order, per-kernel events (values grow 15-fold
+        # per iteration and reach infinity in the 16-bit types; the traffic
+        # is the same)
         ev = [[ts.Event(timing=True) for _ in range(5)] for _ in range(chain_steps)]
-        ts.stream_iteration(tgt, A, B, C, 3.0)
+        settle(lambda: ts.stream_iteration(tgt, A, B, C, 3.0), SETTLE_LAUNCHES // 4)
         for st in range(chain_steps):
             ev[st][0].record(tgt)
             for k, op in enumerate(OPS):
@@ -443,6 +444,17 @@ def timed_launches(ts, tgt, launch, reps):
     return [ev[i].elapsed_ms(ev[i + 1]) for i in range(reps)]
 
 
+SETTLE_LAUNCHES = 40
+
+
+def settle(launch, count=SETTLE_LAUNCHES):
+    """Untimed launches before a measurement that follows host-side work
+    (compiling, allocating, filling): after the GPU has idled, the first few
+    dozen launches of a streaming kernel run up to 20 % slow, then recover."""
+    for _ in range(count):
+        launch()
+
+
 def sweep_leg(ts, tgt, lo=16, hi=29, reps=20, b2b_below=22, b2b_reps=100):
     """Size and alignment sweep for f64 and f32 arrays of 2^p elements,
     aligned and as 2^p + 7 elements one element past an aligned base, seeded
@@ -461,6 +473,8 @@ def sweep_leg(ts, tgt, lo=16, hi=29, reps=20, b2b_below=22, b2b_reps=100):
                 A, B, C = (ts.Array.alloc(tgt, dtype, n, off) for _ in range(3))
                 for k, arr in enumerate((A, B, C)):
                     arr.fill_uniform(3, k)
+                if p >= 24:
+                    settle(lambda: ts.run_op(tgt, "triad", B, C, A, 3.0), SETTLE_LAUNCHES // 2)
                 ws = 3 * n * es
                 row = {"working_set_MiB": round(ws / 2 ** 20, 2),
                        "regime": "L2" if ws <= 32 << 20 else ("MALL" if ws <= 256 << 20 else "HBM")}
@@ -537,6 +551,8 @@ def transform_leg(ts, tgt, n, reps=20):
     tr = ts.Transform(tgt, "fma(q, y, x)", 2, "f64")
     cases = (("transform_fma_expression", lambda: tr(tgt, B, D, C, 3.0)),
              ("tuned_triad_kernel", lambda: ts.triad(tgt, B, C, A, 3.0)))
+    for _, fn in cases:
+        settle(fn, SETTLE_LAUNCHES // 2)
     ms = {name: [] for name, _ in cases}
     for rnd in range(2):
         for name, fn in (cases if rnd == 0 else cases[::-1]):
@@ -586,6 +602,7 @@ def comparator_leg(ts, torch, n, reps=20):
     except (OSError, AttributeError, RuntimeError) as e:
         out["rocblas"] = {"error": str(e)}
     with torch.cuda.stream(stream):
+        settle(cases["runtime_memcpy_d2d"][0])
         for name, (fn, nbytes) in cases.items():
             fn()
             ev = [ts.Event(timing=True) for _ in range(reps + 1)]

@@ -184,7 +184,7 @@ def _reduced_summary(raw, cmd):
          "Made by `python paper_2206_06302_amd/profiling.py run` (then `summarize`); the run:", "",
          "```", "export TMPDIR=/tmp; cd /tmp", cmd, "```", "",
          "Binary64 storage beside binary32, bfloat16 and binary16 storage (arithmetic in binary32 for the",
-         "16-bit types).  Per storage type and map: the launches over 2^28 elements (1 + 20 of the chained",
+         "16-bit types).  Per storage type and map: the launches over 2^28 elements (10 + 20 of the chained",
          "iteration, then 2 + 10 standalone and 1 for the error figure), their average duration from the",
          "trace, STREAM bytes / that duration, and elements per second against binary64's.", "",
          "| storage | map | kernel shape | dispatches | avg µs | GB/s (avg) | Gelem/s | elements/s vs f64 | "
