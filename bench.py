@@ -898,10 +898,12 @@ def main():
             if a.legs and name not in a.legs:
                 continue
             log(f"{name} leg")
+            t_leg = time.perf_counter()
             try:
                 result[name] = fn()
             except Exception as e:  # an extra leg must not hide the headline
                 result[name] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"{name} leg done in {time.perf_counter() - t_leg:.1f} s")
         if "triad_best_GBps" in result.get("batched", {}):
             bt = result["batched"]
             bt["triad_vs_plain_n2p27_triad"] = round(bt["triad_best_GBps"] / tri["best_GBps"], 3)
