@@ -150,7 +150,7 @@ int launch_map(ts_target_s* t, int op, int dtype, const void* x, const void* y, 
     const uint64_t cap = static_cast<uint64_t>(cfg.grid_per_cu) * static_cast<uint64_t>(t->info.compute_units);
     if (grid > cap) grid = cap;
   }
-  if (grid > kMaxGridX) grid = kMaxGridX;  // the loop strides over the rest
+  grid = cap_grid(grid, block);  // the loop strides over the rest
   PlainLaunch L{};
   L.x = x;
   L.y = has_y ? y : x;

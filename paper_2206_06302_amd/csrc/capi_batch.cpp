@@ -135,7 +135,7 @@ int launch_batch(ts_target_s* t, ts_batch_s* b, int op, const ts_kernel_cfg& cfg
                       ? static_cast<uint64_t>(cfg.grid_per_cu) * static_cast<uint64_t>(t->info.compute_units)
                       : groups;
   if (grid > groups) grid = groups;
-  if (grid > kMaxGridX) grid = kMaxGridX;
+  grid = cap_grid(grid, static_cast<uint64_t>(cfg.block));  // the kernel strides over the rest
   if (grid < 1) grid = 1;
   L.grid = static_cast<uint32_t>(grid);
   L.block = static_cast<uint32_t>(cfg.block);
@@ -170,8 +170,7 @@ uint32_t aux_tiles_per_wg() { return kAuxTilesPerWg; }
 
 uint32_t aux_grid(uint64_t ntiles) {
   const uint64_t k = aux_tiles_per_wg();
-  uint64_t g = (ntiles + k - 1) / k;
-  if (g > kMaxGridX) g = kMaxGridX;
+  const uint64_t g = cap_grid((ntiles + k - 1) / k, kAuxBlock);
   return static_cast<uint32_t>(g < 1 ? 1 : g);
 }
 

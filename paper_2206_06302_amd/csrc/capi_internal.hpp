@@ -25,8 +25,6 @@
 
 namespace tsapi {
 
-// Largest grid.x of a launch; kernels stride over whatever lies beyond it.
-constexpr uint64_t kMaxGridX = 0x7fffffffull;
 // Events that only time work: no system-scope release when recorded.
 constexpr unsigned kTimingEventFlags = hipEventDisableSystemFence;
 constexpr uint32_t kBatchMagic = 0x42415431u;

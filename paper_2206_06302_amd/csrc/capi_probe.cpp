@@ -53,6 +53,8 @@ int ts_probe_bandwidth(ts_target t, const ts_probe_cfg* cfg, ts_array x, ts_arra
                 static_cast<unsigned long long>(per_wg));
   const uint64_t grid = bytes / per_wg;
   if (grid > kMaxGridX) return fail(TS_E_SHAPE, "probe: more than 2^31 - 1 workgroups");
+  if (grid * static_cast<uint64_t>(c.block) > kMaxWorkItems)
+    return fail(TS_E_SHAPE, "probe: more than 2^32 - 1 lanes in one launch");
   if ((st = check_operand(t, dst, bytes, "dst")) != TS_OK) return st;
   const uintptr_t dp = reinterpret_cast<uintptr_t>(dst->ptr);
   if (c.reads >= 1) {

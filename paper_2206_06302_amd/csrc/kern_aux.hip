@@ -525,15 +525,15 @@ hipError_t launch_batch_fill(int dt, const BatchTile* tiles, uint64_t ntiles, ui
                              int uniform, double value, uint64_t seed, uint32_t grid, hipStream_t s) {
   if (per_wg < 1 || per_wg > kAuxMaxTilesPerWg) return hipErrorInvalidValue;
   if (uniform) {
-    TS_BY_FORMAT_U(dt, true, dim3(grid), dim3(256), 0, s, tiles, ntiles, per_wg, which, value, seed)
+    TS_BY_FORMAT_U(dt, true, dim3(grid), dim3(kAuxBlock), 0, s, tiles, ntiles, per_wg, which, value, seed)
   }
-  TS_BY_FORMAT_U(dt, false, dim3(grid), dim3(256), 0, s, tiles, ntiles, per_wg, which, value, seed)
+  TS_BY_FORMAT_U(dt, false, dim3(grid), dim3(kAuxBlock), 0, s, tiles, ntiles, per_wg, which, value, seed)
 }
 
 hipError_t launch_batch_mismatch(int dt, const BatchTile* tiles, uint64_t ntiles, uint32_t per_wg, int which,
                                  const double* expected, unsigned long long* counts, uint32_t grid,
                                  hipStream_t s) {
-  TS_BY_FORMAT(dt, batch_mismatch_kernel, dim3(grid), dim3(kReduceBlock), 0, s, tiles, ntiles, per_wg, which,
+  TS_BY_FORMAT(dt, batch_mismatch_kernel, dim3(grid), dim3(kAuxBlock), 0, s, tiles, ntiles, per_wg, which,
                expected, counts)
 }
 

@@ -103,10 +103,11 @@ TypeText type_text(int dtype) {
 }
 
 // The generated source holds three kernels around the expression:
-//   ts_transform_vec     one pass, 16-byte nontemporal vectors (16 / element
-//                        size elements per lane) plus an element-wise head and
-//                        tail, for operands that share their misalignment
-//                        modulo 16 bytes;
+//   ts_transform_vec     16-byte nontemporal vectors (16 / element size
+//                        elements), one per lane in one pass (a grid-stride
+//                        loop covers arrays beyond the largest launch), plus
+//                        an element-wise head and tail, for operands that
+//                        share their misalignment modulo 16 bytes;
 //   ts_transform_vec8    the same with 8-byte vectors, for operands that share
 //                        their misalignment modulo 8 bytes;
 //   ts_transform_kernel  element-wise with a grid-stride loop, for any operands.
@@ -145,22 +146,23 @@ std::string kernel_source(const std::string& expr, int n_inputs, int dtype) {
          "    unsigned long long nvec, unsigned long long tail) {\n"
          "  const ts_arith_t q = (ts_arith_t)qd;\n"
          "  const unsigned long long g = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;\n"
+         "  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;\n"
          "  const unsigned long long t0 = head + nvec * " + w.elems + ";\n";
     s += two ? "  if (g < head) ds[g] = ts_apply(xs[g], ys[g], q);\n"
                "  if (g < tail) ds[t0 + g] = ts_apply(xs[t0 + g], ys[t0 + g], q);\n"
              : "  if (g < head) ds[g] = ts_apply(xs[g], xs[g], q);\n"
                "  if (g < tail) ds[t0 + g] = ts_apply(xs[t0 + g], xs[t0 + g], q);\n";
-    s += "  if (g < nvec) {\n"
+    s += "  for (unsigned long long v = g; v < nvec; v += stride) {\n"
          "    const " + vt + " xv = __builtin_bit_cast(" + vt + ",\n"
-         "        __builtin_nontemporal_load(reinterpret_cast<const " + w.raw + "*>(xs + head) + g));\n";
+         "        __builtin_nontemporal_load(reinterpret_cast<const " + w.raw + "*>(xs + head) + v));\n";
     s += two ? "    const " + vt + " yv = __builtin_bit_cast(" + vt + ",\n"
-               "        __builtin_nontemporal_load(reinterpret_cast<const " + w.raw + "*>(ys + head) + g));\n"
+               "        __builtin_nontemporal_load(reinterpret_cast<const " + w.raw + "*>(ys + head) + v));\n"
              : "    const " + vt + " yv = xv;\n";
     s += "    " + vt + " dv;\n"
          "#pragma unroll\n"
          "    for (unsigned e = 0; e < " + w.elems + "; ++e) dv.v[e] = ts_apply(xv.v[e], yv.v[e], q);\n"
          "    __builtin_nontemporal_store(__builtin_bit_cast(" + w.raw + ", dv), reinterpret_cast<" + w.raw +
-         "*>(ds + head) + g);\n"
+         "*>(ds + head) + v);\n"
          "  }\n}\n";
   }
   return s;
@@ -335,15 +337,14 @@ int ts_transform_apply(ts_target t, ts_transform x, ts_array a, ts_array b, ts_a
       const unsigned long long tail = n - head - nvec * per_vec;
       unsigned long long lanes = nvec > head ? nvec : head;
       if (tail > lanes) lanes = tail;
-      const unsigned long long grid = (lanes + block - 1) / block;
-      if (grid <= 0x7fffffffull) {
-        void* args[] = {&xp, &yp, &dp, &q, &head, const_cast<unsigned long long*>(&nvec),
-                        const_cast<unsigned long long*>(&tail)};
-        he = hipModuleLaunchKernel(vw == 16 ? x->fn_vec : x->fn_vec8, static_cast<unsigned>(grid), 1, 1, block, 1,
-                                   1, 0, t->stream, args, nullptr);
-        if (he != hipSuccess) return api_hip_fail(he, "hipModuleLaunchKernel");
-        return TS_OK;
-      }
+      // one pass of one vector per lane, capped (the kernel strides over the rest)
+      const unsigned long long grid = cap_grid((lanes + block - 1) / block, block);
+      void* args[] = {&xp, &yp, &dp, &q, &head, const_cast<unsigned long long*>(&nvec),
+                      const_cast<unsigned long long*>(&tail)};
+      he = hipModuleLaunchKernel(vw == 16 ? x->fn_vec : x->fn_vec8, static_cast<unsigned>(grid < 1 ? 1 : grid), 1,
+                                 1, block, 1, 1, 0, t->stream, args, nullptr);
+      if (he != hipSuccess) return api_hip_fail(he, "hipModuleLaunchKernel");
+      return TS_OK;
     }
     const unsigned block = 256;
     unsigned long long nn = n;

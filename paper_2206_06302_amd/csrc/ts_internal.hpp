@@ -98,7 +98,9 @@ hipError_t noalloc_parts(int device, CsPart** out);
 hipError_t launch_mismatch(int dt, const void* x, const void* ref, uint64_t n, void* scratch,
                            hipStream_t s);
 // Batched fills and mismatch counts give `per_wg` consecutive tiles to each
-// workgroup of `grid` (which strides over any tiles beyond).
+// workgroup of `grid` (which strides over any tiles beyond), kAuxBlock lanes
+// per workgroup.
+constexpr uint32_t kAuxBlock = 256;
 hipError_t launch_batch_fill(int dt, const BatchTile* tiles, uint64_t ntiles, uint32_t per_wg, int which,
                              int uniform, double value, uint64_t seed, uint32_t grid, hipStream_t s);
 // counts: device array of one unsigned long long per instance, zeroed by the

@@ -13,6 +13,20 @@
 
 namespace ts {
 
+// Largest grid.x of a launch.
+constexpr uint64_t kMaxGridX = 0x7fffffffull;
+// The dispatch counts a launch's work-items (grid.x * block) in 32 bits, so
+// a launch holds at most 2^32 - 1 of them; a larger one would run only part
+// of its grid.
+constexpr uint64_t kMaxWorkItems = 0xffffffffull;
+// Workgroups of `block` lanes for a grid-stride kernel: `grid`, capped so
+// that both limits hold (the kernel's loop covers whatever lies beyond).
+inline uint64_t cap_grid(uint64_t grid, uint64_t block) {
+  uint64_t cap = kMaxWorkItems / block;
+  if (cap > kMaxGridX) cap = kMaxGridX;
+  return grid > cap ? cap : grid;
+}
+
 // Status codes (same values as ts_status in tstream.h).
 enum : int {
   ST_OK = 0,
