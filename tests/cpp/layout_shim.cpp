@@ -83,4 +83,6 @@ int shim_check_batch_overlap(const uint64_t* descs, size_t count, uint64_t es, c
   return st;
 }
 
+uint64_t shim_cap_grid(uint64_t grid, uint64_t block) { return ts::cap_grid(grid, block); }
+
 }  // extern "C"

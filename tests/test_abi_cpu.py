@@ -254,7 +254,23 @@ def shim(tmp_path_factory):
                                     U, U, U]
     lib.shim_check_batch_overlap.argtypes = [U, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_char_p,
                                              ctypes.c_size_t]
+    lib.shim_cap_grid.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    lib.shim_cap_grid.restype = ctypes.c_uint64
     return lib
+
+
+def test_grids_stay_below_the_lane_count_limit(shim):
+    """A launch's lanes (grid x block) are counted in 32 bits and its grid.x
+    in 31: grid-stride launches are capped below both, and grids within them
+    are left alone."""
+    lanes, gx = (1 << 32) - 1, (1 << 31) - 1
+    for block in (64, 128, 256, 512, 1024):
+        for grid in (1, 1000, lanes // block, lanes // block + 1, (1 << 26) + 1, 1 << 40):
+            g = shim.shim_cap_grid(grid, block)
+            assert g * block <= lanes and g <= gx
+            assert g == min(grid, lanes // block, gx)
+    # the one-wave binary64 triad at 2^32 + 9 elements: one pass would need 2^32 + 64 lanes
+    assert shim.shim_cap_grid(((1 << 32) + 9 + 63) // 64, 64) == lanes // 64
 
 
 def _u64(vals):
