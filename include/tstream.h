@@ -57,7 +57,7 @@ extern "C" {
 #endif
 
 #define TS_VERSION_MAJOR 2
-#define TS_VERSION_MINOR 0
+#define TS_VERSION_MINOR 1
 
 typedef enum {
     TS_OK = 0,
@@ -321,6 +321,15 @@ typedef struct {
                             tiles_per_wg 1): 1 = each workgroup also reads
                             the tile record 2048 workgroups ahead into its
                             XCD's L2; 0 = off.  Plain kernels: 0          */
+    int32_t wgs_per_tile; /* batched: one-wave workgroups that share each
+                            tile, 1 (0 = 1) or a power of two up to 128;
+                            workgroup w takes piece w mod P of tile w / P
+                            (one vector per lane, then every P-th), so
+                            consecutive workgroups, spread over the CUs,
+                            cover consecutive pieces of a tile.  More than 1
+                            needs block 64, unroll 1, grid_per_cu 0,
+                            tiles_per_wg 1 and record_ahead 0, and allows
+                            vec_bytes 8 beside 16.  Plain kernels: 0 or 1 */
 } ts_kernel_cfg;
 
 /* Operand alignment classes (keys of the tuning table). */

@@ -25,6 +25,7 @@ class KernelCfg(ctypes.Structure):
         ("tile_elems", ctypes.c_int64),
         ("tiles_per_wg", ctypes.c_int32),
         ("record_ahead", ctypes.c_int32),
+        ("wgs_per_tile", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -42,6 +43,7 @@ class KernelCfg(ctypes.Structure):
         c.tile_elems = int(d.get("tile_elems", 0))
         c.tiles_per_wg = int(d.get("tiles_per_wg", 0))
         c.record_ahead = int(d.get("record_ahead", 0))
+        c.wgs_per_tile = int(d.get("wgs_per_tile", 0))
         return c
 
 

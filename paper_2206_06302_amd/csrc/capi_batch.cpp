@@ -127,6 +127,27 @@ int launch_batch(ts_target_s* t, ts_batch_s* b, int op, const ts_kernel_cfg& cfg
         L.ntiles = p.ntiles;
       }
   }
+  L.op = op;
+  L.unroll = cfg.unroll;
+  L.ntl = cfg.nt_load;
+  L.nts = cfg.nt_store;
+  L.stream = t->stream;
+  if (cfg.wgs_per_tile > 1) {
+    // One-wave workgroups that share each tile, one piece each; the kernel
+    // strides over whatever lies beyond the largest launch.
+    int lg = 0;
+    while ((1 << lg) < cfg.wgs_per_tile) ++lg;
+    const uint64_t grid = cap_grid(L.ntiles << lg, 64);
+    L.grid = static_cast<uint32_t>(grid < 1 ? 1 : grid);
+    L.block = 64;
+    L.tiles_per_wg = 1;
+    L.record_ahead = 0;
+    L.pieces_log2 = lg;
+    L.vb = cfg.vec_bytes;
+    const hipError_t e = batch_launch(b->dtype, L);
+    if (e != hipSuccess) return hip_fail(e, "batched STREAM kernel launch");
+    return TS_OK;
+  }
   // grid_per_cu 0: one workgroup per group of tiles_per_wg consecutive
   // tiles; otherwise a persistent grid that strides over the groups.
   const uint64_t per_wg = cfg.tiles_per_wg > 1 ? static_cast<uint64_t>(cfg.tiles_per_wg) : 1;
@@ -139,13 +160,10 @@ int launch_batch(ts_target_s* t, ts_batch_s* b, int op, const ts_kernel_cfg& cfg
   if (grid < 1) grid = 1;
   L.grid = static_cast<uint32_t>(grid);
   L.block = static_cast<uint32_t>(cfg.block);
-  L.op = op;
-  L.unroll = cfg.unroll;
-  L.ntl = cfg.nt_load;
-  L.nts = cfg.nt_store;
   L.tiles_per_wg = static_cast<int>(per_wg);
   L.record_ahead = cfg.record_ahead && per_wg == 1 && grid >= L.ntiles ? 1 : 0;
-  L.stream = t->stream;
+  L.pieces_log2 = 0;
+  L.vb = 16;
   const hipError_t e = batch_launch(b->dtype, L);
   if (e != hipSuccess) return hip_fail(e, "batched STREAM kernel launch");
   return TS_OK;

@@ -395,6 +395,37 @@ __global__ __launch_bounds__(1024) void batch_kernel(const BatchTile* __restrict
   }
 }
 
+// Pieces: 2^PL one-wave workgroups share each tile.  Workgroup w takes
+// piece p = w mod P of tile t = w / P: vector p*64 + lane of the tile's
+// aligned middle, then every (P*64)-th after it; piece 0 also takes the
+// element-wise head and tail.  Consecutive workgroups go to different CUs,
+// so a tile's pieces stream from many CUs at once, as the plain kernel's
+// one-wave shape does, and the P workgroups of a tile read its record from
+// one cache line.  The grid strides over whatever lies beyond it.
+template <int DT, int OP, int VB, bool NTL, bool NTS>
+__global__ __launch_bounds__(64) void batch_piece_kernel(const BatchTile* __restrict__ tiles, uint64_t ntiles,
+                                                         uint32_t pieces_log2) {
+  using T = typename Fmt<DT>::T;
+  using R = typename Raw<VB>::type;
+  constexpr uint64_t V = VB / sizeof(T);
+  const uint64_t P = 1ull << pieces_log2;
+  const uint64_t lane = threadIdx.x;
+  const uint64_t total = ntiles << pieces_log2;
+  for (uint64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const uint64_t t = w >> pieces_log2, p = w & (P - 1);
+    const TileSpan<DT> s = tile_span<DT, OP>(tiles[t]);
+    const uint64_t nvec = (s.ve - s.vs) / V;
+    for (uint64_t v = p * 64 + lane; v < nvec; v += P * 64) {
+      const R rx = load<VB, NTL>(s.x + s.vs + v * V);
+      R ry;
+      if constexpr (uses_y<OP>()) ry = load<VB, NTL>(s.y + s.vs + v * V);
+      else ry = rx;
+      store<VB, NTS>(s.d + s.vs + v * V, map_vec<DT, OP, VB>(rx, ry, s.q));
+    }
+    if (p == 0) tile_edges<DT, OP>(s, lane, 64);
+  }
+}
+
 template <int DT, int OP, int VB, int U, bool NTL, bool NTS>
 hipError_t launch_plain_inst(const PlainLaunch& L) {
   hipLaunchKernelGGL((stream_kernel<DT, OP, VB, U, NTL, NTS>), dim3(L.grid), dim3(L.block), 0,
@@ -497,8 +528,42 @@ hipError_t batch_u(const BatchLaunch& L) {
   }
 }
 
+template <int DT, int OP, int VB, bool NTL, bool NTS>
+hipError_t launch_piece_inst(const BatchLaunch& L) {
+  hipLaunchKernelGGL((batch_piece_kernel<DT, OP, VB, NTL, NTS>), dim3(L.grid), dim3(64), 0, L.stream, L.tiles,
+                     L.ntiles, static_cast<uint32_t>(L.pieces_log2));
+  return hipGetLastError();
+}
+
+template <int DT, int OP, int VB>
+hipError_t piece_nt(const BatchLaunch& L) {
+  if (L.ntl) {
+    return L.nts ? launch_piece_inst<DT, OP, VB, true, true>(L) : launch_piece_inst<DT, OP, VB, true, false>(L);
+  }
+  return L.nts ? launch_piece_inst<DT, OP, VB, false, true>(L) : launch_piece_inst<DT, OP, VB, false, false>(L);
+}
+
+template <int DT, int OP>
+hipError_t batch_pieces(const BatchLaunch& L) {
+  if (L.block != 64) return hipErrorInvalidValue;
+  switch (L.vb) {
+    case 16: return piece_nt<DT, OP, 16>(L);
+    case 8: return piece_nt<DT, OP, 8>(L);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int DT>
 hipError_t batch_dispatch(const BatchLaunch& L) {
+  if (L.pieces_log2 > 0) {
+    switch (L.op) {
+      case OP_COPY: return batch_pieces<DT, OP_COPY>(L);
+      case OP_SCALE: return batch_pieces<DT, OP_SCALE>(L);
+      case OP_ADD: return batch_pieces<DT, OP_ADD>(L);
+      case OP_TRIAD: return batch_pieces<DT, OP_TRIAD>(L);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (L.op) {
     case OP_COPY: return batch_u<DT, OP_COPY>(L);
     case OP_SCALE: return batch_u<DT, OP_SCALE>(L);

@@ -31,6 +31,8 @@ struct BatchLaunch {
   int op, unroll, ntl, nts;
   int tiles_per_wg;  // consecutive tiles per workgroup: 1, 2, 4 or 8
   int record_ahead;  // one workgroup per tile: read the record kRecordAhead ahead
+  int pieces_log2;   // > 0: 2^pieces_log2 one-wave workgroups share each tile
+  int vb;            // with pieces: bytes per lane access, 16 or 8
   hipStream_t stream;
 };
 

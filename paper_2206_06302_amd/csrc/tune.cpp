@@ -46,6 +46,7 @@ ts_kernel_cfg default_cfg(int batched, int dtype) {
     c.grid_per_cu = 0;
     c.tile_elems = 4096 / es;
     c.tiles_per_wg = 1;
+    c.wgs_per_tile = 1;
   } else {
     c.block = 256;
     c.unroll = 4;
@@ -53,6 +54,7 @@ ts_kernel_cfg default_cfg(int batched, int dtype) {
     c.grid_per_cu = 0;
     c.tile_elems = 0;
     c.tiles_per_wg = 1;
+    c.wgs_per_tile = 1;
   }
   return c;
 }
@@ -61,7 +63,15 @@ std::string cfg_problem(const ts_kernel_cfg& c, int batched) {
   if (c.block < 64 || c.block > 1024 || c.block % 64) return "block must be 64..1024, a multiple of 64";
   if (c.unroll != 1 && c.unroll != 2 && c.unroll != 4 && c.unroll != 8) return "unroll must be 1, 2, 4 or 8";
   if (batched) {
-    if (c.vec_bytes != 16) return "batched kernels use 16-byte vectors";
+    const int P = c.wgs_per_tile;
+    if (P < 0 || P > 128 || (P & (P - 1))) return "wgs_per_tile must be 1 (0 = 1) or a power of two up to 128";
+    if (P > 1) {
+      if (c.vec_bytes != 16 && c.vec_bytes != 8) return "workgroups sharing a tile use 16- or 8-byte vectors";
+      if (c.block != 64 || c.unroll != 1 || c.grid_per_cu != 0 || c.tiles_per_wg > 1 || c.record_ahead != 0)
+        return "workgroups sharing a tile take block 64, unroll 1, grid_per_cu 0, tiles_per_wg 1, record_ahead 0";
+    } else if (c.vec_bytes != 16) {
+      return "batched kernels with one workgroup per tile use 16-byte vectors";
+    }
     if (c.grid_per_cu < 0 || c.grid_per_cu > 64) return "batched grid_per_cu must be 0..64";
     if (c.tile_elems < 0 || c.tile_elems % 8) return "tile_elems must be a multiple of 8";
     if (c.tiles_per_wg != 0 && c.tiles_per_wg != 1 && c.tiles_per_wg != 2 && c.tiles_per_wg != 4 &&
@@ -77,6 +87,7 @@ std::string cfg_problem(const ts_kernel_cfg& c, int batched) {
     if (c.grid_per_cu < 0 || c.grid_per_cu > 64) return "grid_per_cu must be 0..64";
     if (c.tiles_per_wg != 0 && c.tiles_per_wg != 1) return "plain kernels take tiles_per_wg 0 or 1";
     if (c.record_ahead != 0) return "plain kernels take record_ahead 0";
+    if (c.wgs_per_tile != 0 && c.wgs_per_tile != 1) return "plain kernels take wgs_per_tile 0 or 1";
   }
   if ((c.nt_load != 0 && c.nt_load != 1) || (c.nt_store != 0 && c.nt_store != 1))
     return "nt flags must be 0 or 1";
@@ -96,7 +107,7 @@ std::vector<ts_kernel_cfg> candidates(int batched) {
                 // Workgroups of one or two waves only as one pass over the
                 // array: a persistent grid of them leaves each CU a few waves.
                 if (block < 256 && g != 0) continue;
-                out.push_back(ts_kernel_cfg{block, u, vb, ntl, nts, g, 0, 1, 0});
+                out.push_back(ts_kernel_cfg{block, u, vb, ntl, nts, g, 0, 1, 0, 1});
               }
   } else {
     // One workgroup per tile (grid_per_cu 0) with small tiles ...
@@ -105,7 +116,12 @@ std::vector<ts_kernel_cfg> candidates(int batched) {
         for (int ntl : {0, 1})
           for (int64_t tile : {512, 1024, 2048, 4096, 8192})
             for (int ahead : {0, 1})
-              out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, 0, tile, 1, ahead});
+              out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, 0, tile, 1, ahead, 1});
+    // ... one-wave workgroups sharing each tile, one piece each ...
+    for (int vb : {16, 8})
+      for (int P : {8, 16, 32})
+        for (int64_t tile : {1024, 2048, 4096})
+          out.push_back(ts_kernel_cfg{64, 1, vb, 1, 1, 0, tile, 1, 0, P});
     // ... several consecutive small tiles per workgroup, all their first
     // loads in flight together ...
     for (int block : {256, 512})
@@ -113,14 +129,14 @@ std::vector<ts_kernel_cfg> candidates(int batched) {
         for (int ntl : {0, 1})
           for (int k : {2, 4, 8})
             for (int64_t tile : {512, 1024, 2048})
-              out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, 0, tile, k, 0});
+              out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, 0, tile, k, 0, 1});
     // ... and persistent grids that stride over larger tiles.
     for (int block : {512, 1024})
       for (int u : {4, 8})
         for (int ntl : {0, 1})
           for (int g : {4, 8})
             for (int64_t tile : {16384, 65536})
-              out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, g, tile, 1, 0});
+              out.push_back(ts_kernel_cfg{block, u, 16, ntl, 1, g, tile, 1, 0, 1});
   }
   return out;
 }
@@ -180,11 +196,11 @@ std::string TuneTable::to_json() const {
                   "%s\n    {\"op\": \"%s\", \"dtype\": \"%s\", \"bucket\": %d, \"align\": %d, "
                   "\"batched\": %d, \"block\": %d, \"unroll\": %d, \"vec_bytes\": %d, "
                   "\"nt_load\": %d, \"nt_store\": %d, \"grid_per_cu\": %d, \"tile_elems\": %lld, "
-                  "\"tiles_per_wg\": %d, \"record_ahead\": %d, \"bytes_per_s\": %.6e}",
+                  "\"tiles_per_wg\": %d, \"record_ahead\": %d, \"wgs_per_tile\": %d, \"bytes_per_s\": %.6e}",
                   first ? "" : ",", kOpNames[k.op], kTypeNames[k.dtype], k.bucket, k.align,
                   k.batched, c.block, c.unroll, c.vec_bytes, c.nt_load, c.nt_store, c.grid_per_cu,
                   static_cast<long long>(c.tile_elems), c.tiles_per_wg, c.record_ahead,
-                  kv.second.bytes_per_s);
+                  c.wgs_per_tile < 1 ? 1 : c.wgs_per_tile, kv.second.bytes_per_s);
     os << buf;
     first = false;
   }
@@ -295,6 +311,7 @@ bool parse_entry(Reader& r, TuneKey& k, TuneEntry& e) {
   // Tables written before the field existed hold one tile per workgroup.
   e.cfg.tiles_per_wg = nums.count("tiles_per_wg") ? static_cast<int32_t>(nums["tiles_per_wg"]) : 1;
   e.cfg.record_ahead = nums.count("record_ahead") ? static_cast<int32_t>(nums["record_ahead"]) : 0;
+  e.cfg.wgs_per_tile = nums.count("wgs_per_tile") ? static_cast<int32_t>(nums["wgs_per_tile"]) : 1;
   e.bytes_per_s = nums.count("bytes_per_s") ? nums["bytes_per_s"] : 0.0;
   const std::string why = cfg_problem(e.cfg, k.batched);
   if (!why.empty()) return r.fail("invalid configuration: " + why);

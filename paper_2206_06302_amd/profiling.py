@@ -380,25 +380,33 @@ def summarize(raw: str, out: str = PROFILES) -> None:
          "Made by `python paper_2206_06302_amd/profiling.py run` (then `summarize`); the run:", "",
          "```", "export TMPDIR=/tmp; cd /tmp", _command(cmds["batched trace"], raw), "```", "",
          f"Batch: 4096 instances, log-uniform lengths in [1e3, 1e7) (seed 5), {total} elements in total,",
-         f"{3*total*8/1e9:.1f} GB on the device.  Each map is one launch over all instances, one workgroup",
-         f"per group of K consecutive tiles when grid/CU is 0 (the triad's plan: {tiles} tiles of {tile}",
-         f"elements, 64-byte tile records).  Triad configuration: block {cfg['block']}, U{cfg['unroll']}, K "
+         f"{3*total*8/1e9:.1f} GB on the device.  Each map is one launch over all instances: one workgroup",
+         f"per group of K consecutive tiles, or P one-wave workgroups per tile, one piece each (the triad's",
+         f"plan: {tiles} tiles of {tile} elements, 64-byte tile records).  Triad configuration: block "
+         f"{cfg['block']}, U{cfg['unroll']}, {cfg['vec_bytes']}-byte vectors, K "
          f"{cfg.get('tiles_per_wg', 1)}, grid/CU {cfg['grid_per_cu']}, nontemporal loads {cfg['nt_load']} and "
-         f"stores {cfg['nt_store']}, record read-ahead {cfg.get('record_ahead', 0)}.",
+         f"stores {cfg['nt_store']}, record read-ahead {cfg.get('record_ahead', 0)}, P {cfg.get('wgs_per_tile', 1)}.",
          "The four-map iteration runs 50 times from a captured graph plus 1 warm-up; then each map runs",
          "alone (1 + 10 launches; the triad 1 + 20).  GB/s = STREAM bytes of one launch / its average duration.", "",
          "| kernel | map | calls | avg ms | min ms | max ms | GB/s (avg) | GB/s (min time) |",
          "|---|---|---|---|---|---|---|---|"]
     for r in _stats(os.path.join(raw, "trace_batched", "run_kernel_stats.csv")):
         m = re.search(r"batch_kernel<(\d+), (\d+), (\d+), (\d+), (\w+), (\w+), (\w+)>", r["Name"])
-        if not m or m.group(1) != "0":
+        mp = re.search(r"batch_piece_kernel<(\d+), (\d+), (\d+), (\w+), (\w+)>", r["Name"])
+        if m and m.group(1) == "0":
+            op = int(m.group(2))
+            name = (f"batch_kernel<f64,{OPS[op]},U{m.group(3)},K{m.group(4)},nt_load={int(m.group(5) == 'true')},"
+                    f"nt_store={int(m.group(6) == 'true')},record_ahead={int(m.group(7) == 'true')}>")
+        elif mp and mp.group(1) == "0":
+            op = int(mp.group(2))
+            name = (f"batch_piece_kernel<f64,{OPS[op]},VB{mp.group(3)},nt_load={int(mp.group(4) == 'true')},"
+                    f"nt_store={int(mp.group(5) == 'true')}>")
+        else:
             continue
-        op = int(m.group(2))
         b = ARRAYS[op] * total * 8
         avg, mn, mx = float(r["AverageNs"]), float(r["MinNs"]), float(r["MaxNs"])
-        L.append(f"| `batch_kernel<f64,{OPS[op]},U{m.group(3)},K{m.group(4)},nt_load={int(m.group(5) == 'true')},"
-                 f"nt_store={int(m.group(6) == 'true')},record_ahead={int(m.group(7) == 'true')}>` | {OPS[op]} | "
-                 f"{r['Calls']} | {avg/1e6:.3f} | {mn/1e6:.3f} | {mx/1e6:.3f} | {b/avg:.1f} | {b/mn:.1f} |")
+        L.append(f"| `{name}` | {OPS[op]} | {r['Calls']} | {avg/1e6:.3f} | {mn/1e6:.3f} | {mx/1e6:.3f} | "
+                 f"{b/avg:.1f} | {b/mn:.1f} |")
     L += ["", "From the same run (events on the target's stream, profiler attached):", "",
           f"* graph-replayed four-map iteration: {bb['graph_iteration_ms']} ms ({bb['graph_iteration_GBps']} GB/s)",
           f"* batched triad best {bb['triad_best_GBps']} GB/s, average {bb['triad_avg_GBps']} GB/s; one plain "
@@ -416,7 +424,7 @@ def summarize(raw: str, out: str = PROFILES) -> None:
     total, tiles = bj["total_elems"], bj["tiles"]
     rows = []
     for op in range(4):
-        d = cn.launch(rf"batch_kernel<0, {op},")
+        d = cn.launch(rf"batch_(?:piece_)?kernel<0, {op},")
         rows.append((OPS[op], d, (ARRAYS[op] - 1) * total * 8, total * 8))
     L = ["# HBM traffic counters: batched ragged STREAM, 4096 FP64 instances", "",
          "Four counter runs (each a run of its own), made by `python paper_2206_06302_amd/profiling.py run`:", "",

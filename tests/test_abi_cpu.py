@@ -57,7 +57,7 @@ def test_binding_covers_every_function(ts):
 
 
 def test_version_and_errors(ts):
-    assert ts.version() == (2, 0)
+    assert ts.version() == (2, 1)
     L = ts.lib
     assert L.ts_copy(None, None, None) == TS_E_INVALID
     assert "invalid" in ts.last_error()
@@ -193,7 +193,10 @@ def test_forced_configuration(ts):
     # several tiles per workgroup: 1, 2, 4 or 8, with unroll 1 or 2; plain kernels take 0 or 1
     for bad in ({"tiles_per_wg": 3}, {"tiles_per_wg": 16}, {"tiles_per_wg": -1},
                 {"tiles_per_wg": 2, "unroll": 4}, {"record_ahead": 2}, {"record_ahead": 1, "tiles_per_wg": 2},
-                {"record_ahead": 1, "grid_per_cu": 4}):
+                {"record_ahead": 1, "grid_per_cu": 4}, {"wgs_per_tile": 3}, {"wgs_per_tile": 256},
+                {"wgs_per_tile": 16}, {"wgs_per_tile": 16, "block": 64, "unroll": 2},
+                {"wgs_per_tile": 16, "block": 64, "record_ahead": 1},
+                {"wgs_per_tile": 16, "block": 64, "vec_bytes": 4}, {"vec_bytes": 8}):
         cfg = {"block": 256, "unroll": 1, "vec_bytes": 16, "nt_load": 1, "nt_store": 1, "grid_per_cu": 0,
                "tile_elems": 512}
         cfg.update(bad)
@@ -211,6 +214,12 @@ def test_forced_configuration(ts):
                                      "grid_per_cu": 0, "tile_elems": 1024, "tiles_per_wg": 8}, batched=True)
     assert ts.get_kernel_cfg("add", "f64", 1 << 30, batched=True)["tiles_per_wg"] == 8
     ts.set_kernel_cfg("add", "f64", None, batched=True)
+    ts.set_kernel_cfg("triad", "f64", {"block": 64, "unroll": 1, "vec_bytes": 8, "nt_load": 1, "nt_store": 1,
+                                       "grid_per_cu": 0, "tile_elems": 2048, "wgs_per_tile": 32}, batched=True)
+    assert ts.get_kernel_cfg("triad", "f64", 1 << 30, batched=True)["wgs_per_tile"] == 32
+    ts.set_kernel_cfg("triad", "f64", None, batched=True)
+    with pytest.raises(ts.TSError):  # plain kernels take wgs_per_tile 0 or 1
+        ts.set_kernel_cfg("copy", "f64", {"block": 64, "unroll": 1, "vec_bytes": 8, "wgs_per_tile": 2})
     # grid_per_cu 0 on the batched path: one workgroup per tile
     ts.set_kernel_cfg("copy", "f64", {"block": 1024, "unroll": 4, "vec_bytes": 16, "nt_load": 1, "nt_store": 1,
                                       "grid_per_cu": 0, "tile_elems": 4096}, batched=True)
@@ -233,7 +242,11 @@ def test_candidate_sets_are_valid(ts):
     assert all(c["unroll"] <= 2 for c in batched if c["tiles_per_wg"] > 1)
     assert {c["record_ahead"] for c in batched} == {0, 1} and {c["record_ahead"] for c in plain} == {0}
     assert all(c["grid_per_cu"] == 0 and c["tiles_per_wg"] == 1 for c in batched if c["record_ahead"])
-    assert {c["vec_bytes"] for c in batched} == {16}
+    assert {c["vec_bytes"] for c in batched} == {16, 8}
+    assert all(c["wgs_per_tile"] == 1 for c in plain)
+    pieces = [c for c in batched if c["wgs_per_tile"] > 1]
+    assert pieces and all(c["block"] == 64 and c["unroll"] == 1 and c["record_ahead"] == 0 for c in pieces)
+    assert all(c["vec_bytes"] == 16 for c in batched if c["wgs_per_tile"] == 1)
     ts.set_kernel_cfg("copy", "f64", None)
     ts.set_kernel_cfg("copy", "f64", None, batched=True)
 

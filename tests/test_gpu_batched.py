@@ -346,13 +346,17 @@ def test_batch_launch_shapes_do_not_change_results(env, dtype):
         ref.fill_uniform(tgt, k, 6)
     for op in OPS:
         ref.op_plain(tgt, op)
-    # (grid_per_cu, block, unroll, tile, tiles per workgroup)
-    shapes = [(0, 256, 1, 24, 1), (0, 1024, 4, 4096, 1), (0, 512, 2, 2048, 1), (1, 1024, 8, 16384, 1),
-              (64, 64, 1, 8, 1), (0, 256, 1, 24, 8), (0, 512, 2, 1024, 4), (2, 256, 2, 512, 2), (0, 64, 1, 8, 4)]
+    # (grid_per_cu, block, unroll, tile, tiles per workgroup, workgroups per tile, vector bytes)
+    shapes = [(0, 256, 1, 24, 1, 1, 16), (0, 1024, 4, 4096, 1, 1, 16), (0, 512, 2, 2048, 1, 1, 16),
+              (1, 1024, 8, 16384, 1, 1, 16), (64, 64, 1, 8, 1, 1, 16), (0, 256, 1, 24, 8, 1, 16),
+              (0, 512, 2, 1024, 4, 1, 16), (2, 256, 2, 512, 2, 1, 16), (0, 64, 1, 8, 4, 1, 16),
+              # one-wave workgroups sharing tiles: tiles smaller and larger than their pieces
+              (0, 64, 1, 2048, 1, 32, 8), (0, 64, 1, 1024, 1, 16, 16), (0, 64, 1, 24, 1, 8, 8),
+              (0, 64, 1, 8192, 1, 2, 16)]
     try:
-        for grid, block, unroll, tile, per_wg in shapes:
-            cfg = {"block": block, "unroll": unroll, "vec_bytes": 16, "nt_load": 1, "nt_store": 1,
-                   "grid_per_cu": grid, "tile_elems": tile, "tiles_per_wg": per_wg}
+        for grid, block, unroll, tile, per_wg, pieces, vb in shapes:
+            cfg = {"block": block, "unroll": unroll, "vec_bytes": vb, "nt_load": 1, "nt_store": 1,
+                   "grid_per_cu": grid, "tile_elems": tile, "tiles_per_wg": per_wg, "wgs_per_tile": pieces}
             for op in OPS:
                 ts.set_kernel_cfg(op, dtype, cfg, batched=True)
             pool = Pool(ts, torch, lens, dtype, mis)
@@ -360,7 +364,8 @@ def test_batch_launch_shapes_do_not_change_results(env, dtype):
             b.set_tile(tile)
             for k in range(3):
                 b.fill_uniform(tgt, k, 6)
-            say(f"[launch shape grid_per_cu={grid} block={block} U{unroll} tile={tile} x{per_wg} {dtype}]")
+            say(f"[launch shape grid_per_cu={grid} block={block} U{unroll} VB{vb} tile={tile} x{per_wg} "
+                f"/{pieces} {dtype}]")
             for op in OPS:
                 b.op(tgt, op)
             tgt.synchronize()
