@@ -383,7 +383,7 @@ def summarize(raw: str, out: str = PROFILES) -> None:
          f"{3*total*8/1e9:.1f} GB on the device.  Each map is one launch over all instances: one workgroup",
          f"per group of K consecutive tiles, or P one-wave workgroups per tile, one piece each (the triad's",
          f"plan: {tiles} tiles of {tile} elements, 64-byte tile records).  Triad configuration: block "
-         f"{cfg['block']}, U{cfg['unroll']}, {cfg['vec_bytes']}-byte vectors, K "
+         f"{cfg['block']}, U{cfg['unroll']}, {cfg.get('vec_bytes', 16)}-byte vectors, K "
          f"{cfg.get('tiles_per_wg', 1)}, grid/CU {cfg['grid_per_cu']}, nontemporal loads {cfg['nt_load']} and "
          f"stores {cfg['nt_store']}, record read-ahead {cfg.get('record_ahead', 0)}, P {cfg.get('wgs_per_tile', 1)}.",
          "The four-map iteration runs 50 times from a captured graph plus 1 warm-up; then each map runs",
