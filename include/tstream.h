@@ -398,7 +398,9 @@ TS_API int ts_time_op(ts_target exec, ts_op op, ts_array x, ts_array y,
  * `bytes` bytes (TS_E_SHAPE) and lie on the executor's device
  * (TS_E_PLACEMENT); operands of any storage type; dst must not overlap an
  * input (TS_E_ALIAS); y is ignored unless reads == 2, x unless reads >= 1.
- * One launch of bytes / (vec_bytes * block * unroll) workgroups, asynchronous on
+ * One launch of bytes / (vec_bytes * block * unroll) workgroups, which must
+ * hold at most 2^31 - 1 workgroups and 2^32 - 1 lanes (TS_E_SHAPE: the
+ * probe has no loop to cover more), asynchronous on
  * the executor's stream; GPU targets only (TS_E_UNSUPPORTED on a host
  * target). */
 typedef struct {
