@@ -134,11 +134,13 @@ int launch_batch(ts_target_s* t, ts_batch_s* b, int op, const ts_kernel_cfg& cfg
   L.stream = t->stream;
   if (cfg.wgs_per_tile > 1) {
     // One-wave workgroups that share each tile, one piece each; the kernel
-    // strides over whatever lies beyond the largest launch.
+    // strides over whatever lies beyond the largest launch.  Its first piece
+    // is taken unchecked, so the grid is at least 1 and at most ntiles * P.
+    if (L.ntiles == 0) return TS_OK;
     int lg = 0;
     while ((1 << lg) < cfg.wgs_per_tile) ++lg;
     const uint64_t grid = cap_grid(L.ntiles << lg, 64);
-    L.grid = static_cast<uint32_t>(grid < 1 ? 1 : grid);
+    L.grid = static_cast<uint32_t>(grid);
     L.block = 64;
     L.tiles_per_wg = 1;
     L.record_ahead = 0;

@@ -265,15 +265,19 @@ __device__ __forceinline__ TileSpan<DT> tile_span(const BatchTile& tl) {
   s.q = pick_q<DT>(tl.q, tl.qf);
   s.start = tl.start;
   s.end = tl.start + tl.count;
-  s.vs = s.end;
-  s.ve = s.end;
-  if (tl.vec_ok) {
-    const uint64_t h = tl.head;
-    s.vs = s.start < h ? h : h + (s.start - h + V - 1) / V * V;
-    if (s.vs > s.end) s.vs = s.end;
-    s.ve = s.end < h ? s.vs : h + (s.end - h) / V * V;
-    if (s.ve < s.vs) s.ve = s.vs;
-  }
+  // The vector middle is computed whether or not the instance has one, and
+  // then chosen; the empty asm takes both fields up front, so the record
+  // arrives in one round of scalar loads instead of a second one for the
+  // field the compiler would otherwise fetch late.
+  const uint32_t ok = tl.vec_ok;
+  const uint64_t h = tl.head;
+  asm volatile("" ::"s"(ok), "s"(tl.head));
+  uint64_t vs = s.start < h ? h : h + (s.start - h + V - 1) / V * V;
+  if (vs > s.end) vs = s.end;
+  uint64_t ve = s.end < h ? vs : h + (s.end - h) / V * V;
+  if (ve < vs) ve = vs;
+  s.vs = ok ? vs : s.end;
+  s.ve = ok ? ve : s.end;
   return s;
 }
 
@@ -401,7 +405,10 @@ __global__ __launch_bounds__(1024) void batch_kernel(const BatchTile* __restrict
 // element-wise head and tail.  Consecutive workgroups go to different CUs,
 // so a tile's pieces stream from many CUs at once, as the plain kernel's
 // one-wave shape does, and the P workgroups of a tile read its record from
-// one cache line.  The grid strides over whatever lies beyond it.
+// one cache line.  The grid strides over whatever lies beyond it; the host
+// launches at least one and at most ntiles * P workgroups, so every
+// workgroup has a first piece (the loop tests only before the next one, and
+// the first record load waits on nothing but the kernel arguments).
 template <int DT, int OP, int VB, bool NTL, bool NTS>
 __global__ __launch_bounds__(64) void batch_piece_kernel(const BatchTile* __restrict__ tiles, uint64_t ntiles,
                                                          uint32_t pieces_log2) {
@@ -411,7 +418,8 @@ __global__ __launch_bounds__(64) void batch_piece_kernel(const BatchTile* __rest
   const uint64_t P = 1ull << pieces_log2;
   const uint64_t lane = threadIdx.x;
   const uint64_t total = ntiles << pieces_log2;
-  for (uint64_t w = blockIdx.x; w < total; w += gridDim.x) {
+  uint64_t w = blockIdx.x;
+  do {
     const uint64_t t = w >> pieces_log2, p = w & (P - 1);
     const TileSpan<DT> s = tile_span<DT, OP>(tiles[t]);
     const uint64_t nvec = (s.ve - s.vs) / V;
@@ -423,7 +431,8 @@ __global__ __launch_bounds__(64) void batch_piece_kernel(const BatchTile* __rest
       store<VB, NTS>(s.d + s.vs + v * V, map_vec<DT, OP, VB>(rx, ry, s.q));
     }
     if (p == 0) tile_edges<DT, OP>(s, lane, 64);
-  }
+    w += gridDim.x;
+  } while (w < total);
 }
 
 template <int DT, int OP, int VB, int U, bool NTL, bool NTS>
