@@ -280,10 +280,10 @@ TS_API int ts_checksum(ts_target exec, ts_array x, double expected,
  *            result is written there in stream order on the target's
  *            stream.  The call does not wait: synchronise the target (or
  *            order later work on its stream) before reading dev_out.
- * The partial sums live in a fixed device array of 8192 parts of 32 bytes
- * (256 KiB) per GPU, loaded with the library and held until the process
+ * The partial sums live in a fixed device array of 4096 parts of 32 bytes
+ * (128 KiB) per GPU, loaded with the library and held until the process
  * ends; its address is resolved when a target is created on that GPU.  A
- * reduction of any length uses at most 8192 parts, so no n is refused for
+ * checksum of any length uses at most 4096 parts, so no n is refused for
  * scratch size (the check stays, TS_E_SHAPE).  The call makes no hipMalloc,
  * hipHostMalloc, hipFree or hipMemset and does not synchronise.  Every call on
  * one GPU shares that array: calls that overlap in time on one GPU (other

@@ -786,7 +786,7 @@ int ts_checksum_noalloc(ts_target t, ts_array x, double expected, ts_checksum_ou
   const uint64_t xbytes = x->n * dtype_size(x->dtype);
   if (o < xo + xbytes && xo < o + sizeof(ts_checksum_out))
     return fail(TS_E_ALIAS, "dev_out overlaps the array being reduced");
-  const uint32_t np = reduce_parts(x->n);
+  const uint32_t np = checksum_parts(x->dtype, x->n);
   if (np > kNoallocParts)
     return fail(TS_E_SHAPE, "the reduction needs %u parts; the fixed array holds %u", np, kNoallocParts);
   CsPart* parts = nullptr;

@@ -5,6 +5,7 @@
 // (Section 3.2, Listing 1's bulk_construct; Section 4.2).  The uniform fill
 // is SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) evaluated at a counter,
 // so any element can be regenerated alone.
+#include <cmath>
 #include <mutex>
 
 #include "ts_device.hpp"
@@ -161,47 +162,87 @@ __device__ __forceinline__ VecRange<T> vec_range(const T* x, uint64_t lo, uint64
   return VecRange<T>{head, v0, nvec, v0 + nvec * E};
 }
 
-// Pass 1: workgroup g reduces the contiguous range [g*n/P, (g+1)*n/P): its
-// head and tail elements one per lane, the 16-byte vectors between them
-// with nontemporal loads, four in flight per lane.  Each lane folds its
-// elements in ascending order, so the tree depends only on n and on the
-// array's address modulo 16 bytes.
-template <int DT>
+// Pass 1: the 16-byte vectors of x form chunks of kSumChunk vectors (four per
+// lane); workgroup g of G folds chunks g, g + G, g + 2G, ... with nontemporal
+// loads, the next chunk's loads issued before the current chunk is folded.
+// Workgroup 0 also folds the element-wise head before the first vector and
+// the tail after the last.  Each lane folds its elements in ascending order,
+// so the tree depends only on n, the storage type and the array's address
+// modulo 16 bytes.  An element is a mismatch when its binary64 bits differ
+// from expected's, two NaNs agreeing (differs); EM, chosen per launch from
+// `expected`, gives that test its cheapest exact form: kExpNan (expected is
+// a NaN: the element is not one), kExpZero (expected is +0 or -0: compare the
+// bits) or kExpValue (any other expected: compare the values, since a
+// nonzero binary64 value has one encoding and a NaN compares unequal).
+enum : int { kExpValue = 0, kExpNan = 1, kExpZero = 2 };
+template <int DT, int EM>
 __global__ __launch_bounds__(256) void checksum_pass1(const void* xv, uint64_t n, double expected,
                                                       CsPart* parts, uint32_t nparts) {
   using T = typename Fmt<DT>::T;
   using R = typename Raw<16>::type;
   constexpr uint32_t E = 16 / sizeof(T);
   const T* x = static_cast<const T*>(xv);
-  const uint64_t lo = static_cast<uint64_t>(blockIdx.x) * n / nparts;
-  const uint64_t hi = static_cast<uint64_t>(blockIdx.x + 1) * n / nparts;
+  const uint32_t t = threadIdx.x;
   CsPart acc{0.0, 0.0, __builtin_nan(""), 0ull};
+  uint32_t mism = 0;  // a lane folds far fewer than 2^32 elements
   auto add = [&](double v) {
     const double dv = fabs(v - expected);
     acc.sum += v;
     acc.absdev += dv;
     acc.maxdev = fmax(acc.maxdev, dv);
-    acc.mism += differs(v, expected) ? 1ull : 0ull;
+    bool d;
+    if constexpr (EM == kExpNan) d = !__builtin_isnan(v);
+    else if constexpr (EM == kExpZero) d = __builtin_bit_cast(uint64_t, v) != __builtin_bit_cast(uint64_t, expected);
+    else d = v != expected;
+    mism += d ? 1u : 0u;
   };
   auto fold = [&](R r) {
-    const Splat<T> v = __builtin_bit_cast(Splat<T>, r);
+    if constexpr (sizeof(T) == 2) {
+      // Two elements per 32-bit word, the lower address in the low half.
 #pragma unroll
-    for (uint32_t e = 0; e < E; ++e) add(to_f64<DT>(v.e[e]));
+      for (uint32_t w = 0; w < 4; ++w) {
+        const uint32_t b = r[w];
+        if constexpr (DT == DT_BF16) {
+          add(static_cast<double>(__builtin_bit_cast(float, b << 16)));
+          add(static_cast<double>(__builtin_bit_cast(float, b & 0xffff0000u)));
+        } else {
+          add(to_f64<DT>(static_cast<uint16_t>(b)));
+          add(to_f64<DT>(static_cast<uint16_t>(b >> 16)));
+        }
+      }
+    } else {
+      const Splat<T> v = __builtin_bit_cast(Splat<T>, r);
+#pragma unroll
+      for (uint32_t e = 0; e < E; ++e) add(to_f64<DT>(v.e[e]));
+    }
   };
-  const VecRange<T> vr = vec_range(x, lo, hi);
-  if (threadIdx.x < vr.head) add(to_f64<DT>(x[lo + threadIdx.x]));
+  const VecRange<T> vr = vec_range(x, 0, n);
+  if (blockIdx.x == 0 && t < vr.head) add(to_f64<DT>(x[t]));
   const R* xr = reinterpret_cast<const R*>(x + vr.v0);
-  uint64_t k = threadIdx.x;
-  for (; k + 3 * kReduceBlock < vr.nvec; k += 4 * kReduceBlock) {
-    const R r0 = __builtin_nontemporal_load(xr + k), r1 = __builtin_nontemporal_load(xr + k + kReduceBlock);
-    const R r2 = __builtin_nontemporal_load(xr + k + 2 * kReduceBlock);
-    const R r3 = __builtin_nontemporal_load(xr + k + 3 * kReduceBlock);
-    fold(r0), fold(r1), fold(r2), fold(r3);
+  const uint64_t nvec = vr.nvec, step = static_cast<uint64_t>(nparts) * kSumChunk;
+  uint64_t base = static_cast<uint64_t>(blockIdx.x) * kSumChunk;
+  if (base + kSumChunk <= nvec) {
+    R cur[kSumUnroll];
+#pragma unroll
+    for (uint32_t u = 0; u < kSumUnroll; ++u) cur[u] = __builtin_nontemporal_load(xr + base + u * kReduceBlock + t);
+    for (base += step; base + kSumChunk <= nvec; base += step) {
+      R nxt[kSumUnroll];
+#pragma unroll
+      for (uint32_t u = 0; u < kSumUnroll; ++u) nxt[u] = __builtin_nontemporal_load(xr + base + u * kReduceBlock + t);
+#pragma unroll
+      for (uint32_t u = 0; u < kSumUnroll; ++u) fold(cur[u]);
+#pragma unroll
+      for (uint32_t u = 0; u < kSumUnroll; ++u) cur[u] = nxt[u];
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kSumUnroll; ++u) fold(cur[u]);
   }
-  for (; k < vr.nvec; k += kReduceBlock) fold(__builtin_nontemporal_load(xr + k));
-  if (threadIdx.x < hi - vr.t0) add(to_f64<DT>(x[vr.t0 + threadIdx.x]));
+  // The chunk cut short by the end of the vectors, if it is this workgroup's.
+  for (uint64_t k = base + t; k < nvec; k += kReduceBlock) fold(__builtin_nontemporal_load(xr + k));
+  if (blockIdx.x == 0 && t < n - vr.t0) add(to_f64<DT>(x[vr.t0 + t]));
+  acc.mism = mism;
   const CsPart r = block_reduce(acc);
-  if (threadIdx.x == 0) parts[blockIdx.x] = r;
+  if (t == 0) parts[blockIdx.x] = r;
 }
 
 // Pass 2: one workgroup folds the parts in a fixed order.
@@ -218,10 +259,10 @@ __global__ __launch_bounds__(256) void reduce_pass2(const CsPart* parts, uint32_
   if (threadIdx.x == 0) *out = r;
 }
 
-// Count of elements whose bits differ between x and r (two NaNs agree), over
-// the same ranges as checksum_pass1.  When x and r share their address
-// modulo 16 bytes the vectors of both are read 16 bytes at a time;
-// otherwise every element is read alone.
+// Count of elements whose bits differ between x and r (two NaNs agree):
+// workgroup g of P counts the contiguous range [g*n/P, (g+1)*n/P).  When x
+// and r share their address modulo 16 bytes the vectors of both are read 16
+// bytes at a time; otherwise every element is read alone.
 template <int DT>
 __global__ __launch_bounds__(256) void mismatch_pass1(const void* xv, const void* rv, uint64_t n,
                                                       CsPart* parts, uint32_t nparts) {
@@ -407,6 +448,21 @@ uint32_t reduce_parts(uint64_t n) {
   return static_cast<uint32_t>(p < 1 ? 1 : (p > kReduceMaxParts ? kReduceMaxParts : p));
 }
 
+uint32_t checksum_parts(int dt, uint64_t n) {
+  const uint64_t p = (n * dtype_size(dt) + kSumChunk * 16 - 1) / (kSumChunk * 16);
+  return static_cast<uint32_t>(p < 1 ? 1 : (p > kSumMaxParts ? kSumMaxParts : p));
+}
+
+// LDS each first-pass workgroup of the checksum holds (its tree's 8 KiB plus
+// an unused dynamic part), which sets how many share a CU's 160 KiB: two for
+// binary64 and binary32, three for the 16-bit formats, whose fold spends more
+// instructions per byte.  With few resident waves the next chunk's loads
+// keep enough bytes in flight.
+static uint32_t checksum_dynamic_lds(int dt) {
+  constexpr uint32_t kTree = 4 * kReduceBlock * 8;
+  return (dt == DT_F64 || dt == DT_F32 ? 64 * 1024 : 48 * 1024) - kTree;
+}
+
 // The batched fill for storage format dt, constant (U false) or uniform.
 #define TS_BY_FORMAT_U(dt, U, ...)                                                             \
   switch (dt) {                                                                                \
@@ -417,6 +473,16 @@ uint32_t reduce_parts(uint64_t n) {
     default: return hipErrorInvalidValue;                                                      \
   }                                                                                            \
   return hipGetLastError();
+
+// The checksum's first pass for storage format dt; EM as the kernel's.
+#define TS_CHECKSUM_BY_FORMAT(dt, EM, ...)                                                   \
+  switch (dt) {                                                                                \
+    case DT_F64: hipLaunchKernelGGL((checksum_pass1<DT_F64, EM>), __VA_ARGS__); break;       \
+    case DT_F32: hipLaunchKernelGGL((checksum_pass1<DT_F32, EM>), __VA_ARGS__); break;       \
+    case DT_BF16: hipLaunchKernelGGL((checksum_pass1<DT_BF16, EM>), __VA_ARGS__); break;     \
+    case DT_F16: hipLaunchKernelGGL((checksum_pass1<DT_F16, EM>), __VA_ARGS__); break;       \
+    default: return hipErrorInvalidValue;                                                      \
+  }
 
 #define TS_BY_FORMAT(dt, KERNEL, ...)                                                          \
   switch (dt) {                                                                                \
@@ -459,13 +525,15 @@ hipError_t launch_fill_uniform(int dt, void* p, uint64_t n, uint64_t seed, uint6
 
 hipError_t launch_checksum_to(int dt, const void* x, uint64_t n, double expected, CsPart* parts, CsPart* out,
                               hipStream_t s) {
-  const uint32_t np = reduce_parts(n);
-  switch (dt) {
-    case DT_F64: hipLaunchKernelGGL(checksum_pass1<DT_F64>, dim3(np), dim3(kReduceBlock), 0, s, x, n, expected, parts, np); break;
-    case DT_F32: hipLaunchKernelGGL(checksum_pass1<DT_F32>, dim3(np), dim3(kReduceBlock), 0, s, x, n, expected, parts, np); break;
-    case DT_BF16: hipLaunchKernelGGL(checksum_pass1<DT_BF16>, dim3(np), dim3(kReduceBlock), 0, s, x, n, expected, parts, np); break;
-    case DT_F16: hipLaunchKernelGGL(checksum_pass1<DT_F16>, dim3(np), dim3(kReduceBlock), 0, s, x, n, expected, parts, np); break;
-    default: return hipErrorInvalidValue;
+  const uint32_t np = checksum_parts(dt, n);
+  const uint32_t lds = checksum_dynamic_lds(dt);
+  const dim3 g(np), b(kReduceBlock);
+  if (std::isnan(expected)) {
+    TS_CHECKSUM_BY_FORMAT(dt, kExpNan, g, b, lds, s, x, n, expected, parts, np)
+  } else if (expected == 0.0) {
+    TS_CHECKSUM_BY_FORMAT(dt, kExpZero, g, b, lds, s, x, n, expected, parts, np)
+  } else {
+    TS_CHECKSUM_BY_FORMAT(dt, kExpValue, g, b, lds, s, x, n, expected, parts, np)
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -70,13 +70,20 @@ struct CsPart {
 // bytes), never on tuning.
 constexpr uint32_t kReduceBlock = 256;
 constexpr uint32_t kReduceMaxParts = 8192;
+// Parts of the mismatch count: one per 2048 elements, at most kReduceMaxParts.
 uint32_t reduce_parts(uint64_t n);
+// The checksum's first pass reads chunks of kSumChunk 16-byte vectors (four
+// per lane); one part per chunk, at most kSumMaxParts.
+constexpr uint32_t kSumUnroll = 4;
+constexpr uint64_t kSumChunk = static_cast<uint64_t>(kReduceBlock) * kSumUnroll;
+constexpr uint32_t kSumMaxParts = 4096;
+uint32_t checksum_parts(int dt, uint64_t n);
 // Device scratch a target needs for one reduction: parts plus the result.
 constexpr size_t kReduceScratchBytes = (kReduceMaxParts + 1) * sizeof(CsPart);
 
 // Parts held by the fixed per-GPU array of the allocation-free checksum: as
-// many as a reduction of any length uses, so it never limits n.
-constexpr uint32_t kNoallocParts = kReduceMaxParts;
+// many as a checksum of any length uses, so it never limits n.
+constexpr uint32_t kNoallocParts = kSumMaxParts;
 // Devices whose fixed array's address is cached.
 constexpr int kMaxDevices = 64;
 

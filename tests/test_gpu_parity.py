@@ -245,6 +245,96 @@ def test_checksum_against_oracle(env, dtype):
     assert ts.checksum(tgt, X, expected) == cs
 
 
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+def test_checksum_many_chunks_per_workgroup(env, dtype):
+    """Above 4096 chunks of 16 KiB (64 MiB) every first-pass workgroup folds
+    several chunks, the next one loaded while the current one is folded; a
+    size two and a half times that, not a whole number of chunks, and an
+    element offset that gives a head and a tail, give the oracle's counts
+    and maximum exactly and its sums within the summation bound."""
+    ts, torch, tgt = env
+    E = ELEMS_PER_16B[dtype]
+    es = 16 // E
+    odt = oracle.DTYPES[dtype]
+    n = (4096 * 16384 * 2 + 3 * 16384 + 100) // es + 3
+    x = tsgen.uniform_array(21, 0, n, dtype)
+    w = oracle.widen_f64(odt, x)
+    expected = float(w[n // 2])
+    ref = oracle.checksum(odt, x, expected)
+    bound_sum = 2 * n * 2.0 ** -53 * float(np.abs(w).sum())
+    bound_dev = 2 * n * 2.0 ** -53 * float(np.abs(w - expected).sum())
+    del w
+    for off in (0, E - 1):
+        say(f"[checksum many chunks {dtype} n={n} offset={off}]")
+        X = device_array(ts, torch, tgt, x, dtype, off)
+        cs = ts.checksum(tgt, X, expected)
+        assert cs["mismatches"] == ref.mismatches
+        assert cs["max_abs_dev"] == ref.max_abs_dev
+        assert abs(cs["sum"] - ref.sum) <= bound_sum
+        assert abs(cs["abs_dev_sum"] - ref.abs_dev_sum) <= bound_dev
+        del X
+        torch.cuda.empty_cache()
+
+
+SPECIAL_BITS = {  # +0, -0, +inf, -inf, two NaN payloads, the smallest subnormal
+    "f64": [0x0, 0x8000000000000000, 0x7FF0000000000000, 0xFFF0000000000000,
+            0x7FF8000000000001, 0xFFF8000000000ABC, 0x1],
+    "f32": [0x0, 0x80000000, 0x7F800000, 0xFF800000, 0x7FC00001, 0xFFC00ABC, 0x1],
+    "bf16": [0x0, 0x8000, 0x7F80, 0xFF80, 0x7FC1, 0xFFC5, 0x1],
+    "f16": [0x0, 0x8000, 0x7C00, 0xFC00, 0x7E01, 0xFE05, 0x1],
+}
+
+
+def _same_or_both_nan(a: float, b: float) -> bool:
+    return (np.isnan(a) and np.isnan(b)) or a == b
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+def test_checksum_expected_values(env, dtype):
+    """The mismatch test takes one form per expected value: a NaN (elements
+    that are NaNs agree, whatever their payloads), +0 or -0 (bits compared,
+    so the other zero differs) and any other value (values compared).  An
+    array holding signed zeros, infinities, NaNs and subnormals at its head,
+    its tail and chunk edges, checked against each kind of expected value,
+    gives the oracle's counts and maximum exactly; sums that are not finite
+    match exactly, finite ones within the summation bound."""
+    ts, torch, tgt = env
+    E = ELEMS_PER_16B[dtype]
+    odt = oracle.DTYPES[dtype]
+    chunk = 16384 // (16 // E)  # elements in one 16 KiB chunk
+    n = 3 * chunk + 5
+    base = tsgen.uniform_array(23, 0, n, dtype)
+    specials = np.array(SPECIAL_BITS[dtype], dtype=UINT_OF[dtype])
+    spots = [0, 1, 2, chunk - 1, chunk, chunk + 1, 2 * chunk + 3, n - 7, n - 2, n - 1]
+    widened = oracle.widen_f64(odt, base)
+    expecteds = [0.0, -0.0, float("nan"), -float("inf"), float("inf"), float(widened[n // 2]), 0.1, 1.5]
+    for variant in range(2):
+        x = base.copy()
+        bits = x.view(UINT_OF[dtype])
+        for k, j in enumerate(spots):
+            bits[j] = specials[(k + variant) % len(specials)]
+        if variant == 1:  # every zero, infinity and NaN kind also in the middle of chunks
+            bits[chunk // 2: chunk // 2 + len(specials)] = specials
+        w = oracle.widen_f64(odt, x)
+        finite = np.isfinite(w)
+        for expected in expecteds:
+            ref = oracle.checksum(odt, x, expected)
+            for off in (0, E - 1):
+                say(f"[checksum expected {dtype} variant={variant} expected={expected!r} offset={off}]")
+                X = device_array(ts, torch, tgt, x, dtype, off)
+                cs = ts.checksum(tgt, X, expected)
+                assert cs["mismatches"] == ref.mismatches, (expected, off)
+                assert _same_or_both_nan(cs["max_abs_dev"], ref.max_abs_dev), (expected, off)
+                for key, got, want, mag in (
+                        ("sum", cs["sum"], ref.sum, np.abs(w[finite]).sum()),
+                        ("abs_dev_sum", cs["abs_dev_sum"], ref.abs_dev_sum,
+                         np.abs(w[finite] - expected).sum() if np.isfinite(expected) else 0.0)):
+                    if np.isfinite(want):
+                        assert abs(got - want) <= 2 * n * 2.0 ** -53 * float(mag), (key, expected, off)
+                    else:
+                        assert _same_or_both_nan(got, want), (key, expected, off, got, want)
+
 def test_mismatch_count(env):
     ts, torch, tgt = env
     n = 300001
@@ -263,12 +353,13 @@ ELEMS_PER_16B = {"f64": 2, "f32": 4, "bf16": 8, "f16": 8}
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
 def test_checksum_and_mismatch_layouts(env, dtype):
-    """The reductions read each part as a head up to a 16-byte boundary,
-    16-byte vectors and a tail: every element offset within 16 bytes, sizes
-    below one vector, around one part (2048 elements) and across several
-    parts give the oracle's counts and maximum exactly and its sums within
-    the summation bound; the mismatch count also takes operands whose
-    offsets differ modulo 16 bytes (element-wise path)."""
+    """The reductions read a head up to a 16-byte boundary, 16-byte vectors
+    and a tail: every element offset within 16 bytes, sizes below one
+    vector, around one part of the mismatch count (2048 elements) and across
+    several of the checksum's 16 KiB chunks give the oracle's counts and
+    maximum exactly and its sums within the summation bound; the mismatch
+    count also takes operands whose offsets differ modulo 16 bytes
+    (element-wise path)."""
     ts, torch, tgt = env
     E = ELEMS_PER_16B[dtype]
     odt = oracle.DTYPES[dtype]
