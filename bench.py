@@ -25,7 +25,8 @@ N = 2^28 per array; a size/alignment sweep from 2^16 to 2^29 elements (L2,
 Infinity Cache and HBM regimes); launch overhead at small sizes (eager
 calls against HIP graphs); and library comparators on the same traffic (the
 runtime's device copy, torch's elementwise b + q*c); and the triad as a
-run-time-compiled generic transform.  --legs picks a subset.  The CPU-baseline leg times the oracle
+run-time-compiled generic transform; and the validation kernels (constant
+fill, checksum) on 1 GiB of each storage type.  --legs picks a subset.  The CPU-baseline leg times the oracle
 on host cores.
 """
 from __future__ import annotations
@@ -47,7 +48,7 @@ METRIC = "STREAM Triad/Copy GB/s and % of HBM peak, FP64 N=2^27; batched vs plai
 PEAK_GBPS = 8000.0
 OPS = ("copy", "scale", "add", "triad")
 EXTRA_LEGS = ("calibration", "ceiling", "batched", "reduced_precision", "sweep", "launch_overhead", "comparators",
-              "transform")
+              "transform", "validation")
 PROFILE_PMC = os.path.join(ROOT, "profiles", "stream_f64_n2p27_pmc.md")
 
 
@@ -569,6 +570,36 @@ def transform_leg(ts, tgt, n, reps=20):
     return out
 
 
+def validation_leg(ts, tgt, nbytes=1 << 30, reps=20):
+    """The validation kernels on one array of `nbytes` per storage type: the
+    constant fill (write only), launch by launch, and the checksum call
+    (both passes and the copy of its 32-byte result to the host; the call
+    waits for it), each after untimed calls.  GB/s of the array's bytes."""
+    out = {}
+    for dt in ("f64", "f32", "bf16", "f16"):
+        n = nbytes // ts.ELEM_SIZE[dt]
+        X = ts.Array.alloc(tgt, dt, n)
+
+        def fill():
+            X.fill(1.0)
+
+        def check():
+            ts.checksum(tgt, X, 1.0)
+
+        settle(fill, SETTLE_LAUNCHES // 2)
+        tf = timed_launches(ts, tgt, fill, reps)
+        settle(check, 10)
+        tc = timed_launches(ts, tgt, check, reps)
+        cs = ts.checksum(tgt, X, 1.0)
+        X.free()
+        out[dt] = {"n": n,
+                   "fill_const_avg_GBps": round(nbytes / (sum(tf) / len(tf)) / 1e6, 1),
+                   "checksum_call_avg_us": round(1e3 * sum(tc) / len(tc), 1),
+                   "checksum_call_avg_GBps": round(nbytes / (sum(tc) / len(tc)) / 1e6, 1),
+                   "valid": cs["mismatches"] == 0 and cs["sum"] == float(n)}
+    return out
+
+
 def comparator_leg(ts, torch, n, reps=20):
     """The same traffic through library kernels, for context, on N binary64
     elements per array: the runtime's device-to-device copy (hipMemcpyAsync
@@ -894,7 +925,8 @@ def main():
                          ("sweep", lambda: sweep_leg(ts, tgt)),
                          ("launch_overhead", lambda: overhead_leg(ts, torch, tgt)),
                          ("comparators", lambda: comparator_leg(ts, torch, a.n)),
-                         ("transform", lambda: transform_leg(ts, tgt, a.n))):
+                         ("transform", lambda: transform_leg(ts, tgt, a.n)),
+                         ("validation", lambda: validation_leg(ts, tgt))):
             if a.legs and name not in a.legs:
                 continue
             log(f"{name} leg")

@@ -3,12 +3,13 @@
     python paper_2206_06302_amd/profiling.py run --raw DIR        # on a machine with the GPU
     python paper_2206_06302_amd/profiling.py summarize --raw DIR  # anywhere: rewrites profiles/*.md
 
-`run` starts seven rocprofv3 runs, each a process of its own with the program
+`run` starts eight rocprofv3 runs, each a process of its own with the program
 directly after `--`, from /tmp with TMPDIR=/tmp:
 
   headline trace   --kernel-trace --stats of bench.py --quick --no-cpu --warmup 1 --steps 20
   batched trace    --kernel-trace --stats of bench.py --no-cpu --legs batched --warmup 1 --steps 20
   reduced trace    --kernel-trace         of bench.py --no-cpu --legs reduced_precision --warmup 1 --steps 3
+  validation trace --kernel-trace         of bench.py --no-cpu --legs validation --warmup 1 --steps 3
   fetch counters   --pmc FETCH_SIZE       of bench.py --no-cpu --legs calibration,batched --no-per-instance
                                           --warmup 1 --steps 3
   write counters   --pmc WRITE_SIZE       of the same command
@@ -17,8 +18,8 @@ directly after `--`, from /tmp with TMPDIR=/tmp:
 
 `summarize` turns the raw CSV files into short markdown summaries: the
 per-kernel trace of the headline, of the batched leg (with the bench's own
-event timings from the same runs beside rocprof's) and of the maps on
-reduced-precision storage, and the HBM traffic per launch of the four
+event timings from the same runs beside rocprof's), of the maps on
+reduced-precision storage and of the validation kernels per storage type, and the HBM traffic per launch of the four
 headline maps and the four batched maps.
 
 HBM bytes come from the L2-to-memory request counts: on gfx950 every read
@@ -103,6 +104,10 @@ def runs(raw: str) -> list[tuple[str, list[str], str]]:
                            os.path.join(raw, "trace_reduced"), "-o", "run", "--",
                            *_bench("--no-cpu", "--legs", "reduced_precision", "--warmup", "1", "--steps", "3")],
          os.path.join(raw, "trace_reduced.json")),
+        ("validation trace", ["rocprofv3", "--kernel-trace", "--output-format", "csv", "-d",
+                              os.path.join(raw, "trace_validation"), "-o", "run", "--",
+                              *_bench("--no-cpu", "--legs", "validation", "--warmup", "1", "--steps", "3")],
+         os.path.join(raw, "trace_validation.json")),
     ]
     for name, sub, counters in PMC_RUNS:
         out.append((name, ["rocprofv3", "--pmc", *counters, "--output-format", "csv", "-d", os.path.join(raw, sub),
@@ -207,6 +212,57 @@ def _reduced_summary(raw, cmd):
     return L + [""]
 
 
+def _validation_summary(raw, cmd):
+    """Per storage type, the checksum's two passes and the constant fill over
+    the validation leg's 1 GiB arrays (the largest grid of each kernel and
+    type), average durations from the per-dispatch trace."""
+    nbytes = 1 << 30
+    rows = {}
+    for f in glob.glob(os.path.join(raw, "trace_validation", "**", "*kernel_trace.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            name = r["Kernel_Name"]
+            m = re.search(r"(checksum_pass1|fill_const_kernel)<(\d+)", name)
+            if m:
+                key = (int(m.group(2)), m.group(1))
+            elif "reduce_pass2" in name:
+                key = (None, "reduce_pass2")
+            else:
+                continue
+            grid = int(r["Grid_Size_X"])
+            dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            rows.setdefault(key, {}).setdefault(grid, []).append(dur)
+    bj = _bench_json(os.path.join(raw, "trace_validation.json")).get("validation", {})
+    L = ["# Kernel trace: validation kernels over 1 GiB per storage type (bench validation leg)", "",
+         "Made by `python paper_2206_06302_amd/profiling.py run` (then `summarize`); the run:", "",
+         "```", "export TMPDIR=/tmp; cd /tmp", cmd, "```", "",
+         "The checksum's first pass (grid-strided 16 KiB chunks, one workgroup part each) and the constant",
+         "fill over one array of 2^30 bytes per storage type: the launches of the largest grid, their",
+         "average duration from the trace, and bytes / that duration.  The bench's own figure for a whole",
+         "checksum call (both passes, the result's copy to the host and the wait for it) is beside it.",
+         "The binary64 rows also hold the headline's own validation calls on its 2^27-element arrays,",
+         "which are the same size.  The first pass's workgroups of 256 lanes reserve 64 KiB of LDS for",
+         "binary64 and binary32 and 48 KiB for the 16-bit types, which leaves room for two or three on a",
+         "CU (the trace lists only the 8 KiB the kernel declares).", "",
+         "| storage | kernel | grid (workgroups) | dispatches | avg µs | GB/s (avg) | bench GB/s |",
+         "|---|---|---|---|---|---|---|"]
+    for dt in range(4):
+        for kern, bench_key, wg in (("checksum_pass1", "checksum_call_avg_GBps", 256),
+                                    ("fill_const_kernel", "fill_const_avg_GBps", 256)):
+            if (dt, kern) not in rows:
+                continue
+            grid = max(rows[(dt, kern)])
+            launches = rows[(dt, kern)][grid]
+            avg = sum(launches) / len(launches)
+            ev = bj.get(DT_NAMES[dt], {}).get(bench_key, "")
+            L.append(f"| {DT_NAMES[dt]} | `{kern}` | {grid // wg} | {len(launches)} | "
+                     f"{avg / 1e3:.1f} | {nbytes / avg:.1f} | {ev} |")
+    if (None, "reduce_pass2") in rows:
+        p2 = [d for v in rows[(None, "reduce_pass2")].values() for d in v]
+        L += ["", f"The second pass (one workgroup folding the parts in a fixed order) averages "
+              f"{sum(p2) / len(p2) / 1e3:.1f} µs over {len(p2)} dispatches."]
+    return L + [""]
+
+
 def _plain_name(name):
     m = re.search(r"stream_kernel<(\d+), (\d+), (\d+), (\d+), (\w+), (\w+)>", name)
     if not m:
@@ -217,7 +273,7 @@ def _plain_name(name):
 
 
 def _short(name):
-    m = re.search(r"(\w+_kernel(?:<[^>]*>)?|__amd_rocclr_\w+|reduce_pass2|\w+_pass1<\d+>)", name)
+    m = re.search(r"(\w+_kernel(?:<[^>]*>)?|__amd_rocclr_\w+|reduce_pass2|\w+_pass1<[^>]*>)", name)
     return m.group(1) if m else name[:60]
 
 
@@ -418,6 +474,9 @@ def summarize(raw: str, out: str = PROFILES) -> None:
     # reduced-precision trace
     L = _reduced_summary(raw, _command(cmds["reduced trace"], raw))
     open(os.path.join(out, "stream_reduced_n2p28_kernel_trace.md"), "w").write("\n".join(L))
+    if os.path.isdir(os.path.join(raw, "trace_validation")):
+        L = _validation_summary(raw, _command(cmds["validation trace"], raw))
+        open(os.path.join(out, "checksum_fill_1gib_kernel_trace.md"), "w").write("\n".join(L))
 
     # batched counters
     bj = _bench_json(os.path.join(raw, "pmc_rdreq.json"))["batched"]

@@ -129,8 +129,8 @@ def test_profiler_runs_follow_the_rules():
                       for c in counters)
             assert 1 <= len(counters) and tcc <= 4, counters
             assert not {"--kernel-trace", "--sys-trace", "--runtime-trace", "-s", "-r"} & set(cmd[:cmd.index("--")])
-    assert names == ["headline trace", "batched trace", "reduced trace", "fetch counters", "write counters",
-                     "read requests", "write requests"]
+    assert names == ["headline trace", "batched trace", "reduced trace", "validation trace", "fetch counters",
+                     "write counters", "read requests", "write requests"]
 
 
 def _load_profiling():
@@ -224,6 +224,20 @@ def _synthetic_raw(raw):
     _write_csv(os.path.join(raw, "trace_reduced", "run_kernel_trace.csv"), trace, rows)
     with open(os.path.join(raw, "trace_reduced.json"), "w") as f:
         f.write(json.dumps({"reduced_precision": {"f32": {"triad": {"GBps": 1.5}}}}) + "\n")
+
+    trace = ["Kernel_Name", "Grid_Size_X", "Start_Timestamp", "End_Timestamp", "LDS_Block_Size"]
+    cs = "void ts::(anonymous namespace)::checksum_pass1<{dt}, 0>(void const*, unsigned long, double, ts::CsPart*, unsigned int)"
+    fill = "void ts::(anonymous namespace)::fill_const_kernel<{dt}>(void*, unsigned long, double, unsigned long, unsigned long)"
+    rows = []
+    for dt in range(4):
+        # 2^30 bytes in 100 µs (checksum) and 200 µs (fill); small launches that must be left out
+        rows += [[cs.format(dt=dt), 4096 * 256, 0, 100000, 65536]] * 3 + [[cs.format(dt=dt), 256, 0, 1, 65536]]
+        rows += [[fill.format(dt=dt), 262144 * 256, 0, 200000, 0]] * 2 + [[fill.format(dt=dt), 256, 0, 1, 0]]
+    rows += [["void ts::(anonymous namespace)::reduce_pass2(ts::CsPart const*, unsigned int, ts::CsPart*)", 256, 0,
+              5000, 8192]] * 4
+    _write_csv(os.path.join(raw, "trace_validation", "run_kernel_trace.csv"), trace, rows)
+    with open(os.path.join(raw, "trace_validation.json"), "w") as f:
+        f.write(json.dumps({"validation": {"bf16": {"checksum_call_avg_GBps": 2.5, "fill_const_avg_GBps": 3.5}}}) + "\n")
     return prof
 
 
@@ -235,6 +249,7 @@ def test_profile_summaries_from_known_counts(tmp_path, monkeypatch):
     prof = _synthetic_raw(raw)
     prof.summarize(raw, out)
     assert sorted(os.listdir(out)) == ["batched_f64_4096_kernel_trace.md", "batched_f64_4096_pmc.md",
+                                       "checksum_fill_1gib_kernel_trace.md",
                                        "stream_f64_n2p27_kernel_trace.md", "stream_f64_n2p27_pmc.md",
                                        "stream_reduced_n2p28_kernel_trace.md"]
     read = lambda f: open(os.path.join(out, f)).read()  # noqa: E731
@@ -270,6 +285,19 @@ def test_profile_summaries_from_known_counts(tmp_path, monkeypatch):
     # elements per second against binary64: 2x for 4-byte storage, 4x for 2-byte storage
     assert rows["f32"][8].strip() == "2.00" and rows["bf16"][8].strip() == "4.00"
     assert rows["f32"][9].strip() == "1.5"
+
+    val = read("checksum_fill_1gib_kernel_trace.md")
+    rows = [ln.split("|") for ln in val.splitlines() if ln.startswith("| ") and "`" in ln]
+    assert len(rows) == 8
+    for r in rows:  # the small-grid launches are left out
+        if "checksum_pass1" in r[2]:
+            assert [c.strip() for c in r[3:7]] == ["4096", "3", "100.0", "10737.4"], r
+        else:
+            assert [c.strip() for c in r[3:7]] == ["262144", "2", "200.0", "5368.7"], r
+    bf16 = [r for r in rows if r[1].strip() == "bf16"]
+    assert [r[7].strip() for r in bf16] == ["2.5", "3.5"]
+    assert "averages 5.0 µs over 4 dispatches" in val
+    assert "--legs validation" in val
 
     monkeypatch.setattr(bench, "PROFILE_PMC", os.path.join(out, "stream_f64_n2p27_pmc.md"))
     assert bench.committed_traffic() == 3.221225e9

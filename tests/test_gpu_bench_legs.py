@@ -53,3 +53,13 @@ def test_reduced_and_calibration_legs(env):
     c = bench.calibration_leg(ts, tgt, 1 << 20, reps=2)
     assert c["read_1r"]["bytes_read"] == 8 << 20 and c["write_1w"]["bytes_written"] == 8 << 20
     assert all(c[k]["avg_GBps"] > 0 for k in ("read_1r", "write_1w", "copy_1r1w"))
+
+
+def test_validation_leg(env):
+    bench, ts, torch, tgt = env
+    v = bench.validation_leg(ts, tgt, nbytes=(8 << 20) + 48, reps=2)
+    assert set(v) == {"f64", "f32", "bf16", "f16"}
+    for dt, r in v.items():
+        assert r["valid"], dt
+        assert r["n"] == ((8 << 20) + 48) // ts.ELEM_SIZE[dt]
+        assert r["fill_const_avg_GBps"] > 0 and r["checksum_call_avg_GBps"] > 0 and r["checksum_call_avg_us"] > 0
