@@ -60,26 +60,40 @@ struct Splat {
   T e[16 / sizeof(T)];
 };
 
-// Elements [0, head) and those after the `nvec` 16-byte vectors are stored
-// one by one; the vectors in between with 16-byte nontemporal stores.
+// 8 bytes of one repeated element.
+template <class T>
+struct Splat8 {
+  T e[8 / sizeof(T)];
+};
+
+// Elements [0, head) and those after the `nwords` 8-byte words are stored one
+// by one.  The words in between go in chunks of kFillChunkWords (4 KiB), chunk
+// c to workgroup c modulo the grid: each of its four waves stores one
+// contiguous KiB with two 8-byte nontemporal stores per lane.
 template <int DT>
 __global__ __launch_bounds__(256) void fill_const_kernel(void* p, uint64_t n, double value, uint64_t head,
-                                                         uint64_t nvec) {
+                                                         uint64_t nwords) {
   using T = typename Fmt<DT>::T;
-  using R = typename Raw<16>::type;
-  constexpr uint64_t E = 16 / sizeof(T);
+  using W = typename Raw<8>::type;
+  constexpr uint64_t E = 8 / sizeof(T);
   T* d = static_cast<T*>(p);
   const T v = from_f64<DT>(value);
-  const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint32_t t = threadIdx.x;
+  const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + t;
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t j = g; j < head; j += stride) d[j] = v;
-  for (uint64_t j = head + nvec * E + g; j < n; j += stride) d[j] = v;
-  Splat<T> s;
+  for (uint64_t j = head + nwords * E + g; j < n; j += stride) d[j] = v;
+  Splat8<T> s;
 #pragma unroll
   for (uint64_t e = 0; e < E; ++e) s.e[e] = v;
-  const R r = __builtin_bit_cast(R, s);
-  R* dv = reinterpret_cast<R*>(d + head);
-  for (uint64_t k = g; k < nvec; k += stride) __builtin_nontemporal_store(r, dv + k);
+  const W r = __builtin_bit_cast(W, s);
+  W* dw = reinterpret_cast<W*>(d + head);
+  const uint64_t lane_word = (t >> 6) * 128 + (t & 63);
+  for (uint64_t c = blockIdx.x; c * kFillChunkWords < nwords; c += gridDim.x) {
+    const uint64_t i = c * kFillChunkWords + lane_word;
+    if (i < nwords) __builtin_nontemporal_store(r, dw + i);
+    if (i + 64 < nwords) __builtin_nontemporal_store(r, dw + i + 64);
+  }
 }
 
 // lo + w * u01 with u01 = (h >> 11) * 2^-53 in [0, 1): a product and a sum,
@@ -507,11 +521,20 @@ static void vector_split(int dt, const void* p, uint64_t n, uint64_t* head, uint
   *grid = g < 1 ? 1 : (g > (1u << 20) ? (1u << 20) : g);
 }
 
+// LDS a constant-fill workgroup reserves without using it, so that four share
+// a CU: writes alone stream fastest with fewer resident waves.
+constexpr uint32_t kFillLds = 40 * 1024;
+
 hipError_t launch_fill_const(int dt, void* p, uint64_t n, double value, hipStream_t s) {
-  uint64_t head, nvec, grid;
-  vector_split(dt, p, n, &head, &nvec, &grid);
-  TS_BY_FORMAT(dt, fill_const_kernel, dim3(static_cast<uint32_t>(grid)), dim3(256), 0, s, p, n, value, head,
-               nvec)
+  const uint64_t es = dtype_size(dt);
+  const uint64_t a = reinterpret_cast<uintptr_t>(p) % 8;  // a multiple of es
+  uint64_t head = ((8 - a) % 8) / es;
+  if (head > n) head = n;
+  const uint64_t nwords = (n - head) * es / 8;
+  uint64_t g = (nwords + kFillChunkWords - 1) / kFillChunkWords;
+  g = g < 1 ? 1 : (g > (1u << 20) ? (1u << 20) : g);
+  TS_BY_FORMAT(dt, fill_const_kernel, dim3(static_cast<uint32_t>(g)), dim3(256), kFillLds, s, p, n, value, head,
+               nwords)
 }
 
 hipError_t launch_fill_uniform(int dt, void* p, uint64_t n, uint64_t seed, uint64_t stream_id,

@@ -87,6 +87,8 @@ constexpr uint32_t kNoallocParts = kSumMaxParts;
 // Devices whose fixed array's address is cached.
 constexpr int kMaxDevices = 64;
 
+// The constant fill's chunk: 256 lanes x two 8-byte words.
+constexpr uint64_t kFillChunkWords = 512;
 hipError_t launch_fill_const(int dt, void* p, uint64_t n, double value, hipStream_t s);
 // Element j: lo + w * u01(first_index + j + 1), narrowed to the storage type.
 hipError_t launch_fill_uniform(int dt, void* p, uint64_t n, uint64_t seed, uint64_t stream_id,

@@ -187,11 +187,13 @@ def test_fill_uniform_matches_generator(env, dtype, first):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
 def test_fill_small_and_offset(env, dtype):
-    """Constant fills store an element-wise head, 16-byte vectors and an
-    element-wise tail: every split of n and offset writes exactly [0, n)."""
+    """Constant fills store an element-wise head, 8-byte words in 4 KiB
+    chunks and an element-wise tail (uniform fills 16-byte vectors): every
+    split of n and offset, up to many chunks with a cut one, writes exactly
+    [0, n)."""
     ts, torch, tgt = env
     es = ts.ELEM_SIZE[dtype]
-    for n in (1, 2, 3, 5, 7, 8, 9, 15, 16, 17, 31, 33, 1000):
+    for n in (1, 2, 3, 5, 7, 8, 9, 15, 16, 17, 31, 33, 1000, 4099, 70001):
         for off in range(8):
             buf = torch.empty(n + off + 8, dtype=ts.TORCH_DTYPES[dtype], device="cuda")
             buf.view(torch.uint8).fill_(0x55)
