@@ -571,14 +571,16 @@ def transform_leg(ts, tgt, n, reps=20):
 
 
 def validation_leg(ts, tgt, nbytes=1 << 30, reps=20):
-    """The validation kernels on one array of `nbytes` per storage type: the
-    constant fill (write only), launch by launch, and the checksum call
-    (both passes and the copy of its 32-byte result to the host; the call
-    waits for it), each after untimed calls.  GB/s of the array's bytes."""
+    """The validation kernels on arrays of `nbytes` per storage type: the
+    constant fill (write only), launch by launch; the checksum call (both
+    passes and the copy of its 32-byte result to the host; the call waits
+    for it) and the mismatch-count call against a second array (two arrays
+    read), each after untimed calls.  GB/s of the bytes read or written."""
     out = {}
     for dt in ("f64", "f32", "bf16", "f16"):
         n = nbytes // ts.ELEM_SIZE[dt]
         X = ts.Array.alloc(tgt, dt, n)
+        Y = ts.Array.alloc(tgt, dt, n).fill(1.0)
 
         def fill():
             X.fill(1.0)
@@ -586,17 +588,24 @@ def validation_leg(ts, tgt, nbytes=1 << 30, reps=20):
         def check():
             ts.checksum(tgt, X, 1.0)
 
+        def count():
+            ts.mismatch_count(tgt, X, Y)
+
         settle(fill, SETTLE_LAUNCHES // 2)
         tf = timed_launches(ts, tgt, fill, reps)
         settle(check, 10)
         tc = timed_launches(ts, tgt, check, reps)
+        settle(count, 10)
+        tm = timed_launches(ts, tgt, count, reps)
         cs = ts.checksum(tgt, X, 1.0)
-        X.free()
+        same = ts.mismatch_count(tgt, X, Y) == 0
+        X.free(), Y.free()
         out[dt] = {"n": n,
                    "fill_const_avg_GBps": round(nbytes / (sum(tf) / len(tf)) / 1e6, 1),
                    "checksum_call_avg_us": round(1e3 * sum(tc) / len(tc), 1),
                    "checksum_call_avg_GBps": round(nbytes / (sum(tc) / len(tc)) / 1e6, 1),
-                   "valid": cs["mismatches"] == 0 and cs["sum"] == float(n)}
+                   "mismatch_call_avg_GBps": round(2 * nbytes / (sum(tm) / len(tm)) / 1e6, 1),
+                   "valid": cs["mismatches"] == 0 and cs["sum"] == float(n) and same}
     return out
 
 

@@ -273,10 +273,14 @@ __global__ __launch_bounds__(256) void reduce_pass2(const CsPart* parts, uint32_
   if (threadIdx.x == 0) *out = r;
 }
 
-// Count of elements whose bits differ between x and r (two NaNs agree):
-// workgroup g of P counts the contiguous range [g*n/P, (g+1)*n/P).  When x
-// and r share their address modulo 16 bytes the vectors of both are read 16
-// bytes at a time; otherwise every element is read alone.
+// Count of elements whose bits differ between x and r (two NaNs agree).
+// When x and r share their address modulo 16 bytes, their 16-byte vectors
+// form chunks of kSumChunk vectors as in checksum_pass1: workgroup g of P
+// counts chunks g, g + P, g + 2P, ..., issuing the next chunk's loads before
+// it compares the current one, and workgroup 0 also the element-wise head
+// and tail.  Otherwise workgroup g counts the contiguous range
+// [g*n/P, (g+1)*n/P) element by element.  A count is a sum of integers, so
+// the split does not change it.
 template <int DT>
 __global__ __launch_bounds__(256) void mismatch_pass1(const void* xv, const void* rv, uint64_t n,
                                                       CsPart* parts, uint32_t nparts) {
@@ -285,16 +289,16 @@ __global__ __launch_bounds__(256) void mismatch_pass1(const void* xv, const void
   constexpr uint32_t E = 16 / sizeof(T);
   const T* x = static_cast<const T*>(xv);
   const T* r = static_cast<const T*>(rv);
-  const uint64_t lo = static_cast<uint64_t>(blockIdx.x) * n / nparts;
-  const uint64_t hi = static_cast<uint64_t>(blockIdx.x + 1) * n / nparts;
+  const uint32_t t = threadIdx.x;
   CsPart acc{0.0, 0.0, 0.0, 0ull};
+  uint32_t mism = 0;  // a lane compares far fewer than 2^32 elements
   auto count = [&](T a, T b) {
     bool diff;
     if constexpr (sizeof(T) == 8) diff = __builtin_bit_cast(uint64_t, a) != __builtin_bit_cast(uint64_t, b);
     else if constexpr (sizeof(T) == 4) diff = __builtin_bit_cast(uint32_t, a) != __builtin_bit_cast(uint32_t, b);
     else diff = a != b;
     if (diff && __builtin_isnan(to_f64<DT>(a)) && __builtin_isnan(to_f64<DT>(b))) diff = false;
-    acc.mism += diff ? 1ull : 0ull;
+    mism += diff ? 1u : 0u;
   };
   auto fold = [&](R ra, R rb) {
     const Splat<T> va = __builtin_bit_cast(Splat<T>, ra), vb = __builtin_bit_cast(Splat<T>, rb);
@@ -302,29 +306,51 @@ __global__ __launch_bounds__(256) void mismatch_pass1(const void* xv, const void
     for (uint32_t e = 0; e < E; ++e) count(va.e[e], vb.e[e]);
   };
   if ((reinterpret_cast<uintptr_t>(x) - reinterpret_cast<uintptr_t>(r)) % 16 == 0) {
-    const VecRange<T> vr = vec_range(x, lo, hi);
-    if (threadIdx.x < vr.head) count(x[lo + threadIdx.x], r[lo + threadIdx.x]);
+    const VecRange<T> vr = vec_range(x, 0, n);
+    if (blockIdx.x == 0 && t < vr.head) count(x[t], r[t]);
     const R* xr = reinterpret_cast<const R*>(x + vr.v0);
     const R* rr = reinterpret_cast<const R*>(r + vr.v0);
-    uint64_t k = threadIdx.x;
-    for (; k + kReduceBlock < vr.nvec; k += 2 * kReduceBlock) {  // two pairs of vectors in flight
-      const R a0 = __builtin_nontemporal_load(xr + k), b0 = __builtin_nontemporal_load(rr + k);
-      const R a1 = __builtin_nontemporal_load(xr + k + kReduceBlock);
-      const R b1 = __builtin_nontemporal_load(rr + k + kReduceBlock);
-      fold(a0, b0), fold(a1, b1);
+    const uint64_t nvec = vr.nvec, step = static_cast<uint64_t>(nparts) * kSumChunk;
+    uint64_t base = static_cast<uint64_t>(blockIdx.x) * kSumChunk;
+    if (base + kSumChunk <= nvec) {
+      R ca[kSumUnroll], cb[kSumUnroll];
+#pragma unroll
+      for (uint32_t u = 0; u < kSumUnroll; ++u) {
+        ca[u] = __builtin_nontemporal_load(xr + base + u * kReduceBlock + t);
+        cb[u] = __builtin_nontemporal_load(rr + base + u * kReduceBlock + t);
+      }
+      for (base += step; base + kSumChunk <= nvec; base += step) {
+        R na[kSumUnroll], nb[kSumUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kSumUnroll; ++u) {
+          na[u] = __builtin_nontemporal_load(xr + base + u * kReduceBlock + t);
+          nb[u] = __builtin_nontemporal_load(rr + base + u * kReduceBlock + t);
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kSumUnroll; ++u) fold(ca[u], cb[u]);
+#pragma unroll
+        for (uint32_t u = 0; u < kSumUnroll; ++u) ca[u] = na[u], cb[u] = nb[u];
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kSumUnroll; ++u) fold(ca[u], cb[u]);
     }
-    for (; k < vr.nvec; k += kReduceBlock) fold(__builtin_nontemporal_load(xr + k), __builtin_nontemporal_load(rr + k));
-    if (threadIdx.x < hi - vr.t0) count(x[vr.t0 + threadIdx.x], r[vr.t0 + threadIdx.x]);
+    // The chunk cut short by the end of the vectors, if it is this workgroup's.
+    for (uint64_t k = base + t; k < nvec; k += kReduceBlock)
+      fold(__builtin_nontemporal_load(xr + k), __builtin_nontemporal_load(rr + k));
+    if (blockIdx.x == 0 && t < n - vr.t0) count(x[vr.t0 + t], r[vr.t0 + t]);
   } else {
-    uint64_t j = lo + threadIdx.x;
+    const uint64_t lo = static_cast<uint64_t>(blockIdx.x) * n / nparts;
+    const uint64_t hi = static_cast<uint64_t>(blockIdx.x + 1) * n / nparts;
+    uint64_t j = lo + t;
     for (; j + kReduceBlock < hi; j += 2 * kReduceBlock) {  // two pairs of loads in flight per lane
       const T a0 = x[j], b0 = r[j], a1 = x[j + kReduceBlock], b1 = r[j + kReduceBlock];
       count(a0, b0), count(a1, b1);
     }
     for (; j < hi; j += kReduceBlock) count(x[j], r[j]);
   }
+  acc.mism = mism;
   const CsPart res = block_reduce(acc);
-  if (threadIdx.x == 0) parts[blockIdx.x] = res;
+  if (t == 0) parts[blockIdx.x] = res;
 }
 
 // Whole 16-byte vectors [vs, ve) inside the tile [start, end) of an array
@@ -457,11 +483,6 @@ uint32_t fill_grid(uint64_t n) {
 
 }  // namespace
 
-uint32_t reduce_parts(uint64_t n) {
-  const uint64_t p = (n + 2047) / 2048;
-  return static_cast<uint32_t>(p < 1 ? 1 : (p > kReduceMaxParts ? kReduceMaxParts : p));
-}
-
 uint32_t checksum_parts(int dt, uint64_t n) {
   const uint64_t p = (n * dtype_size(dt) + kSumChunk * 16 - 1) / (kSumChunk * 16);
   return static_cast<uint32_t>(p < 1 ? 1 : (p > kSumMaxParts ? kSumMaxParts : p));
@@ -476,6 +497,10 @@ static uint32_t checksum_dynamic_lds(int dt) {
   constexpr uint32_t kTree = 4 * kReduceBlock * 8;
   return (dt == DT_F64 || dt == DT_F32 ? 64 * 1024 : 48 * 1024) - kTree;
 }
+
+// LDS each mismatch-count workgroup holds (its tree's 8 KiB plus an unused
+// dynamic part): 64 KiB, two workgroups per CU, as for the binary64 checksum.
+static uint32_t mismatch_dynamic_lds() { return 64 * 1024 - 4 * kReduceBlock * 8; }
 
 // The batched fill for storage format dt, constant (U false) or uniform.
 #define TS_BY_FORMAT_U(dt, U, ...)                                                             \
@@ -598,12 +623,13 @@ hipError_t noalloc_parts(int device, CsPart** out) {
 hipError_t launch_mismatch(int dt, const void* x, const void* ref, uint64_t n, void* scratch,
                            hipStream_t s) {
   CsPart* parts = static_cast<CsPart*>(scratch);
-  const uint32_t np = reduce_parts(n);
+  const uint32_t np = checksum_parts(dt, n);
+  const uint32_t lds = mismatch_dynamic_lds();
   switch (dt) {
-    case DT_F64: hipLaunchKernelGGL(mismatch_pass1<DT_F64>, dim3(np), dim3(kReduceBlock), 0, s, x, ref, n, parts, np); break;
-    case DT_F32: hipLaunchKernelGGL(mismatch_pass1<DT_F32>, dim3(np), dim3(kReduceBlock), 0, s, x, ref, n, parts, np); break;
-    case DT_BF16: hipLaunchKernelGGL(mismatch_pass1<DT_BF16>, dim3(np), dim3(kReduceBlock), 0, s, x, ref, n, parts, np); break;
-    case DT_F16: hipLaunchKernelGGL(mismatch_pass1<DT_F16>, dim3(np), dim3(kReduceBlock), 0, s, x, ref, n, parts, np); break;
+    case DT_F64: hipLaunchKernelGGL(mismatch_pass1<DT_F64>, dim3(np), dim3(kReduceBlock), lds, s, x, ref, n, parts, np); break;
+    case DT_F32: hipLaunchKernelGGL(mismatch_pass1<DT_F32>, dim3(np), dim3(kReduceBlock), lds, s, x, ref, n, parts, np); break;
+    case DT_BF16: hipLaunchKernelGGL(mismatch_pass1<DT_BF16>, dim3(np), dim3(kReduceBlock), lds, s, x, ref, n, parts, np); break;
+    case DT_F16: hipLaunchKernelGGL(mismatch_pass1<DT_F16>, dim3(np), dim3(kReduceBlock), lds, s, x, ref, n, parts, np); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();

@@ -70,10 +70,9 @@ struct CsPart {
 // bytes), never on tuning.
 constexpr uint32_t kReduceBlock = 256;
 constexpr uint32_t kReduceMaxParts = 8192;
-// Parts of the mismatch count: one per 2048 elements, at most kReduceMaxParts.
-uint32_t reduce_parts(uint64_t n);
-// The checksum's first pass reads chunks of kSumChunk 16-byte vectors (four
-// per lane); one part per chunk, at most kSumMaxParts.
+// The first passes of the checksum and the mismatch count read chunks of
+// kSumChunk 16-byte vectors (four per lane); one part per chunk, at most
+// kSumMaxParts.
 constexpr uint32_t kSumUnroll = 4;
 constexpr uint64_t kSumChunk = static_cast<uint64_t>(kReduceBlock) * kSumUnroll;
 constexpr uint32_t kSumMaxParts = 4096;

@@ -213,15 +213,15 @@ def _reduced_summary(raw, cmd):
 
 
 def _validation_summary(raw, cmd):
-    """Per storage type, the checksum's two passes and the constant fill over
-    the validation leg's 1 GiB arrays (the largest grid of each kernel and
+    """Per storage type, the checksum's two passes, the constant fill and the
+    mismatch count over the validation leg's 1 GiB arrays (the largest grid of each kernel and
     type), average durations from the per-dispatch trace."""
     nbytes = 1 << 30
     rows = {}
     for f in glob.glob(os.path.join(raw, "trace_validation", "**", "*kernel_trace.csv"), recursive=True):
         for r in csv.DictReader(open(f)):
             name = r["Kernel_Name"]
-            m = re.search(r"(checksum_pass1|fill_const_kernel)<(\d+)", name)
+            m = re.search(r"(checksum_pass1|fill_const_kernel|mismatch_pass1)<(\d+)", name)
             if m:
                 key = (int(m.group(2)), m.group(1))
             elif "reduce_pass2" in name:
@@ -235,10 +235,11 @@ def _validation_summary(raw, cmd):
     L = ["# Kernel trace: validation kernels over 1 GiB per storage type (bench validation leg)", "",
          "Made by `python paper_2206_06302_amd/profiling.py run` (then `summarize`); the run:", "",
          "```", "export TMPDIR=/tmp; cd /tmp", cmd, "```", "",
-         "The checksum's first pass (grid-strided 16 KiB chunks, one workgroup part each) and the constant",
-         "fill over one array of 2^30 bytes per storage type: the launches of the largest grid, their",
-         "average duration from the trace, and bytes / that duration.  The bench's own figure for a whole",
-         "checksum call (both passes, the result's copy to the host and the wait for it) is beside it.",
+         "The checksum's first pass (grid-strided 16 KiB chunks, one workgroup part each), the constant",
+         "fill and the mismatch count's first pass (two arrays read) over arrays of 2^30 bytes per storage",
+         "type: the launches of the largest grid, their average duration from the trace, and bytes / that",
+         "duration.  The bench's own figure for a whole call (both passes, the result's copy to the host",
+         "and the wait for it; for the fill, the launch) is beside it.",
          "The binary64 rows also hold the headline's own validation calls on its 2^27-element arrays,",
          "which are the same size.  The first pass's workgroups of 256 lanes reserve 64 KiB of LDS for",
          "binary64 and binary32 and 48 KiB for the 16-bit types, which leaves room for two or three on a",
@@ -246,16 +247,17 @@ def _validation_summary(raw, cmd):
          "| storage | kernel | grid (workgroups) | dispatches | avg µs | GB/s (avg) | bench GB/s |",
          "|---|---|---|---|---|---|---|"]
     for dt in range(4):
-        for kern, bench_key, wg in (("checksum_pass1", "checksum_call_avg_GBps", 256),
-                                    ("fill_const_kernel", "fill_const_avg_GBps", 256)):
+        for kern, bench_key, arrays in (("checksum_pass1", "checksum_call_avg_GBps", 1),
+                                        ("fill_const_kernel", "fill_const_avg_GBps", 1),
+                                        ("mismatch_pass1", "mismatch_call_avg_GBps", 2)):
             if (dt, kern) not in rows:
                 continue
             grid = max(rows[(dt, kern)])
             launches = rows[(dt, kern)][grid]
             avg = sum(launches) / len(launches)
             ev = bj.get(DT_NAMES[dt], {}).get(bench_key, "")
-            L.append(f"| {DT_NAMES[dt]} | `{kern}` | {grid // wg} | {len(launches)} | "
-                     f"{avg / 1e3:.1f} | {nbytes / avg:.1f} | {ev} |")
+            L.append(f"| {DT_NAMES[dt]} | `{kern}` | {grid // 256} | {len(launches)} | "
+                     f"{avg / 1e3:.1f} | {arrays * nbytes / avg:.1f} | {ev} |")
     if (None, "reduce_pass2") in rows:
         p2 = [d for v in rows[(None, "reduce_pass2")].values() for d in v]
         L += ["", f"The second pass (one workgroup folding the parts in a fixed order) averages "
