@@ -250,11 +250,14 @@ def test_checksum_against_oracle(env, dtype):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
 def test_checksum_many_chunks_per_workgroup(env, dtype):
-    """Above 4096 chunks of 16 KiB (64 MiB) every first-pass workgroup folds
-    several chunks, the next one loaded while the current one is folded; a
-    size two and a half times that, not a whole number of chunks, and an
-    element offset that gives a head and a tail, give the oracle's counts
-    and maximum exactly and its sums within the summation bound."""
+    """Above 4096 chunks of 16 KiB (64 MiB) every first-pass workgroup of the
+    checksum and of the mismatch count takes several chunks, the next one
+    loaded while the current one is folded; a size two and a half times
+    that, not a whole number of chunks, and an element offset that gives a
+    head and a tail, give the oracle's counts and maximum exactly and its
+    sums within the summation bound.  The mismatch count compares against a
+    copy with bits flipped at the head, chunk edges and the tail, at the
+    same offset (chunked path) and at another (element-wise path)."""
     ts, torch, tgt = env
     E = ELEMS_PER_16B[dtype]
     es = 16 // E
@@ -267,6 +270,12 @@ def test_checksum_many_chunks_per_workgroup(env, dtype):
     bound_sum = 2 * n * 2.0 ** -53 * float(np.abs(w).sum())
     bound_dev = 2 * n * 2.0 ** -53 * float(np.abs(w - expected).sum())
     del w
+    r = x.copy()
+    chunk = 16384 // es
+    plant = sorted({0, 1, chunk - 1, chunk, 4096 * chunk - 1, 4096 * chunk, 4097 * chunk + 5, n - 2, n - 1})
+    r.view(UINT_OF[dtype])[plant] ^= 1
+    want_mm = oracle.mismatch_count(odt, x, r)
+    assert want_mm == len(plant)
     for off in (0, E - 1):
         say(f"[checksum many chunks {dtype} n={n} offset={off}]")
         X = device_array(ts, torch, tgt, x, dtype, off)
@@ -275,6 +284,11 @@ def test_checksum_many_chunks_per_workgroup(env, dtype):
         assert cs["max_abs_dev"] == ref.max_abs_dev
         assert abs(cs["sum"] - ref.sum) <= bound_sum
         assert abs(cs["abs_dev_sum"] - ref.abs_dev_sum) <= bound_dev
+        for roff in (off, (off + 1) % E):
+            say(f"[mismatch many chunks {dtype} n={n} offset={off} ref offset={roff}]")
+            R = device_array(ts, torch, tgt, r, dtype, roff)
+            assert ts.mismatch_count(tgt, X, R) == want_mm, (off, roff)
+            del R
         del X
         torch.cuda.empty_cache()
 
@@ -357,8 +371,8 @@ ELEMS_PER_16B = {"f64": 2, "f32": 4, "bf16": 8, "f16": 8}
 def test_checksum_and_mismatch_layouts(env, dtype):
     """The reductions read a head up to a 16-byte boundary, 16-byte vectors
     and a tail: every element offset within 16 bytes, sizes below one
-    vector, around one part of the mismatch count (2048 elements) and across
-    several of the checksum's 16 KiB chunks give the oracle's counts and
+    vector, around one 16 KiB chunk for binary64 (2048 elements) and across
+    several chunks give the oracle's counts and
     maximum exactly and its sums within the summation bound; the mismatch
     count also takes operands whose offsets differ modulo 16 bytes
     (element-wise path)."""
