@@ -181,16 +181,21 @@ int check_batch_exec(ts_target_s* t, ts_batch_s* b) {
   return use_device(t->device);
 }
 
-// Fills and mismatch counts over a batch give four consecutive tiles to each
-// workgroup: with one per tile, the workgroups of 512-element binary64 tiles
-// are dispatched more slowly than they stream (mismatch count 4.7 against
-// 5.5 TB/s; uniform fill 3.9 against 4.1).
-constexpr uint32_t kAuxTilesPerWg = 4;
-uint32_t aux_tiles_per_wg() { return kAuxTilesPerWg; }
+// Fills and mismatch counts over a batch give each workgroup about 16 KiB of
+// tiles: one tile of 16 KiB or more, else up to four consecutive ones.  With
+// one per tile, the workgroups of 512-element (4 KiB) binary64 tiles are
+// dispatched more slowly than they stream (mismatch count 4.7 against 5.5
+// TB/s with four; uniform fill 3.9 against 4.1); with 2048-element tiles one
+// per workgroup is the faster (constant fill 5.59-5.65 against 5.40-5.42
+// TB/s with four, mismatch count 7.26-7.27 against 7.19).
+uint32_t aux_tiles_per_wg(const ts_batch_s* b) {
+  const uint64_t tile_bytes = static_cast<uint64_t>(b->tile_elems) * dtype_size(b->dtype);
+  const uint64_t k = tile_bytes ? 16384 / tile_bytes : kAuxMaxTilesPerWg;
+  return static_cast<uint32_t>(k < 1 ? 1 : (k > kAuxMaxTilesPerWg ? kAuxMaxTilesPerWg : k));
+}
 
-uint32_t aux_grid(uint64_t ntiles) {
-  const uint64_t k = aux_tiles_per_wg();
-  const uint64_t g = cap_grid((ntiles + k - 1) / k, kAuxBlock);
+uint32_t aux_grid(uint64_t ntiles, uint32_t per_wg) {
+  const uint64_t g = cap_grid((ntiles + per_wg - 1) / per_wg, kAuxBlock);
   return static_cast<uint32_t>(g < 1 ? 1 : g);
 }
 
@@ -344,8 +349,9 @@ int ts_batch_fill(ts_target exec, ts_batch b, int which, double value) {
   if (st != TS_OK) return st;
   if (which < 0 || which > 2) return fail(TS_E_INVALID, "which must be 0 (a), 1 (b) or 2 (c)");
   if (b->tiles.empty()) return TS_OK;
-  const hipError_t e = launch_batch_fill(b->dtype, b->d_tiles, b->tiles.size(), aux_tiles_per_wg(), which, 0,
-                                         value, 0, aux_grid(b->tiles.size()), exec->stream);
+  const uint32_t per_wg = aux_tiles_per_wg(b);
+  const hipError_t e = launch_batch_fill(b->dtype, b->d_tiles, b->tiles.size(), per_wg, which, 0, value, 0,
+                                         aux_grid(b->tiles.size(), per_wg), exec->stream);
   if (e != hipSuccess) return hip_fail(e, "batched fill launch");
   return TS_OK;
   TS_GUARD_END
@@ -359,8 +365,9 @@ int ts_batch_fill_uniform(ts_target exec, ts_batch b, int which, uint64_t seed) 
   if (b->host.size() > (((1ull << 16) - 16) / 3))
     return fail(TS_E_UNSUPPORTED, "too many instances for 16-bit stream ids");
   if (b->tiles.empty()) return TS_OK;
-  const hipError_t e = launch_batch_fill(b->dtype, b->d_tiles, b->tiles.size(), aux_tiles_per_wg(), which, 1,
-                                         0.0, seed, aux_grid(b->tiles.size()), exec->stream);
+  const uint32_t per_wg = aux_tiles_per_wg(b);
+  const hipError_t e = launch_batch_fill(b->dtype, b->d_tiles, b->tiles.size(), per_wg, which, 1, 0.0, seed,
+                                         aux_grid(b->tiles.size(), per_wg), exec->stream);
   if (e != hipSuccess) return hip_fail(e, "batched uniform fill launch");
   return TS_OK;
   TS_GUARD_END
@@ -382,8 +389,9 @@ int ts_batch_mismatch_count(ts_target exec, ts_batch b, int which, const double*
   hipError_t e = launch_zero_u64(b->d_counts, n, exec->stream);
   if (e != hipSuccess) return hip_fail(e, "zero kernel launch");
   if (!b->tiles.empty()) {
-    e = launch_batch_mismatch(b->dtype, b->d_tiles, b->tiles.size(), aux_tiles_per_wg(), which, b->d_expected,
-                              b->d_counts, aux_grid(b->tiles.size()), exec->stream);
+    const uint32_t per_wg = aux_tiles_per_wg(b);
+    e = launch_batch_mismatch(b->dtype, b->d_tiles, b->tiles.size(), per_wg, which, b->d_expected, b->d_counts,
+                              aux_grid(b->tiles.size(), per_wg), exec->stream);
     if (e != hipSuccess) return hip_fail(e, "batched mismatch launch");
   }
   TS_HIP(hipMemcpyAsync(b->h_counts, b->d_counts, n * sizeof(uint64_t), hipMemcpyDeviceToHost, exec->stream));

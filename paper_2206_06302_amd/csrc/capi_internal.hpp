@@ -176,6 +176,8 @@ ts_kernel_cfg batch_cfg(const ts_batch_s* b, int op);
 int build_op_plans(ts_batch_s* b);
 int launch_batch(ts_target_s* t, ts_batch_s* b, int op, const ts_kernel_cfg& cfg);
 int check_batch_exec(ts_target_s* t, ts_batch_s* b);
-uint32_t aux_grid(uint64_t ntiles);
+// Tiles per workgroup of a batch's fills and mismatch counts, and their grid.
+uint32_t aux_tiles_per_wg(const ts_batch_s* b);
+uint32_t aux_grid(uint64_t ntiles, uint32_t per_wg);
 
 }  // namespace tsapi

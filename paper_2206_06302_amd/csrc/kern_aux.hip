@@ -369,12 +369,9 @@ __device__ __forceinline__ uint64_t head_of(const T* p) {
 }
 
 // Tiles [c, c + per_wg) of the table go to workgroup c / per_wg (striding
-// by the grid over any beyond it): fewer, longer workgroups than one per
-// tile, which the hardware dispatches at a limited rate.  A workgroup reads
-// the records of its group together (scalar loads issued back to back), so
-// it waits on the table once per group, not once per tile.
-constexpr uint32_t kAuxMaxTilesPerWg = 4;
-
+// by the grid over any beyond it), per_wg at most kAuxMaxTilesPerWg.  A
+// workgroup reads the records of its group together (scalar loads issued
+// back to back), so it waits on the table once per group, not once per tile.
 #define TS_FOR_TILE_GROUPS(c0, cnt)                                                               \
   for (uint64_t c0 = static_cast<uint64_t>(blockIdx.x) * per_wg, cnt = 0; c0 < ntiles;             \
        c0 += static_cast<uint64_t>(gridDim.x) * per_wg)                                           \

@@ -111,6 +111,9 @@ hipError_t launch_mismatch(int dt, const void* x, const void* ref, uint64_t n, v
 // workgroup of `grid` (which strides over any tiles beyond), kAuxBlock lanes
 // per workgroup.
 constexpr uint32_t kAuxBlock = 256;
+// The most tiles one workgroup of those kernels takes: the records of a group
+// are read together, so a workgroup waits on the table once per group.
+constexpr uint32_t kAuxMaxTilesPerWg = 4;
 hipError_t launch_batch_fill(int dt, const BatchTile* tiles, uint64_t ntiles, uint32_t per_wg, int which,
                              int uniform, double value, uint64_t seed, uint32_t grid, hipStream_t s);
 // counts: device array of one unsigned long long per instance, zeroed by the
