@@ -572,10 +572,11 @@ def transform_leg(ts, tgt, n, reps=20):
 
 def validation_leg(ts, tgt, nbytes=1 << 30, reps=20):
     """The validation kernels on arrays of `nbytes` per storage type: the
-    constant fill (write only), launch by launch; the checksum call (both
-    passes and the copy of its 32-byte result to the host; the call waits
-    for it) and the mismatch-count call against a second array (two arrays
-    read), each after untimed calls.  GB/s of the bytes read or written."""
+    constant and the uniform fill (write only), launch by launch; the
+    checksum call (both passes and the copy of its 32-byte result to the
+    host; the call waits for it) and the mismatch-count call against a
+    second array (two arrays read), each after untimed calls.  GB/s of the
+    bytes read or written."""
     out = {}
     for dt in ("f64", "f32", "bf16", "f16"):
         n = nbytes // ts.ELEM_SIZE[dt]
@@ -585,6 +586,9 @@ def validation_leg(ts, tgt, nbytes=1 << 30, reps=20):
         def fill():
             X.fill(1.0)
 
+        def fill_uniform():
+            X.fill_uniform(7, 1)
+
         def check():
             ts.checksum(tgt, X, 1.0)
 
@@ -592,6 +596,8 @@ def validation_leg(ts, tgt, nbytes=1 << 30, reps=20):
             ts.mismatch_count(tgt, X, Y)
 
         settle(fill, SETTLE_LAUNCHES // 2)
+        settle(fill_uniform, SETTLE_LAUNCHES // 2)
+        tu = timed_launches(ts, tgt, fill_uniform, reps)
         tf = timed_launches(ts, tgt, fill, reps)
         settle(check, 10)
         tc = timed_launches(ts, tgt, check, reps)
@@ -602,6 +608,7 @@ def validation_leg(ts, tgt, nbytes=1 << 30, reps=20):
         X.free(), Y.free()
         out[dt] = {"n": n,
                    "fill_const_avg_GBps": round(nbytes / (sum(tf) / len(tf)) / 1e6, 1),
+                   "fill_uniform_avg_GBps": round(nbytes / (sum(tu) / len(tu)) / 1e6, 1),
                    "checksum_call_avg_us": round(1e3 * sum(tc) / len(tc), 1),
                    "checksum_call_avg_GBps": round(nbytes / (sum(tc) / len(tc)) / 1e6, 1),
                    "mismatch_call_avg_GBps": round(2 * nbytes / (sum(tm) / len(tm)) / 1e6, 1),

@@ -213,15 +213,15 @@ def _reduced_summary(raw, cmd):
 
 
 def _validation_summary(raw, cmd):
-    """Per storage type, the checksum's two passes, the constant fill and the
-    mismatch count over the validation leg's 1 GiB arrays (the largest grid of each kernel and
+    """Per storage type, the checksum's two passes, the constant and uniform
+    fills and the mismatch count over the validation leg's 1 GiB arrays (the largest grid of each kernel and
     type), average durations from the per-dispatch trace."""
     nbytes = 1 << 30
     rows = {}
     for f in glob.glob(os.path.join(raw, "trace_validation", "**", "*kernel_trace.csv"), recursive=True):
         for r in csv.DictReader(open(f)):
             name = r["Kernel_Name"]
-            m = re.search(r"(checksum_pass1|fill_const_kernel|mismatch_pass1)<(\d+)", name)
+            m = re.search(r"(checksum_pass1|fill_const_kernel|fill_uniform_kernel|mismatch_pass1)<(\d+)", name)
             if m:
                 key = (int(m.group(2)), m.group(1))
             elif "reduce_pass2" in name:
@@ -236,7 +236,7 @@ def _validation_summary(raw, cmd):
          "Made by `python paper_2206_06302_amd/profiling.py run` (then `summarize`); the run:", "",
          "```", "export TMPDIR=/tmp; cd /tmp", cmd, "```", "",
          "The checksum's first pass (grid-strided 16 KiB chunks, one workgroup part each), the constant",
-         "fill and the mismatch count's first pass (two arrays read) over arrays of 2^30 bytes per storage",
+         "and uniform fills and the mismatch count's first pass (two arrays read) over arrays of 2^30 bytes per storage",
          "type: the launches of the largest grid, their average duration from the trace, and bytes / that",
          "duration.  The bench's own figure for a whole call (both passes, the result's copy to the host",
          "and the wait for it; for the fill, the launch) is beside it.",
@@ -249,6 +249,7 @@ def _validation_summary(raw, cmd):
     for dt in range(4):
         for kern, bench_key, arrays in (("checksum_pass1", "checksum_call_avg_GBps", 1),
                                         ("fill_const_kernel", "fill_const_avg_GBps", 1),
+                                        ("fill_uniform_kernel", "fill_uniform_avg_GBps", 1),
                                         ("mismatch_pass1", "mismatch_call_avg_GBps", 2)):
             if (dt, kern) not in rows:
                 continue

@@ -228,12 +228,14 @@ def _synthetic_raw(raw):
     trace = ["Kernel_Name", "Grid_Size_X", "Start_Timestamp", "End_Timestamp", "LDS_Block_Size"]
     cs = "void ts::(anonymous namespace)::checksum_pass1<{dt}, 0>(void const*, unsigned long, double, ts::CsPart*, unsigned int)"
     fill = "void ts::(anonymous namespace)::fill_const_kernel<{dt}>(void*, unsigned long, double, unsigned long, unsigned long)"
+    uni = "void ts::(anonymous namespace)::fill_uniform_kernel<{dt}>(void*, unsigned long, unsigned long, unsigned long, double, double, unsigned long, unsigned long)"
     mm = "void ts::(anonymous namespace)::mismatch_pass1<{dt}>(void const*, void const*, unsigned long, ts::CsPart*, unsigned int)"
     rows = []
     for dt in range(4):
         # 2^30 bytes in 100 µs (checksum) and 200 µs (fill); small launches that must be left out
         rows += [[cs.format(dt=dt), 4096 * 256, 0, 100000, 65536]] * 3 + [[cs.format(dt=dt), 256, 0, 1, 65536]]
         rows += [[fill.format(dt=dt), 262144 * 256, 0, 200000, 0]] * 2 + [[fill.format(dt=dt), 256, 0, 1, 0]]
+        rows += [[uni.format(dt=dt), 262144 * 256, 0, 250000, 0]] * 2
         # two arrays of 2^30 bytes read in 400 µs
         rows += [[mm.format(dt=dt), 8192 * 256, 0, 400000, 0]] + [[mm.format(dt=dt), 256, 0, 1, 0]]
     rows += [["void ts::(anonymous namespace)::reduce_pass2(ts::CsPart const*, unsigned int, ts::CsPart*)", 256, 0,
@@ -292,16 +294,18 @@ def test_profile_summaries_from_known_counts(tmp_path, monkeypatch):
 
     val = read("checksum_fill_1gib_kernel_trace.md")
     rows = [ln.split("|") for ln in val.splitlines() if ln.startswith("| ") and "`" in ln]
-    assert len(rows) == 12
+    assert len(rows) == 16
     for r in rows:  # the small-grid launches are left out
         if "checksum_pass1" in r[2]:
             assert [c.strip() for c in r[3:7]] == ["4096", "3", "100.0", "10737.4"], r
         elif "fill_const" in r[2]:
             assert [c.strip() for c in r[3:7]] == ["262144", "2", "200.0", "5368.7"], r
+        elif "fill_uniform" in r[2]:
+            assert [c.strip() for c in r[3:7]] == ["262144", "2", "250.0", "4295.0"], r
         else:
             assert [c.strip() for c in r[3:7]] == ["8192", "1", "400.0", "5368.7"], r
     bf16 = [r for r in rows if r[1].strip() == "bf16"]
-    assert [r[7].strip() for r in bf16] == ["2.5", "3.5", "4.5"]
+    assert [r[7].strip() for r in bf16] == ["2.5", "3.5", "", "4.5"]
     assert "averages 5.0 µs over 4 dispatches" in val
     assert "--legs validation" in val
 

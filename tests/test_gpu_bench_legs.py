@@ -63,4 +63,4 @@ def test_validation_leg(env):
         assert r["valid"], dt
         assert r["n"] == ((8 << 20) + 48) // ts.ELEM_SIZE[dt]
         assert r["fill_const_avg_GBps"] > 0 and r["checksum_call_avg_GBps"] > 0 and r["checksum_call_avg_us"] > 0
-        assert r["mismatch_call_avg_GBps"] > 0
+        assert r["mismatch_call_avg_GBps"] > 0 and r["fill_uniform_avg_GBps"] > 0
